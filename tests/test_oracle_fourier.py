@@ -1,0 +1,66 @@
+"""Fourier-analysis pins (paper Sec. 4.2) and the link between the symbol and
+the oracle's matrix-free stepper."""
+import numpy as np
+import pytest
+
+from paper_2404_03399_amd import workloads as W
+from oracle import fourier, stepper
+
+
+def test_dg1_rk2_stability_limit_one_third():
+    # Sec. 4.2.1: DG(1)-RK2 with upwind flux is stable only for sigma <= 0.333
+    s = fourier.sigma_star(1, "heun", tol=1e-5, n_theta=361)
+    assert abs(s - 1.0 / 3.0) < 2e-5
+
+
+@pytest.mark.parametrize("p,rk,known", [(2, "ssprk3", 0.209), (3, "rk4", 0.145)])
+def test_published_cfl_limits(p, rk, known):
+    # Cockburn & Shu's RKDG CFL table (upwind, Lagrange/Legendre degree p)
+    s = fourier.sigma_star(p, rk, tol=1e-4, n_theta=361)
+    assert abs(s - known) < 1.5e-3
+
+
+def test_rk_polynomials_are_truncated_exponentials():
+    th = 0.7
+    for p, rk, nst in [(1, "heun", 2), (2, "ssprk3", 3), (3, "rk4", 4)]:
+        z = fourier.stage_matrix(p, "upwind", 0.05, th)
+        g = np.eye(p + 1, dtype=complex)
+        term = np.eye(p + 1, dtype=complex)
+        for j in range(1, nst + 1):
+            term = term @ z / j
+            g = g + term
+        np.testing.assert_allclose(fourier.amplification(p, rk, "upwind", 0.05, th), g, atol=1e-14)
+
+
+def test_physical_mode_follows_exact_dispersion():
+    for sig in (0.333, 0.1):
+        kk, om = fourier.dispersion(1, "heun", "upwind", sig, 0.2)
+        best = om[np.argmin(np.abs(om - kk))]
+        assert abs(best.real - kk) < 1e-3 and abs(best.imag) < 1e-3
+
+
+@pytest.mark.parametrize("p,rk,flux", [(1, "heun", "upwind"), (2, "rk4", "central"), (3, "ssprk3", "upwind")])
+def test_stepper_matrix_spectrum_equals_symbol(p, rk, flux):
+    ne, sig = 8, 0.1
+    dx = W.TWO_PI / ne
+    w = W.Workload(name="f", scheme="dg", rk=rk, flux=flux, degree=p, n_elem=ne, pe_size=ne,
+                   dt=sig * dx)
+    g = fourier.global_step_matrix(stepper.Stepper(w))
+    ev = np.sort_complex(np.linalg.eigvals(g))
+    sym = np.concatenate([np.linalg.eigvals(fourier.amplification(p, rk, flux, sig, 2 * np.pi * m / ne))
+                          for m in range(ne)])
+    sym = np.sort_complex(sym)
+    # match each eigenvalue to its nearest symbol eigenvalue
+    d = np.abs(ev[:, None] - sym[None, :]).min(axis=1)
+    assert d.max() < 1e-10
+
+
+def test_paper_async_companion_verdict():
+    # Sec. 4.2.2: ADG(1)-RK2-L2 is unstable at sigma = 0.333; decreasing sigma
+    # decreases the growth (the paper calls 0.1 and 0.05 stable; the printed
+    # matrices give growth below 1.5e-4 there).
+    th = np.linspace(-np.pi, np.pi, 361)
+    rho = {s: max(np.max(np.abs(np.linalg.eigvals(fourier.paper_async_companion(s, t))))
+                  for t in th) for s in (0.333, 0.1, 0.05)}
+    assert rho[0.333] > 1.01
+    assert rho[0.1] < 1.0 + 1.5e-4 and rho[0.05] < rho[0.1]

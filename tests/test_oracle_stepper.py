@@ -1,0 +1,193 @@
+"""Pins for the oracle stepper (paper Secs. 2-6).
+
+Each test checks the oracle against something it does not compute itself:
+the paper's K-matrix equations, exact solutions, invariants (conservation),
+the printed convergence orders, and special cases that must collapse to
+plain DG."""
+import math
+from dataclasses import replace
+
+import numpy as np
+import pytest
+
+from paper_2404_03399_amd import workloads as W
+from oracle import basis, exact, stats, stepper
+
+
+def _wl(**kw):
+    base = dict(name="t", degree=2, n_elem=32, pe_size=8, probs=("0.3", "0.4", "0.3"), seed=3,
+                dt=0.01, n_steps=10, ic=W.PAPER_MULTISINE)
+    base.update(kw)
+    return W.Workload(**base)
+
+
+def _kmatrix_operator(u, p, a, dx, bp, bm, old=None, faces=()):
+    """Paper's matrix form, assembled element by element:
+    M du^e/dt = (2a/dx) (K^- u^{e-1} + (K_l + S + K_r) u^e + K^+ u^{e+1}),
+    and, at a PE face x_e with common delayed level (Sec. 4.1),
+    e-1: K^- u^{e-2} + (K_l + S) u^{e-1} + K_r u_old^{e-1} + K^+ u_old^e
+    e  : K^- u_old^{e-1} + K_l u_old^e + (S + K_r) u^e + K^+ u^{e+1}."""
+    m = basis.mass_matrix(p)
+    s = basis.stiffness_matrix(p)
+    km, kp, kl, kr = basis.flux_matrices(p, bp, bm)
+    ne = u.shape[0]
+    out = np.zeros_like(u)
+    faces = set(faces)
+    for e in range(ne):
+        em, ep = (e - 1) % ne, (e + 1) % ne
+        left_pe = e in faces
+        right_pe = ep in faces
+        r = s @ u[e]
+        if left_pe:
+            r = r + km @ old[em] + kl @ old[e]
+        else:
+            r = r + km @ u[em] + kl @ u[e]
+        if right_pe:
+            r = r + kr @ old[e] + kp @ old[ep]
+        else:
+            r = r + kr @ u[e] + kp @ u[ep]
+        out[e] = (2.0 * a / dx) * np.linalg.solve(m, r)
+    return out
+
+
+@pytest.mark.parametrize("flux,bp,bm", [("upwind", 1.0, 0.0), ("central", 0.5, 0.5)])
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_sync_operator_equals_paper_matrix_form(flux, bp, bm, p):
+    w = _wl(scheme="dg", flux=flux, degree=p, speed=1.7)
+    st = stepper.Stepper(w)
+    u = np.random.default_rng(p).standard_normal((w.n_elem, p + 1))
+    ref = _kmatrix_operator(u, p, 1.7, st.dx, bp, bm)
+    np.testing.assert_allclose(st.operator(u, 0, 0), ref, rtol=1e-12, atol=1e-10)
+
+
+@pytest.mark.parametrize("flux,bp,bm", [("upwind", 1.0, 0.0), ("central", 0.5, 0.5)])
+def test_conservative_adg_equals_paper_equation(flux, bp, bm):
+    """Sec. 4.1 conservative update at PE faces with a delayed common level."""
+    p = 2
+    w = _wl(scheme="adg", flux=flux, degree=p, probs=("0", "1"))
+    st = stepper.Stepper(w)
+    st.forced = lambda n, s: np.full(w.n_pe, 0 if n == 4 else 1)
+    rng = np.random.default_rng(0)
+    u_old = rng.standard_normal((w.n_elem, p + 1))
+    u_new = rng.standard_normal((w.n_elem, p + 1))
+    st.operator(u_old, 4, 1)                 # level 4, stage 1 is stored as history
+    got = st.operator(u_new, 5, 1)           # every boundary delayed by k = 1
+    faces = [b * w.pe_size for b in range(w.n_pe)]
+    ref = _kmatrix_operator(u_new, p, 1.0, st.dx, bp, bm, old=u_old, faces=faces)
+    np.testing.assert_allclose(got, ref, rtol=1e-12, atol=1e-10)
+
+
+def _run_error(w):
+    st = stepper.Stepper(w)
+    u0 = stepper.initial_state(w)
+    i0 = st.integral(u0)
+    u = st.run(u0, w.n_steps)
+    x = basis.element_nodes(w.x_left, w.length, w.n_elem, w.degree)
+    ue = exact.solution(w, x, w.dt * w.n_steps)
+    return stats.mean_abs(u, ue), stats.max_abs(u, ue), abs(st.integral(u) - i0)
+
+
+CASES = [(1, "heun", 0.1), (2, "ssprk3", 0.02), (3, "rk4", 0.01)]
+
+
+def _series(p, rk, sig, scheme, sizes, probs=("0.3", "0.4", "0.3"), seed=1, t_final=0.5):
+    out = []
+    for ne in sizes:
+        dt, n = W.time_step(W.TWO_PI, ne, sig, 1.0, t_final)
+        w = _wl(scheme=scheme, rk=rk, degree=p, n_elem=ne, pe_size=ne // 8, probs=probs,
+                seed=seed, per_stage=False, dt=dt, n_steps=n)
+        out.append(_run_error(w))
+    return np.array(out)
+
+
+@pytest.mark.parametrize("p,rk,sig", CASES)
+def test_sync_dg_order_and_conservation(p, rk, sig):
+    e = _series(p, rk, sig, "dg", [32, 64, 128])
+    slopes = np.log2(e[:-1, 0] / e[1:, 0])
+    assert np.all(slopes > p + 1 - 0.15), slopes      # paper Fig. 7: slopes -2, -3, -4
+    assert e[:, 2].max() < 1e-12
+
+
+@pytest.mark.parametrize("p,rk,sig", CASES)
+def test_adg_loses_order_at_recovers_it(p, rk, sig):
+    sizes = [64, 128, 256] if p < 3 else [64, 128]
+    dg = _series(p, rk, sig, "dg", sizes)
+    adg = _series(p, rk, sig, "adg", sizes)
+    at = _series(p, rk, sig, "adg_at", sizes)
+    # conservative schemes conserve the integral to round-off (Sec. 4.1)
+    assert adg[:, 2].max() < 1e-12 and at[:, 2].max() < 1e-12
+    # standard fluxes with delays: at most first order in the max norm and far
+    # larger errors than synchronous DG (Sec. 4.3, Fig. 7)
+    linf_adg = np.log2(adg[:-1, 1] / adg[1:, 1])
+    assert linf_adg.mean() < 1.6, linf_adg
+    assert np.all(adg[:, 1] > 2 * dg[:, 1]) and np.all(adg[:, 0] > 1.2 * dg[:, 0])
+    if p > 1:
+        assert adg[-1, 0] > 10 * dg[-1, 0]
+    # AT fluxes restore order p+1 and DG-level errors (Sec. 5, Fig. 8)
+    slopes_at = np.log2(at[:-1, 0] / at[1:, 0])
+    assert np.all(slopes_at > p + 1 - 0.2), slopes_at
+    assert np.all(at[:, 0] < 1.5 * dg[:, 0])
+
+
+def test_naive_adg_breaks_conservation():
+    """Sec. 4.1: independent delays on the two sides make the flux two-valued."""
+    e = _series(1, "heun", 0.1, "naive", [64])
+    assert e[0, 2] > 1e-6
+    sizes = [64, 128, 256]
+    naive = _series(1, "heun", 0.1, "naive", sizes)
+    slopes = np.log2(naive[:-1, 0] / naive[1:, 0])
+    assert np.all(slopes < 1.3), slopes                  # first order (Fig. 7)
+
+
+@pytest.mark.parametrize("rk", ["heun", "ssprk3", "rk4"])
+def test_special_cases_reduce_to_dg(rk):
+    base = _wl(rk=rk, degree=2, n_elem=48, pe_size=12, dt=0.002, n_steps=25, seed=9)
+    u0 = stepper.initial_state(base)
+    dg = stepper.Stepper(replace(base, scheme="dg")).run(u0, 25)
+    # one delay level only (L = 1): every delay is zero
+    for sch in ("adg", "adg_at"):
+        got = stepper.Stepper(replace(base, scheme=sch, probs=("1",))).run(u0, 25)
+        assert np.array_equal(got, dg)
+        # zero-probability delays
+        got = stepper.Stepper(replace(base, scheme=sch, probs=("1", "0", "0"))).run(u0, 25)
+        assert np.array_equal(got, dg)
+        # a single PE has no PE boundaries
+        got = stepper.Stepper(replace(base, scheme=sch, pe_size=48)).run(u0, 25)
+        assert np.array_equal(got, dg)
+    # AT with one level is plain ADG
+    a = stepper.Stepper(replace(base, scheme="adg")).run(u0, 25)
+    b = stepper.Stepper(replace(base, scheme="adg_at", at_levels=1)).run(u0, 25)
+    assert np.array_equal(a, b)
+
+
+def test_delays_really_applied_and_clamped():
+    w = _wl(scheme="adg_at", degree=2, probs=("0", "0", "1"))   # always k = 2 (mean delay 2.0)
+    st = stepper.Stepper(w, record_delays=True)
+    st.run(stepper.initial_state(w), 8)
+    ks = [st.delay_log[(n, 0)][0] for n in range(8)]
+    # q = 3: k = min(2, max(0, n - 2))
+    assert ks == [0, 0, 0, 1, 2, 2, 2, 2]
+
+
+def test_burgers_pre_shock_exact_solution():
+    errs = []
+    for ne in (32, 64, 128):
+        dx = W.TWO_PI / ne
+        w = W.c3_burgers(n_elem=ne, n_steps=0, sigma=0.05, scheme="dg")
+        dt, n = W.time_step(W.TWO_PI, ne, 0.05, 1.5, 0.4)
+        w = replace(w, dt=dt, n_steps=n, pe_size=ne // 4)
+        errs.append(_run_error(w))
+    e = np.array(errs)
+    assert e[:, 2].max() < 1e-12                                   # conservation
+    slopes = np.log2(e[:-1, 0] / e[1:, 0])
+    assert np.all(slopes > 2.3), slopes                            # high order before the shock
+    # asynchronous AT run stays at the DG error level (smaller Courant number:
+    # the AT extrapolation narrows the stability region, Sec. 4.2.2)
+    ne = 128
+    dt, n = W.time_step(W.TWO_PI, ne, 0.01, 1.5, 0.4)
+    w = replace(W.c3_burgers(n_elem=ne, n_steps=n, sigma=0.01), dt=dt, pe_size=16)
+    at = _run_error(w)
+    dg = _run_error(replace(w, scheme="dg"))
+    adg = _run_error(replace(w, scheme="adg"))
+    assert at[2] < 1e-12 and adg[2] < 1e-12
+    assert at[0] < 1.1 * dg[0] and adg[0] > 1.5 * dg[0]
