@@ -1,0 +1,184 @@
+#!/usr/bin/env python3
+"""Throughput of the ADG-AT forward step on one MI355X.
+
+Workload: 1D linear advection on [0, 2 pi], 2^20 elements, degree 3, 4096
+PEs of 256 elements, delays {0..3} with probabilities (0.5, 0.25, 0.15, 0.1)
+drawn per (step, stage, boundary), ADG-AT with q = 4, classical RK4, FP64,
+eight-mode multi-sine initial data (synthetic).  One bench step = one RK
+time step of the whole hot path (all four stages, interior and PE faces,
+delay draws, ring traffic); the fused step kernel is replayed from a
+hipGraph.  Metric: DOF-stage updates per second (N_E (p+1) S steps / s).
+
+Prints ONE JSON line.  --gpus above 1 is rejected: this build runs on a
+single GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
+BYTES_PER_DOF_STEP_FUSED = 16  # read u^n once, write u^{n+1} once (FP64)
+BYTES_PER_DOF_STAGE_STAGEK = {"rk4": 34.0, "ssprk3": 64.0 / 3, "heun": 28.0}
+
+
+def kernel_source_hash() -> str:
+    path = os.path.join(ROOT, "paper_2404_03399_amd", "csrc", "adg_kernels.hip")
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
+
+def ring_bytes_per_step(w) -> float:
+    """PE-face ring traffic per step: each stage writes one flux per boundary
+    and reads up to q past levels."""
+    if w.scheme == "dg" or w.n_pe <= 1:
+        return 0.0
+    q = (w.at_levels or w.degree + 1) if w.scheme == "adg_at" else 1
+    stages = {"rk4": 4, "ssprk3": 3, "heun": 2}[w.rk]
+    return w.n_pe * stages * 8.0 * (1 + q)
+
+
+def read_traffic(workload_name: str):
+    """HBM bytes per launch from the committed rocprofv3 PMC summary, if it was
+    taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "pmc_fused_step_c2.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", text)
+    t = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not m or not t or m.group(1) != kernel_source_hash():
+        return None
+    return float(t.group(1))
+
+
+def time_solver(torch, solver, u, steps, warmup, graph=True):
+    solver.run(u, warmup, graph=graph)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    solver.run(u, steps, graph=graph)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return ev0.elapsed_time(ev1) / 1e3, wall
+
+
+def cpu_baseline(w, steps: int):
+    """The FP64 oracle on a bounded window of the same workload, one thread."""
+    from threadpoolctl import threadpool_limits
+    from oracle import stepper
+    u0 = stepper.initial_state(w)
+    with threadpool_limits(1):
+        st = stepper.Stepper(w)
+        t0 = time.perf_counter()
+        st.run(u0, steps)
+        dt = time.perf_counter() - t0
+    dof_stage = w.n_elem * (w.degree + 1) * 4 * steps
+    return {"value": dof_stage / dt, "unit": "DOF-stage/s", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} RK4 steps of the same 2^20-element ADG-AT problem ({dt:.1f} s, numpy FP64, 1 thread)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--cpu-steps", type=int, default=8)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--kernel", default="fused", choices=["fused", "stage"])
+    ap.add_argument("--n-elem", type=int, default=1 << 20)
+    ap.add_argument("--extras", action="store_true", help="also time DG/ADG, per-stage kernel, 2^24 mesh")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+    from paper_2404_03399_amd import workloads as W
+    from paper_2404_03399_amd.solver import Solver
+
+    w = W.c2_advection_large("adg_at", n_elem=args.n_elem)
+    s = Solver(w, kernel=args.kernel)
+    u = s.initial_state()
+    gpu_s, wall = time_solver(torch, s, u, args.steps, args.warmup)
+    dofs = w.n_elem * (w.degree + 1)
+    stages = 4
+    value = dofs * stages * args.steps / gpu_s
+    launch_s = gpu_s / args.steps if args.kernel == "fused" else gpu_s / (args.steps * stages)
+    if args.kernel == "fused":
+        alg_bytes = BYTES_PER_DOF_STEP_FUSED * dofs + ring_bytes_per_step(w)
+        kname = "k_fused_step<RK4, upwind>"
+    else:
+        alg_bytes = BYTES_PER_DOF_STAGE_STAGEK["rk4"] * dofs + ring_bytes_per_step(w) / stages
+        kname = "k_stage<RK4, upwind, s> (mean over stages)"
+    achieved = alg_bytes / launch_s / 1e9
+    traffic = read_traffic(w.name) if args.kernel == "fused" and args.n_elem == (1 << 20) else None
+    finite = bool(torch.isfinite(u).all().item())
+
+    out = {
+        "metric": "DOF-stage updates/s (fwd, adjoint) vs HBM roofline; batched vs plain",
+        "value": value,
+        "unit": "DOF-stage/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": gpu_s / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"linear advection ADG-AT(q=4) RK4, N_E={w.n_elem}, p=3, "
+                               f"PE size 256 (P={w.n_pe}), delays {{0..3}} p=(0.5,0.25,0.15,0.1) per stage",
+                   "n_elem": w.n_elem, "degree": 3, "pe_size": 256, "rk": "rk4", "scheme": "adg_at",
+                   "kernel": args.kernel, "dofs": dofs},
+        "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "alg_bytes_per_launch": alg_bytes, "launch_us": launch_s * 1e6,
+                     "note": "working set 2 x 33.6 MB fits the 256 MB Infinity Cache"},
+        "wall_s": wall,
+        "state_finite": finite,
+    }
+    if args.extras:
+        ex = {}
+        for scheme in ("dg", "adg"):
+            ws = W.c2_advection_large(scheme, n_elem=args.n_elem)
+            so = Solver(ws)
+            uu = so.initial_state()
+            g, _ = time_solver(torch, so, uu, args.steps // 2, 20)
+            ex[f"{scheme}_dof_stage_per_s"] = dofs * stages * (args.steps // 2) / g
+            so.close()
+        so = Solver(w, kernel="stage")
+        uu = so.initial_state()
+        g, _ = time_solver(torch, so, uu, args.steps // 2, 20)
+        ex["stage_kernel_dof_stage_per_s"] = dofs * stages * (args.steps // 2) / g
+        so.close()
+        wl = W.c2_advection_large("adg_at", n_elem=1 << 24)
+        so = Solver(wl)
+        uu = so.initial_state()
+        g, _ = time_solver(torch, so, uu, 100, 10)
+        d24 = wl.n_elem * 4
+        ex["n2^24_dof_stage_per_s"] = d24 * stages * 100 / g
+        ex["n2^24_hbm_frac"] = (BYTES_PER_DOF_STEP_FUSED * d24 + ring_bytes_per_step(wl)) / (g / 100) / 1e9 / HBM_PEAK_GBS
+        so.close()
+        out["extras"] = ex
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
+        out["cpu_baseline"]["host"] = {"cpu_count": os.cpu_count()}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,188 @@
+/*
+ * adg.h -- C ABI of the MI355X (gfx950) asynchronous discontinuous Galerkin
+ * stepper with asynchrony-tolerant (AT) fluxes.
+ *
+ * Method: Goswami & Aditya, "An asynchronous discontinuous Galerkin method
+ * for massively parallel PDE solvers", arXiv 2404.03399.
+ *   - u_t + f(u)_x = 0 on a periodic interval (Sec. 2, model problem);
+ *     f = a u (linear advection) or f = u^2/2 (inviscid Burgers).
+ *   - N_E uniform elements, nodal Lagrange basis of degree N_p on
+ *     Gauss-Lobatto-Legendre nodes, exact mass matrix (Sec. 2, element-wise
+ *     weak form and reference matrices).
+ *   - The elements are split into P = n_elem / pe_size processing elements
+ *     (PEs); only the P faces between PEs see delayed data (Sec. 2 parallel
+ *     implementation, Sec. 3).
+ *   - Delays k in {0..L-1} with probabilities p_k are emulated by a
+ *     counter-based draw (Sec. 6.1 delay emulation): one draw per PE
+ *     boundary per step (or per RK stage), SplitMix64 chained over
+ *     (seed, step, stage key, boundary), 53-bit uniform, binned by
+ *     integer thresholds.
+ *   - Conservative ADG: both neighbours use the flux of the common delayed
+ *     level (Sec. 4.1).  ADG-AT: flux = sum_{j<q} c_j(k) F^{n-k-j} with the
+ *     AT coefficients of Sec. 5 / Table 1 (q = N_p + 1 by default).
+ *
+ * Conventions
+ *   - Every call returns an int status (adg_status); nothing throws or aborts
+ *     across the ABI.  adg_last_error() returns a thread-local message.
+ *   - The library never allocates device memory.  All device buffers (state,
+ *     workspace, adjoint outputs) are caller-owned; the workspace must stay
+ *     alive and untouched until adg_destroy.
+ *   - Work is enqueued on the caller's HIP stream and the call returns
+ *     without synchronising (except adg_run with ADG_RUN_CHECK_FINITE and
+ *     adg_adjoint's final scalar read, which synchronise the stream).  A kernel
+ *     fault surfaces as ADG_E_HIP from a later call or from the caller's own
+ *     stream synchronisation.
+ *   - State layout: structure of arrays per problem.  Problem i owns
+ *     u[offset_i + j * ld_i + e], node plane j in [0, degree], element
+ *     e in [0, n_elem); ld_i = n_elem rounded up to 64.  Padding entries are
+ *     never read or written.  Offsets/lds come from adg_state_layout.
+ *   - A context is not thread-safe.  All problems of one context advance
+ *     together and must share equation, flux, rk and scheme; degree, mesh,
+ *     PE size, delays, seed, speed and dt may differ (batched ensembles).
+ */
+#ifndef ADG_H
+#define ADG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ADG_ABI_VERSION 1
+
+enum adg_status {
+  ADG_OK = 0,
+  ADG_E_INVALID = -1,      /* bad argument or unsupported combination           */
+  ADG_E_ABI = -2,          /* adg_problem.abi_version != ADG_ABI_VERSION        */
+  ADG_E_WORKSPACE = -3,    /* workspace missing, too small or misaligned        */
+  ADG_E_HIP = -4,          /* a HIP runtime call failed                         */
+  ADG_E_STATE = -5,        /* call sequence invalid (e.g. adjoint w/o record)   */
+  ADG_E_NONFINITE = -6,    /* ADG_RUN_CHECK_FINITE found a NaN/Inf              */
+  ADG_E_UNSUPPORTED = -7   /* valid request not implemented by this build       */
+};
+
+enum adg_equation { ADG_EQ_ADVECTION = 0, ADG_EQ_BURGERS = 1 };
+enum adg_scheme { ADG_SCHEME_DG = 0, ADG_SCHEME_ADG = 1, ADG_SCHEME_ADG_AT = 2 };
+/* upwind / central: f^ = a (B+ u- + B- u+) (Sec. 2);  llf: local Lax-Friedrichs
+ * 1/2 (f(u-) + f(u+)) - lambda/2 (u+ - u-), lambda = max(|u-|, |u+|) (Sec. 6.1). */
+enum adg_flux { ADG_FLUX_UPWIND = 0, ADG_FLUX_CENTRAL = 1, ADG_FLUX_LLF = 2 };
+/* Heun RK2 as in Sec. 4.2.1; Shu-Osher SSP-RK3; classical RK4. */
+enum adg_rk { ADG_RK2_HEUN = 0, ADG_SSPRK3 = 1, ADG_RK4 = 2 };
+enum adg_delay_granularity { ADG_DELAY_PER_STEP = 0, ADG_DELAY_PER_STAGE = 1 };
+/* Kernel family: one launch per RK stage with the RK registers in HBM, or one
+ * launch per time step with all stages kept on chip (halo recompute). */
+enum adg_kernel { ADG_KERNEL_AUTO = 0, ADG_KERNEL_STAGE = 1, ADG_KERNEL_FUSED = 2 };
+
+#define ADG_RUN_GRAPH 1u         /* capture the step loop in a hipGraph and replay it */
+#define ADG_RUN_RECORD 2u        /* keep checkpoints for adg_adjoint (run must start at step 0) */
+#define ADG_RUN_CHECK_FINITE 4u  /* fail with ADG_E_NONFINITE if the final state has NaN/Inf */
+
+/* One problem (plain data, copied by adg_init). */
+typedef struct adg_problem {
+  uint32_t abi_version;        /* = ADG_ABI_VERSION */
+  uint32_t equation;           /* adg_equation */
+  uint32_t scheme;             /* adg_scheme */
+  uint32_t flux;               /* adg_flux: upwind/central need advection, llf needs Burgers */
+  uint32_t rk;                 /* adg_rk */
+  uint32_t degree;             /* N_p in 1..4 */
+  uint32_t at_levels;          /* q of the AT flux, 1..5; 0 -> degree + 1; must be 0 unless ADG-AT */
+  uint32_t n_delays;           /* L in 1..8 (delays 0..L-1) */
+  uint32_t delay_granularity;  /* adg_delay_granularity */
+  uint32_t reserved;           /* must be 0 */
+  int64_t n_elem;              /* N_E >= 2 */
+  int64_t pe_size;             /* elements per PE, divides n_elem; P = n_elem / pe_size; P == 1: no PE faces */
+  uint64_t seed;               /* delay-stream seed */
+  uint64_t delay_threshold[7]; /* L-1 non-decreasing cut-offs T_1..T_{L-1} <= 2^53 on the 53-bit uniform;
+                                  delay = #{k : U >= T_k}; unused entries ignored */
+  double x_left;               /* left end of the periodic interval */
+  double length;               /* interval length (> 0) */
+  double speed;                /* advection speed a (advection only; != 0) */
+  double dt;                   /* fixed time step (> 0) */
+} adg_problem;
+
+typedef struct adg_options {
+  int64_t ckpt_every;          /* adjoint checkpoint interval in steps; 0 -> 64 */
+  int32_t kernel;              /* adg_kernel; AUTO -> FUSED */
+  int32_t tile_elems;          /* owned elements per workgroup for the fused kernel; 0 -> default */
+  uint32_t flags;              /* reserved, 0 */
+  uint32_t reserved;
+} adg_options;
+
+typedef struct adg_ctx adg_ctx;  /* opaque, host side, library owned */
+
+/* Returns ADG_ABI_VERSION. */
+int adg_abi_version(void);
+
+/* Thread-local description of the last failure in this thread ("" if none). */
+const char* adg_last_error(void);
+
+/* GLL nodes of the reference element [-1, 1] for the given degree (1..4):
+ * writes degree+1 doubles to host array xi.  Lets callers build nodal
+ * initial data u[j*ld+e] = u0(x_left + e*dx + (xi[j]+1)*dx/2). */
+int adg_nodes(int32_t degree, double* xi);
+
+/* Layout of the state vector for n_probs problems: per-problem offsets and
+ * leading dimensions (host arrays of n_probs int64), and the total number of
+ * doubles the caller must allocate. */
+int adg_state_layout(const adg_problem* probs, int32_t n_probs, int64_t* offsets, int64_t* lds,
+                     int64_t* total_doubles);
+
+/* Device workspace bytes needed by adg_init for these problems, options and
+ * an adjoint recording horizon of n_steps_record steps (0 if adg_adjoint
+ * is not used). */
+int adg_workspace_size(const adg_problem* probs, int32_t n_probs, const adg_options* opt,
+                       int64_t n_steps_record, int64_t* bytes_out);
+
+/* Validate the problems, build the reference operators, AT table and tile
+ * work list on the host, upload them into the caller's device workspace
+ * (256-byte aligned, >= adg_workspace_size bytes) on hip_stream (a
+ * hipStream_t, NULL = default stream) and reset the step counter and delay
+ * history.  n_steps_record must match the value given to
+ * adg_workspace_size.  On success *out owns a host-side context. */
+int adg_init(adg_ctx** out, const adg_problem* probs, int32_t n_probs, const adg_options* opt,
+             int64_t n_steps_record, void* d_workspace, int64_t workspace_bytes, void* hip_stream);
+
+/* Step counter := 0, delay history := 0, recorded checkpoints dropped. */
+int adg_reset(adg_ctx* ctx);
+
+/* Number of steps taken since init/reset (host mirror of the device counter). */
+int adg_step_count(const adg_ctx* ctx, int64_t* steps);
+
+/* One RK time step of every problem, in place on the device state d_u. */
+int adg_step(adg_ctx* ctx, double* d_u);
+
+/* n_steps RK time steps in place on d_u.  flags: ADG_RUN_GRAPH,
+ * ADG_RUN_RECORD (the context must be at step 0 and n_steps <= the recording
+ * horizon given to adg_init), ADG_RUN_CHECK_FINITE. */
+int adg_run(adg_ctx* ctx, double* d_u, int64_t n_steps, uint32_t flags);
+
+/* Discrete adjoint of the recorded run (delay schedule held fixed) for
+ * J(u(T)) with cotangent d_cot_uT = dJ/du(T) (device, state layout).
+ * Writes dJ/du(0) to d_grad_u0 (device, state layout) and, for advection,
+ * dJ/da per problem to the host array h_grad_speed (n_probs doubles; dt is
+ * held fixed).  Requires the last adg_run to have used ADG_RUN_RECORD. */
+int adg_adjoint(adg_ctx* ctx, const double* d_cot_uT, double* d_grad_u0, double* h_grad_speed);
+
+/* Per-problem error statistics against a reference state (same layout):
+ * for each problem i writes h_out[3*i + 0] = mean |u - ref| over all nodal
+ * values, h_out[3*i + 1] = max |u - ref|, h_out[3*i + 2] = (dx/2) sum_e w^T u^e
+ * (the discrete integral).  Deterministic (fixed reduction order).
+ * Synchronises the stream. */
+int adg_error_stats(adg_ctx* ctx, const double* d_u, const double* d_ref, double* h_out);
+
+/* Host-side delay schedule of one problem (same integers the kernels use):
+ * h_k[((n - step0) * S + s) * P + b] = clamped delay at step n, RK stage s,
+ * boundary b, for n in [step0, step0 + n_steps).  S = number of RK stages,
+ * P = number of PEs (P == 1: nothing written). */
+int adg_delay_schedule(const adg_problem* prob, int64_t step0, int64_t n_steps, int32_t* h_k);
+
+/* Release the context (host memory and hipGraphs).  The workspace may be
+ * freed afterwards. */
+int adg_destroy(adg_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ADG_H */

@@ -1,0 +1,612 @@
+// C ABI of the ADG library: validation, reference operators, AT table,
+// workspace layout, launch sequencing and hipGraph replay.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "adg.h"
+#include "adg_launch.hpp"
+
+using namespace adg;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define ADG_HIP(expr)                                                                         \
+  do {                                                                                        \
+    hipError_t e_ = (expr);                                                                   \
+    if (e_ != hipSuccess) return fail(ADG_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr int64_t kAlign = 256;
+int64_t align_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+
+// ------------------------------------------------ reference element (host) --
+// Legendre P_p and P_p' at x by the three-term recurrence.
+void legendre(int p, long double x, long double* P, long double* dP) {
+  long double p0 = 1.0L, p1 = x;
+  if (p == 0) { *P = 1.0L; *dP = 0.0L; return; }
+  for (int k = 1; k < p; ++k) {
+    const long double p2 = ((2 * k + 1) * x * p1 - k * p0) / (k + 1);
+    p0 = p1;
+    p1 = p2;
+  }
+  *P = p1;
+  *dP = p * (x * p1 - p0) / (x * x - 1.0L);  // valid for |x| < 1
+}
+
+// Gauss-Lobatto-Legendre nodes: -1, roots of P_p' (Newton from the
+// Chebyshev-Lobatto points), +1.
+void gll(int p, long double* x) {
+  x[0] = -1.0L;
+  x[p] = 1.0L;
+  for (int i = 1; i < p; ++i) {
+    long double z = -std::cos(3.14159265358979323846264338327950288L * i / p);
+    for (int it = 0; it < 100; ++it) {
+      long double P, dP;
+      legendre(p, z, &P, &dP);
+      // (1 - z^2) P'' = 2 z P' - p (p + 1) P
+      const long double d2P = (2.0L * z * dP - p * (p + 1) * P) / (1.0L - z * z);
+      const long double step = dP / d2P;
+      z -= step;
+      if (std::fabs(step) < 1e-30L) break;
+    }
+    x[i] = z;
+  }
+  std::sort(x, x + p + 1);
+}
+
+// Monomial coefficients c[j][m] of the Lagrange cardinal polynomials.
+void lagrange_monomials(int p, const long double* x, long double c[kMaxNp][kMaxNp]) {
+  for (int j = 0; j <= p; ++j) {
+    long double poly[kMaxNp] = {1.0L};
+    int deg = 0;
+    for (int m = 0; m <= p; ++m) {
+      if (m == j) continue;
+      const long double inv = 1.0L / (x[j] - x[m]);
+      long double nxt[kMaxNp] = {0};
+      for (int d = 0; d <= deg; ++d) {
+        nxt[d + 1] += poly[d] * inv;
+        nxt[d] -= poly[d] * x[m] * inv;
+      }
+      ++deg;
+      std::memcpy(poly, nxt, sizeof(poly));
+    }
+    for (int m = 0; m <= p; ++m) c[j][m] = poly[m];
+  }
+}
+
+long double mono_int(int k) { return (k % 2) ? 0.0L : 2.0L / (k + 1); }  // int_{-1}^{1} xi^k
+
+// Solve A X = B (n x n, m right-hand sides) by Gaussian elimination with
+// partial pivoting, in place (B becomes X).
+void solve(int n, int m, long double A[kMaxNp][kMaxNp], long double B[kMaxNp][kMaxNp + 2]) {
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < n; ++r)
+      if (std::fabs(A[r][c]) > std::fabs(A[piv][c])) piv = r;
+    for (int k = 0; k < n; ++k) std::swap(A[c][k], A[piv][k]);
+    for (int k = 0; k < m; ++k) std::swap(B[c][k], B[piv][k]);
+    for (int r = 0; r < n; ++r) {
+      if (r == c) continue;
+      const long double f = A[r][c] / A[c][c];
+      for (int k = 0; k < n; ++k) A[r][k] -= f * A[c][k];
+      for (int k = 0; k < m; ++k) B[r][k] -= f * B[c][k];
+    }
+  }
+  for (int r = 0; r < n; ++r)
+    for (int k = 0; k < m; ++k) B[r][k] /= A[r][r];
+}
+
+// D = M^-1 S, lift_l = M^-1 e_0, lift_r = M^-1 e_p, w = M 1; M and S integrated
+// exactly on monomials: M_ij = int phi_i phi_j, S_ij = int phi_j phi_i'.
+void element_operators(int p, DevProblem* dp) {
+  const int np = p + 1;
+  long double x[kMaxNp], c[kMaxNp][kMaxNp];
+  gll(p, x);
+  lagrange_monomials(p, x, c);
+  long double M[kMaxNp][kMaxNp] = {}, RHS[kMaxNp][kMaxNp + 2] = {};
+  for (int i = 0; i < np; ++i)
+    for (int j = 0; j < np; ++j) {
+      long double m = 0.0L, s = 0.0L;
+      for (int a = 0; a < np; ++a)
+        for (int b = 0; b < np; ++b) {
+          m += c[i][a] * c[j][b] * mono_int(a + b);
+          if (b >= 1) s += c[j][a] * (b * c[i][b]) * mono_int(a + b - 1);
+        }
+      M[i][j] = m;
+      RHS[i][j] = s;
+    }
+  long double w[kMaxNp] = {};
+  for (int i = 0; i < np; ++i)
+    for (int j = 0; j < np; ++j) w[i] += M[i][j];
+  RHS[0][np] = 1.0L;       // e_0
+  RHS[p][np + 1] = 1.0L;   // e_p
+  solve(np, np + 2, M, RHS);
+  for (int i = 0; i < kMaxNp * kMaxNp; ++i) dp->D[i] = 0.0;
+  for (int i = 0; i < np; ++i) {
+    for (int j = 0; j < np; ++j) dp->D[i * kMaxNp + j] = (double)RHS[i][j];
+    dp->lift_l[i] = (double)RHS[i][np];
+    dp->lift_r[i] = (double)RHS[i][np + 1];
+    dp->wq[i] = (double)w[i];
+  }
+}
+
+// AT coefficients in closed form: the moment conditions of the AT flux make
+// c_j(k) the Lagrange weights extrapolating levels -(k+j) to 0:
+// c_j(k) = prod_{m != j} (k + m) / (m - j)  (integers).
+double at_coefficient(int q, int k, int j) {
+  long long num = 1, den = 1;
+  for (int m = 0; m < q; ++m) {
+    if (m == j) continue;
+    num *= (long long)(k + m);
+    den *= (long long)(m - j);
+  }
+  return (double)(num / den);
+}
+
+int phys_of(const adg_problem& p) {
+  if (p.equation == ADG_EQ_BURGERS) return PHYS_BURGERS_LLF;
+  return p.flux == ADG_FLUX_CENTRAL ? PHYS_ADV_CENTRAL : PHYS_ADV_UPWIND;
+}
+
+int q_of(const adg_problem& p) {
+  if (p.scheme != ADG_SCHEME_ADG_AT) return 1;
+  return p.at_levels ? (int)p.at_levels : (int)p.degree + 1;
+}
+
+int64_t ld_of(const adg_problem& p) { return align_up(p.n_elem, 64); }
+
+bool async_of(const adg_problem& p) { return p.scheme != ADG_SCHEME_DG && p.n_elem / p.pe_size > 1; }
+
+int validate_one(const adg_problem& p, int idx) {
+  const std::string at = "problem " + std::to_string(idx) + ": ";
+  if (p.abi_version != ADG_ABI_VERSION) return fail(ADG_E_ABI, at + "abi_version mismatch");
+  if (p.equation > ADG_EQ_BURGERS) return fail(ADG_E_INVALID, at + "unknown equation");
+  if (p.scheme > ADG_SCHEME_ADG_AT) return fail(ADG_E_INVALID, at + "unknown scheme");
+  if (p.flux > ADG_FLUX_LLF) return fail(ADG_E_INVALID, at + "unknown flux");
+  if (p.rk > ADG_RK4) return fail(ADG_E_INVALID, at + "unknown rk");
+  if (p.degree < 1 || p.degree > 4) return fail(ADG_E_INVALID, at + "degree must be in 1..4");
+  if (p.equation == ADG_EQ_ADVECTION && p.flux == ADG_FLUX_LLF)
+    return fail(ADG_E_INVALID, at + "llf flux is for Burgers");
+  if (p.equation == ADG_EQ_BURGERS && p.flux != ADG_FLUX_LLF)
+    return fail(ADG_E_INVALID, at + "Burgers needs the llf flux");
+  if (p.at_levels != 0 && p.scheme != ADG_SCHEME_ADG_AT)
+    return fail(ADG_E_INVALID, at + "at_levels is only for ADG-AT");
+  if (p.at_levels > (uint32_t)kMaxQ) return fail(ADG_E_INVALID, at + "at_levels must be <= 5");
+  if (p.scheme == ADG_SCHEME_ADG_AT && p.at_levels == 0 && p.degree + 1 > (uint32_t)kMaxQ)
+    return fail(ADG_E_INVALID, at + "q = degree + 1 exceeds 5");
+  if (p.n_delays < 1 || p.n_delays > (uint32_t)kMaxL) return fail(ADG_E_INVALID, at + "n_delays must be in 1..8");
+  if (p.delay_granularity > ADG_DELAY_PER_STAGE) return fail(ADG_E_INVALID, at + "bad delay_granularity");
+  if (p.reserved != 0) return fail(ADG_E_INVALID, at + "reserved must be 0");
+  if (p.n_elem < 2 || p.n_elem > (int64_t)1 << 30) return fail(ADG_E_INVALID, at + "n_elem must be in 2..2^30");
+  if (p.pe_size < 1 || p.n_elem % p.pe_size != 0) return fail(ADG_E_INVALID, at + "pe_size must divide n_elem");
+  for (uint32_t i = 0; i + 1 < p.n_delays; ++i) {
+    if (p.delay_threshold[i] > (1ull << 53)) return fail(ADG_E_INVALID, at + "threshold > 2^53");
+    if (i > 0 && p.delay_threshold[i] < p.delay_threshold[i - 1])
+      return fail(ADG_E_INVALID, at + "thresholds must be non-decreasing");
+  }
+  if (!(p.length > 0.0) || !std::isfinite(p.length)) return fail(ADG_E_INVALID, at + "length must be > 0");
+  if (!(p.dt > 0.0) || !std::isfinite(p.dt)) return fail(ADG_E_INVALID, at + "dt must be > 0");
+  if (!std::isfinite(p.x_left)) return fail(ADG_E_INVALID, at + "x_left must be finite");
+  if (p.equation == ADG_EQ_ADVECTION && (!(p.speed != 0.0) || !std::isfinite(p.speed)))
+    return fail(ADG_E_INVALID, at + "speed must be finite and non-zero");
+  return ADG_OK;
+}
+
+int validate(const adg_problem* probs, int32_t n) {
+  if (!probs || n < 1) return fail(ADG_E_INVALID, "need at least one problem");
+  for (int32_t i = 0; i < n; ++i) {
+    const int rc = validate_one(probs[i], i);
+    if (rc) return rc;
+  }
+  for (int32_t i = 1; i < n; ++i) {
+    const adg_problem &a = probs[0], &b = probs[i];
+    if (a.equation != b.equation || a.flux != b.flux || a.rk != b.rk || a.scheme != b.scheme)
+      return fail(ADG_E_INVALID, "all problems of a context must share equation, flux, rk and scheme");
+  }
+  return ADG_OK;
+}
+
+struct Layout {
+  int64_t probs, work_f, work_s, first_s, ctr, ring, state2, y0, y1, acc, part, stats_out, total;
+  int32_t n_work_f, n_work_s;
+  int64_t total_doubles;
+  int64_t ring_doubles;
+};
+
+int kernel_of(const adg_options* opt) {
+  if (!opt || opt->kernel == ADG_KERNEL_AUTO) return ADG_KERNEL_FUSED;
+  return opt->kernel;
+}
+
+Layout make_layout(const adg_problem* probs, int32_t n, const adg_options* opt) {
+  Layout L{};
+  const int S = rk_stages((int)probs[0].rk);
+  const int T = fused_tile((int)probs[0].rk);
+  int64_t nwf = 0, nws = 0, tot = 0, ring = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    const adg_problem& p = probs[i];
+    nwf += (p.n_elem + T - 1) / T;
+    nws += (p.n_elem + kBlock - 1) / kBlock;
+    tot += ld_of(p) * (p.degree + 1);
+    if (async_of(p)) ring += (p.n_elem / p.pe_size) * S * (int64_t)(p.n_delays + q_of(p) - 1);
+  }
+  L.n_work_f = (int32_t)nwf;
+  L.n_work_s = (int32_t)nws;
+  L.total_doubles = tot;
+  L.ring_doubles = ring;
+  const int kern = kernel_of(opt);
+  int64_t off = 0;
+  auto take = [&](int64_t bytes) { const int64_t o = off; off = align_up(off + bytes, kAlign); return o; };
+  L.probs = take((int64_t)sizeof(DevProblem) * n);
+  L.work_f = take((int64_t)sizeof(WorkItem) * nwf);
+  L.work_s = take((int64_t)sizeof(WorkItem) * nws);
+  L.first_s = take((int64_t)sizeof(int32_t) * (n + 1));
+  L.ctr = take(8 * sizeof(int64_t));
+  L.ring = take(8 * std::max<int64_t>(ring, 1));
+  L.state2 = kern == ADG_KERNEL_FUSED ? take(8 * tot) : -1;
+  L.y0 = kern == ADG_KERNEL_STAGE ? take(8 * tot) : -1;
+  L.y1 = kern == ADG_KERNEL_STAGE ? take(8 * tot) : -1;
+  L.acc = kern == ADG_KERNEL_STAGE ? take(8 * tot) : -1;
+  L.part = take(3 * 8 * nws);
+  L.stats_out = take(3 * 8 * (int64_t)n);
+  L.total = off;
+  return L;
+}
+
+}  // namespace
+
+struct adg_ctx {
+  std::vector<adg_problem> probs;
+  std::vector<DevProblem> dev;
+  adg_options opt{};
+  int kernel = ADG_KERNEL_FUSED;
+  int rk = 0, phys = 0, S = 0;
+  hipStream_t stream = nullptr;
+  char* ws = nullptr;
+  Layout L{};
+  int64_t steps = 0;
+  // graph cache
+  hipGraphExec_t graph = nullptr;
+  const double* graph_u = nullptr;
+  int graph_steps = 0;
+
+  StepArgs fused_args() const {
+    return StepArgs{(const DevProblem*)(ws + L.probs), (const WorkItem*)(ws + L.work_f), L.n_work_f,
+                    (double*)(ws + L.ring), (int64_t*)(ws + L.ctr)};
+  }
+  StepArgs stage_args() const {
+    return StepArgs{(const DevProblem*)(ws + L.probs), (const WorkItem*)(ws + L.work_s), L.n_work_s,
+                    (double*)(ws + L.ring), (int64_t*)(ws + L.ctr)};
+  }
+  double* state2() const { return (double*)(ws + L.state2); }
+};
+
+namespace {
+
+// Enqueue one step; for the fused kernel the result lands in *cur after a
+// swap with the internal buffer.
+int enqueue_step(adg_ctx* c, double** cur, double** other, int32_t step_offset, hipStream_t st) {
+  if (c->kernel == ADG_KERNEL_FUSED) {
+    const StepArgs a = c->fused_args();
+    ADG_HIP(launch_fused_step(c->rk, c->phys, a, *cur, *other, step_offset, st));
+    std::swap(*cur, *other);
+    return ADG_OK;
+  }
+  const StepArgs a = c->stage_args();
+  double* U = *cur;
+  double* Y0 = (double*)(c->ws + c->L.y0);
+  double* Y1 = (double*)(c->ws + c->L.y1);
+  double* A = (double*)(c->ws + c->L.acc);
+  for (int s = 0; s < c->S; ++s) {
+    const double* yin = s == 0 ? U : ((s & 1) ? Y0 : Y1);
+    double* yout = (s & 1) ? Y1 : Y0;
+    ADG_HIP(launch_stage(c->rk, c->phys, s, a, yin, yout, U, A, step_offset, st));
+  }
+  return ADG_OK;
+}
+
+int reset_device(adg_ctx* c) {
+  ADG_HIP(hipMemsetAsync(c->ws + c->L.ctr, 0, 8 * sizeof(int64_t), c->stream));
+  ADG_HIP(hipMemsetAsync(c->ws + c->L.ring, 0, 8 * std::max<int64_t>(c->L.ring_doubles, 1), c->stream));
+  c->steps = 0;
+  return ADG_OK;
+}
+
+void drop_graph(adg_ctx* c) {
+  if (c->graph) (void)hipGraphExecDestroy(c->graph);
+  c->graph = nullptr;
+  c->graph_u = nullptr;
+  c->graph_steps = 0;
+}
+
+constexpr int kGraphSteps = 16;  // even: the fused ping-pong ends in the caller's buffer
+
+int build_graph(adg_ctx* c, double* d_u) {
+  drop_graph(c);
+  hipStream_t cap;
+  ADG_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+  hipGraph_t g = nullptr;
+  int rc = ADG_OK;
+  if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    (void)hipStreamDestroy(cap);
+    return fail(ADG_E_HIP, "hipStreamBeginCapture failed");
+  }
+  double* cur = d_u;
+  double* other = c->state2();
+  for (int i = 0; i < kGraphSteps && rc == ADG_OK; ++i) rc = enqueue_step(c, &cur, &other, i, cap);
+  if (rc == ADG_OK && launch_advance((int64_t*)(c->ws + c->L.ctr), kGraphSteps, cap) != hipSuccess)
+    rc = fail(ADG_E_HIP, "capture of the step-counter advance failed");
+  const hipError_t e1 = hipStreamEndCapture(cap, &g);
+  (void)hipStreamDestroy(cap);
+  if (rc != ADG_OK) { if (g) (void)hipGraphDestroy(g); return rc; }
+  if (e1 != hipSuccess) return fail(ADG_E_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e1));
+  hipGraphExec_t ex = nullptr;
+  const hipError_t e2 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e2 != hipSuccess) return fail(ADG_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e2));
+  c->graph = ex;
+  c->graph_u = d_u;
+  c->graph_steps = kGraphSteps;
+  return ADG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int adg_abi_version(void) { return ADG_ABI_VERSION; }
+
+const char* adg_last_error(void) { return g_err.c_str(); }
+
+int adg_nodes(int32_t degree, double* xi) {
+  if (degree < 1 || degree > 4 || !xi) return fail(ADG_E_INVALID, "adg_nodes: degree must be 1..4");
+  long double x[kMaxNp];
+  gll(degree, x);
+  for (int i = 0; i <= degree; ++i) xi[i] = (double)x[i];
+  return ADG_OK;
+}
+
+int adg_state_layout(const adg_problem* probs, int32_t n_probs, int64_t* offsets, int64_t* lds,
+                     int64_t* total_doubles) {
+  int rc = validate(probs, n_probs);
+  if (rc) return rc;
+  int64_t off = 0;
+  for (int32_t i = 0; i < n_probs; ++i) {
+    if (offsets) offsets[i] = off;
+    if (lds) lds[i] = ld_of(probs[i]);
+    off += ld_of(probs[i]) * (probs[i].degree + 1);
+  }
+  if (total_doubles) *total_doubles = off;
+  return ADG_OK;
+}
+
+int adg_workspace_size(const adg_problem* probs, int32_t n_probs, const adg_options* opt, int64_t n_steps_record,
+                       int64_t* bytes_out) {
+  int rc = validate(probs, n_probs);
+  if (rc) return rc;
+  if (!bytes_out) return fail(ADG_E_INVALID, "bytes_out is null");
+  if (n_steps_record != 0) return fail(ADG_E_UNSUPPORTED, "adjoint recording is not available in this build");
+  const int k = kernel_of(opt);
+  if (k != ADG_KERNEL_FUSED && k != ADG_KERNEL_STAGE) return fail(ADG_E_INVALID, "unknown kernel family");
+  *bytes_out = make_layout(probs, n_probs, opt).total;
+  return ADG_OK;
+}
+
+int adg_init(adg_ctx** out, const adg_problem* probs, int32_t n_probs, const adg_options* opt, int64_t n_steps_record,
+             void* d_workspace, int64_t workspace_bytes, void* hip_stream) {
+  if (!out) return fail(ADG_E_INVALID, "out is null");
+  *out = nullptr;
+  int64_t need = 0;
+  int rc = adg_workspace_size(probs, n_probs, opt, n_steps_record, &need);
+  if (rc) return rc;
+  if (!d_workspace || workspace_bytes < need) return fail(ADG_E_WORKSPACE, "workspace too small: need " + std::to_string(need));
+  if (((uintptr_t)d_workspace) % kAlign) return fail(ADG_E_WORKSPACE, "workspace must be 256-byte aligned");
+  if (opt && opt->tile_elems != 0) return fail(ADG_E_UNSUPPORTED, "tile_elems override is not available");
+
+  adg_ctx* c = new adg_ctx();
+  c->probs.assign(probs, probs + n_probs);
+  if (opt) c->opt = *opt;
+  c->kernel = kernel_of(opt);
+  c->rk = (int)probs[0].rk;
+  c->phys = phys_of(probs[0]);
+  c->S = rk_stages(c->rk);
+  c->stream = (hipStream_t)hip_stream;
+  c->ws = (char*)d_workspace;
+  c->L = make_layout(probs, n_probs, opt);
+
+  // descriptors
+  c->dev.resize(n_probs);
+  int64_t uoff = 0, roff = 0;
+  for (int32_t i = 0; i < n_probs; ++i) {
+    const adg_problem& p = probs[i];
+    DevProblem& d = c->dev[i];
+    std::memset(&d, 0, sizeof(d));
+    d.n_elem = p.n_elem;
+    d.pe_size = p.pe_size;
+    d.n_pe = p.n_elem / p.pe_size;
+    d.ld = ld_of(p);
+    d.u_off = uoff;
+    uoff += d.ld * (p.degree + 1);
+    d.np = (int)p.degree + 1;
+    d.q = q_of(p);
+    d.n_delays = (int)p.n_delays;
+    d.depth = d.n_delays + d.q - 1;
+    d.per_stage = p.delay_granularity == ADG_DELAY_PER_STAGE;
+    d.scheme = (int)p.scheme;
+    d.async_faces = async_of(p) ? 1 : 0;
+    d.pe_div = make_fast_div((uint32_t)p.pe_size);
+    for (int64_t v : {(int64_t)0, p.pe_size - 1, p.pe_size, p.n_elem - 1, p.n_elem, p.n_elem / 2 + 1}) {
+      if (v < 0) continue;
+      if ((int64_t)fast_div((uint32_t)v, d.pe_div) != v / p.pe_size) {
+        delete c;
+        return fail(ADG_E_INVALID, "internal: division by pe_size failed self-check");
+      }
+    }
+    d.ring_off = roff;
+    if (d.async_faces) roff += d.n_pe * c->S * (int64_t)d.depth;
+    d.seed = p.seed;
+    for (int k = 0; k + 1 < d.n_delays; ++k) d.thr[k] = p.delay_threshold[k];
+    const double dx = p.length / (double)p.n_elem;
+    d.two_over_dx = 2.0 / dx;
+    d.half_dx = 0.5 * dx;
+    d.speed = p.equation == ADG_EQ_ADVECTION ? p.speed : 1.0;
+    d.dt = p.dt;
+    element_operators((int)p.degree, &d);
+    for (int k = 0; k < d.n_delays; ++k)
+      for (int j = 0; j < d.q; ++j) d.atc[k][j] = at_coefficient(d.q, k, j);
+  }
+  // work lists: heaviest (highest degree) problems first
+  std::vector<int32_t> order(n_probs);
+  for (int32_t i = 0; i < n_probs; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return probs[a].degree > probs[b].degree; });
+  const int T = fused_tile(c->rk);
+  std::vector<WorkItem> wf, ws_;
+  std::vector<int32_t> first(n_probs + 1, 0);
+  wf.reserve(c->L.n_work_f);
+  for (int32_t i : order) {
+    const int64_t nt = (probs[i].n_elem + T - 1) / T;
+    for (int64_t t = 0; t < nt; ++t) wf.push_back(WorkItem{i, (int32_t)t});
+  }
+  for (int32_t i = 0; i < n_probs; ++i) {  // stage/stats list in problem order (contiguous per problem)
+    first[i] = (int32_t)ws_.size();
+    const int64_t nt = (probs[i].n_elem + kBlock - 1) / kBlock;
+    for (int64_t t = 0; t < nt; ++t) ws_.push_back(WorkItem{i, (int32_t)t});
+  }
+  first[n_probs] = (int32_t)ws_.size();
+
+  auto up = [&](int64_t off, const void* src, int64_t bytes) -> int {
+    ADG_HIP(hipMemcpyAsync(c->ws + off, src, bytes, hipMemcpyHostToDevice, c->stream));
+    return ADG_OK;
+  };
+  if ((rc = up(c->L.probs, c->dev.data(), (int64_t)sizeof(DevProblem) * n_probs)) ||
+      (rc = up(c->L.work_f, wf.data(), (int64_t)sizeof(WorkItem) * wf.size())) ||
+      (rc = up(c->L.work_s, ws_.data(), (int64_t)sizeof(WorkItem) * ws_.size())) ||
+      (rc = up(c->L.first_s, first.data(), (int64_t)sizeof(int32_t) * first.size())) ||
+      (rc = reset_device(c))) {
+    delete c;
+    return rc;
+  }
+  // host data above must stay valid until the copies ran
+  if (hipStreamSynchronize(c->stream) != hipSuccess) {
+    delete c;
+    return fail(ADG_E_HIP, "stream synchronisation after upload failed");
+  }
+  *out = c;
+  return ADG_OK;
+}
+
+int adg_reset(adg_ctx* c) {
+  if (!c) return fail(ADG_E_INVALID, "null context");
+  return reset_device(c);
+}
+
+int adg_step_count(const adg_ctx* c, int64_t* steps) {
+  if (!c || !steps) return fail(ADG_E_INVALID, "null argument");
+  *steps = c->steps;
+  return ADG_OK;
+}
+
+int adg_run(adg_ctx* c, double* d_u, int64_t n_steps, uint32_t flags) {
+  if (!c || !d_u) return fail(ADG_E_INVALID, "null argument");
+  if (n_steps < 0) return fail(ADG_E_INVALID, "n_steps < 0");
+  if (flags & ~(ADG_RUN_GRAPH | ADG_RUN_RECORD | ADG_RUN_CHECK_FINITE)) return fail(ADG_E_INVALID, "unknown flags");
+  if (flags & ADG_RUN_RECORD) return fail(ADG_E_UNSUPPORTED, "adjoint recording is not available in this build");
+  double* cur = d_u;
+  double* other = c->kernel == ADG_KERNEL_FUSED ? c->state2() : nullptr;
+  int64_t left = n_steps;
+  int rc;
+  if ((flags & ADG_RUN_GRAPH) && left >= kGraphSteps) {
+    if (c->graph_u != d_u || !c->graph) {
+      if ((rc = build_graph(c, d_u))) return rc;
+    }
+    while (left >= c->graph_steps) {
+      ADG_HIP(hipGraphLaunch(c->graph, c->stream));
+      left -= c->graph_steps;
+    }
+  }
+  // remaining steps in batches of at most kGraphSteps, each closed by one
+  // counter advance
+  while (left > 0) {
+    const int32_t m = (int32_t)std::min<int64_t>(left, kGraphSteps);
+    for (int32_t i = 0; i < m; ++i)
+      if ((rc = enqueue_step(c, &cur, &other, i, c->stream))) return rc;
+    ADG_HIP(launch_advance((int64_t*)(c->ws + c->L.ctr), m, c->stream));
+    left -= m;
+  }
+  if (cur != d_u)
+    ADG_HIP(hipMemcpyAsync(d_u, cur, 8 * c->L.total_doubles, hipMemcpyDeviceToDevice, c->stream));
+  c->steps += n_steps;
+  if (flags & ADG_RUN_CHECK_FINITE) {
+    int64_t* ctr = (int64_t*)(c->ws + c->L.ctr);
+    ADG_HIP(hipMemsetAsync(ctr + 2, 0, sizeof(int64_t), c->stream));
+    ADG_HIP(launch_check_finite(c->stage_args(), d_u, c->stream));
+    int64_t flag = 0;
+    ADG_HIP(hipMemcpyAsync(&flag, ctr + 2, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+    ADG_HIP(hipStreamSynchronize(c->stream));
+    if (flag) return fail(ADG_E_NONFINITE, "state contains NaN or Inf");
+  }
+  return ADG_OK;
+}
+
+int adg_step(adg_ctx* c, double* d_u) { return adg_run(c, d_u, 1, 0); }
+
+int adg_adjoint(adg_ctx* c, const double* d_cot_uT, double* d_grad_u0, double* h_grad_speed) {
+  (void)d_cot_uT; (void)d_grad_u0; (void)h_grad_speed;
+  if (!c) return fail(ADG_E_INVALID, "null context");
+  return fail(ADG_E_STATE, "adg_adjoint needs a run recorded with ADG_RUN_RECORD");
+}
+
+int adg_error_stats(adg_ctx* c, const double* d_u, const double* d_ref, double* h_out) {
+  if (!c || !d_u || !d_ref || !h_out) return fail(ADG_E_INVALID, "null argument");
+  const int32_t n = (int32_t)c->probs.size();
+  double* part = (double*)(c->ws + c->L.part);
+  double* dout = (double*)(c->ws + c->L.stats_out);
+  ADG_HIP(launch_stats(c->stage_args(), d_u, d_ref, part, (const int32_t*)(c->ws + c->L.first_s), n, dout, c->stream));
+  ADG_HIP(hipMemcpyAsync(h_out, dout, 3 * sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
+  ADG_HIP(hipStreamSynchronize(c->stream));
+  return ADG_OK;
+}
+
+int adg_delay_schedule(const adg_problem* p, int64_t step0, int64_t n_steps, int32_t* h_k) {
+  int rc = validate(p, 1);
+  if (rc) return rc;
+  if (!h_k || step0 < 0 || n_steps < 0) return fail(ADG_E_INVALID, "bad schedule arguments");
+  const int S = rk_stages((int)p->rk);
+  const int64_t P = p->n_elem / p->pe_size;
+  if (P <= 1) return ADG_OK;
+  const int q = q_of(*p);
+  for (int64_t i = 0; i < n_steps; ++i) {
+    const int64_t n = step0 + i;
+    for (int s = 0; s < S; ++s) {
+      const int key = p->delay_granularity == ADG_DELAY_PER_STAGE ? s : 0;
+      for (int64_t b = 0; b < P; ++b) {
+        int k = 0;
+        if (p->scheme != ADG_SCHEME_DG) {
+          k = draw_delay(p->seed, n, key, b, p->delay_threshold, (int)p->n_delays);
+          k = clamp_delay(k, n, q);
+        }
+        h_k[(i * S + s) * P + b] = k;
+      }
+    }
+  }
+  return ADG_OK;
+}
+
+int adg_destroy(adg_ctx* c) {
+  if (!c) return ADG_OK;
+  drop_graph(c);
+  delete c;
+  return ADG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,112 @@
+// Shared host/device definitions of the ADG library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace adg {
+
+constexpr int kMaxNp = 5;     // degree <= 4
+constexpr int kMaxL = 8;      // delays 0..7
+constexpr int kMaxQ = 5;      // AT levels
+constexpr int kBlock = 256;   // threads per workgroup (4 wave64)
+
+enum Phys : int { PHYS_ADV_UPWIND = 0, PHYS_ADV_CENTRAL = 1, PHYS_BURGERS_LLF = 2 };
+enum Rk : int { RK_HEUN = 0, RK_SSP3 = 1, RK_RK4 = 2 };
+enum Scheme : int { SCH_DG = 0, SCH_ADG = 1, SCH_AT = 2 };
+
+__host__ __device__ constexpr int rk_stages(int rk) { return rk == RK_HEUN ? 2 : (rk == RK_SSP3 ? 3 : 4); }
+
+// Division by a run-time invariant 0 < d < 2^31 for dividends n < 2^31 by
+// multiplication (Granlund & Montgomery, PLDI 1994): with l = ceil(log2 d),
+// m = floor(2^(31+l) / d) + 1 and s = 31 + l, q = (n * m) >> s is exact
+// because the rounding excess n (m - 2^s/d) / 2^s < 2^-l <= 1/d.
+struct FastDiv {
+  uint32_t d;
+  uint32_t m;
+  uint32_t s;
+  uint32_t pad;
+};
+
+__host__ __device__ inline uint32_t fast_div(uint32_t n, const FastDiv& f) {
+  return (uint32_t)(((uint64_t)n * (uint64_t)f.m) >> f.s);
+}
+
+inline FastDiv make_fast_div(uint32_t d) {
+  uint32_t l = 0;
+  while ((1ull << l) < d) ++l;
+  FastDiv f;
+  f.d = d;
+  f.m = (uint32_t)(((1ull << (31 + l)) / d) + 1ull);
+  f.s = 31 + l;
+  f.pad = 0;
+  return f;
+}
+
+// Per-problem descriptor, resident in the device workspace and read with
+// uniform (scalar) loads by every workgroup of that problem.
+struct DevProblem {
+  int64_t n_elem;        // N_E
+  int64_t pe_size;       // elements per PE
+  int64_t n_pe;          // P (1: no PE faces)
+  int64_t ld;            // plane stride of the state
+  int64_t u_off;         // offset of the problem in the state vector
+  int64_t ring_off;      // offset of the problem's delay ring (doubles)
+  int32_t np;            // degree + 1
+  int32_t q;             // AT levels (1 for ADG)
+  int32_t n_delays;      // L
+  int32_t depth;         // ring slots per (boundary, stage): L + q - 1
+  int32_t per_stage;     // delay key includes the stage
+  int32_t scheme;        // Scheme
+  int32_t async_faces;   // 1 if PE faces use delayed data (scheme != DG and P > 1)
+  int32_t pad0;
+  FastDiv pe_div;        // division by pe_size
+  uint64_t seed;
+  uint64_t thr[kMaxL - 1];
+  double two_over_dx;
+  double speed;
+  double dt;
+  double half_dx;
+  double D[kMaxNp * kMaxNp];   // M^-1 S, row major
+  double lift_l[kMaxNp];       // M^-1 phi(-1)
+  double lift_r[kMaxNp];       // M^-1 phi(+1)
+  double wq[kMaxNp];           // M 1 (quadrature weights)
+  double atc[kMaxL][kMaxQ];    // c_j(k), j < q, k < L
+};
+
+struct WorkItem {
+  int32_t prob;
+  int32_t tile;
+};
+
+// SplitMix64 output function for state x (Steele, Lea & Flood 2014; the
+// variant-13 finaliser of the public-domain reference generator).
+__host__ __device__ inline uint64_t splitmix64(uint64_t x) {
+  uint64_t z = x + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Delay drawn for (seed, step, stage key, boundary), before clamping:
+// number of thresholds at or below the 53-bit uniform h >> 11.
+__host__ __device__ inline int draw_delay(uint64_t seed, int64_t step, int32_t key, int64_t boundary,
+                                          const uint64_t* thr, int n_delays) {
+  uint64_t h = splitmix64(seed);
+  h = splitmix64(h ^ (uint64_t)step);
+  h = splitmix64(h ^ (uint64_t)(int64_t)key);
+  h = splitmix64(h ^ (uint64_t)boundary);
+  const uint64_t u = h >> 11;
+  int k = 0;
+  for (int i = 0; i < n_delays - 1; ++i) k += (u >= thr[i]) ? 1 : 0;
+  return k;
+}
+
+// Usable delay: every level n-k-j, j < q, must exist.
+__host__ __device__ inline int clamp_delay(int k, int64_t step, int q) {
+  int64_t lim = step - q + 1;
+  if (lim < 0) lim = 0;
+  return (int64_t)k < lim ? k : (int)lim;
+}
+
+}  // namespace adg

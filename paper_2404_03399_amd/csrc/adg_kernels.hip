@@ -1,0 +1,548 @@
+// HIP kernels (gfx950, FP64) of the asynchronous DG stepper with AT fluxes.
+//
+// Element update of the reference-element weak form (paper Sec. 2):
+//   du^e/dt = (2/dx) ( D f(u^e) + l_l F_e - l_r F_{e+1} ),  D = M^-1 S,
+//   l_l = M^-1 phi(-1), l_r = M^-1 phi(1),
+// with one numerical flux per face shared by both neighbours (conservation,
+// Sec. 4.1).  At PE faces the flux is the AT combination of delayed levels
+// (Sec. 5): F = sum_{j<q} c_j(k) F^{n-k-j}, read from a per-(boundary, stage)
+// ring of past face fluxes.
+//
+// Layout: structure of arrays, u[off + j*ld + e]; lane = element, so every
+// node-plane load/store of a wave64 is one contiguous 512-byte segment.
+// Neighbour traces come through LDS (fused kernel) or through the cache
+// from the neighbouring lanes' own loads (stage kernel).  No MFMA: the
+// per-element operators are at most 5x5.
+#include "adg_launch.hpp"
+
+namespace adg {
+
+// ---------------------------------------------------------------- physics ---
+template <int PHYS>
+struct Physics;
+
+template <>
+struct Physics<PHYS_ADV_UPWIND> {
+  __device__ static double f(double u, double a) { return a * u; }
+  __device__ static double fhat(double um, double up, double a) { return a >= 0.0 ? a * um : a * up; }
+};
+
+template <>
+struct Physics<PHYS_ADV_CENTRAL> {
+  __device__ static double f(double u, double a) { return a * u; }
+  __device__ static double fhat(double um, double up, double a) { return a * (0.5 * um + 0.5 * up); }
+};
+
+template <>
+struct Physics<PHYS_BURGERS_LLF> {
+  __device__ static double f(double u, double) { return 0.5 * u * u; }
+  __device__ static double fhat(double um, double up, double) {
+    const double lam = fmax(fabs(um), fabs(up));
+    return 0.5 * (0.5 * um * um + 0.5 * up * up) - 0.5 * lam * (up - um);
+  }
+};
+
+// ------------------------------------------------------- PE-face AT flux ---
+// Slot of level n - back (0 <= back < depth) given slot_n = n mod depth.
+__device__ __forceinline__ int ring_slot(int slot_n, int back, int depth) {
+  const int s = slot_n - back;
+  return s < 0 ? s + depth : s;
+}
+
+// Clamped delay of boundary b at (step n, stage s).
+__device__ __forceinline__ int pe_delay(const DevProblem& P, int64_t n, int s, uint32_t b) {
+  const int key = P.per_stage ? s : 0;
+  return clamp_delay(draw_delay(P.seed, n, key, (int64_t)b, P.thr, P.n_delays), n, P.q);
+}
+
+// sum_{j<q} c_j(k) F^{n-k-j} over the ring of (boundary, stage); k >= 1, so
+// every level is a past one.
+__device__ __forceinline__ double at_past_sum(const DevProblem& P, const double* __restrict__ r, int k,
+                                              int slot_n) {
+  double acc = 0.0;
+  for (int j = 0; j < P.q; ++j) acc += P.atc[k][j] * r[ring_slot(slot_n, k + j, P.depth)];
+  return acc;
+}
+
+// (2/dx) ( D f(y) + l_l fl - l_r fr ) with the operators held in registers.
+template <int NP, int PHYS>
+__device__ __forceinline__ void element_rhs(const double (&Dm)[NP][NP], const double (&ll)[NP],
+                                            const double (&lr)[NP], double two_dx, double a,
+                                            const double (&y)[NP], double fl, double fr, double (&k)[NP]) {
+  double fy[NP];
+#pragma unroll
+  for (int j = 0; j < NP; ++j) fy[j] = Physics<PHYS>::f(y[j], a);
+#pragma unroll
+  for (int i = 0; i < NP; ++i) {
+    double v = 0.0;
+#pragma unroll
+    for (int j = 0; j < NP; ++j) v += Dm[i][j] * fy[j];
+    k[i] = two_dx * (v + ll[i] * fl - lr[i] * fr);
+  }
+}
+
+template <int NP>
+__device__ __forceinline__ void load_operators(const DevProblem& P, double (&Dm)[NP][NP], double (&ll)[NP],
+                                               double (&lr)[NP]) {
+#pragma unroll
+  for (int i = 0; i < NP; ++i) {
+#pragma unroll
+    for (int j = 0; j < NP; ++j) Dm[i][j] = P.D[i * kMaxNp + j];
+    ll[i] = P.lift_l[i];
+    lr[i] = P.lift_r[i];
+  }
+}
+
+// RK update after the stage-s operator value k (oracle's algebraic forms).
+// u0: u^n; y: stage input (in) -> next stage input or u^{n+1} (out);
+// ks: RK4 running sum k1 + 2k2 + 2k3, Heun k1 = dt L(u^n).
+template <int NP, int RK>
+__device__ __forceinline__ void rk_update(int s, double dt, const double (&u0)[NP], double (&y)[NP],
+                                          double (&ks)[NP], const double (&k)[NP]) {
+  if constexpr (RK == RK_RK4) {
+    if (s == 0) {
+#pragma unroll
+      for (int j = 0; j < NP; ++j) { ks[j] = k[j]; y[j] = u0[j] + (0.5 * dt) * k[j]; }
+    } else if (s == 1) {
+#pragma unroll
+      for (int j = 0; j < NP; ++j) { ks[j] = ks[j] + 2.0 * k[j]; y[j] = u0[j] + (0.5 * dt) * k[j]; }
+    } else if (s == 2) {
+#pragma unroll
+      for (int j = 0; j < NP; ++j) { ks[j] = ks[j] + 2.0 * k[j]; y[j] = u0[j] + dt * k[j]; }
+    } else {
+#pragma unroll
+      for (int j = 0; j < NP; ++j) y[j] = u0[j] + (dt / 6.0) * (ks[j] + k[j]);
+    }
+  } else if constexpr (RK == RK_SSP3) {
+    if (s == 0) {
+#pragma unroll
+      for (int j = 0; j < NP; ++j) y[j] = u0[j] + dt * k[j];
+    } else if (s == 1) {
+#pragma unroll
+      for (int j = 0; j < NP; ++j) y[j] = 0.75 * u0[j] + 0.25 * (y[j] + dt * k[j]);
+    } else {
+#pragma unroll
+      for (int j = 0; j < NP; ++j) y[j] = u0[j] / 3.0 + (2.0 / 3.0) * (y[j] + dt * k[j]);
+    }
+  } else {  // Heun
+    if (s == 0) {
+#pragma unroll
+      for (int j = 0; j < NP; ++j) { ks[j] = dt * k[j]; y[j] = u0[j] + ks[j]; }
+    } else {
+#pragma unroll
+      for (int j = 0; j < NP; ++j) y[j] = u0[j] + 0.5 * (ks[j] + dt * k[j]);
+    }
+  }
+}
+
+// The absolute step index of a launch is ctr[0] + step_offset: launches of
+// one batch (or one captured graph) carry offsets 0, 1, 2, ... and a single
+// k_advance at the end of the batch adds the batch length to ctr[0].  No
+// workgroup ever writes the counter while others read it.
+__global__ void k_advance(int64_t* __restrict__ ctr, int64_t n_steps) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) ctr[0] = ctr[0] + n_steps;
+}
+
+// Element index of virtual position x on the periodic mesh of N elements.
+__device__ __forceinline__ int wrap_elem(int x, int N) {
+  while (x < 0) x += N;
+  while (x >= N) x -= N;
+  return x;
+}
+
+// ------------------------------------------------------ fused step kernel ---
+constexpr int kMaxStages = 4;
+
+struct FusedSmem {
+  double tr[2][2][kBlock];             // stage traces, double buffered: [buf][first|last][lane]
+  double pef[kMaxStages][kBlock];      // AT sum of past levels at the left face of lane t
+  unsigned char pek[kMaxStages][kBlock];  // 1: delayed (use pef), 0: synchronous
+};
+
+// One workgroup = T owned elements plus H = S halo elements per side, one
+// element per lane.  Each stage shrinks the valid range by one element per
+// side; after S stages the owned elements are exact.  Halo values are
+// recomputed with the same instructions as by their owners, so a shared face
+// gets bitwise-identical fluxes on both sides.  Delays and the AT sums over
+// past levels only depend on earlier steps, so they are computed in a
+// prologue that overlaps the state loads.
+template <int NP, int RK, int PHYS>
+__device__ __forceinline__ void fused_tile(const DevProblem& P, int tile, const double* __restrict__ uin,
+                                           double* __restrict__ uout, double* __restrict__ ring, int64_t n,
+                                           FusedSmem& sm) {
+  constexpr int S = rk_stages(RK);
+  constexpr int H = S;
+  constexpr int T = kBlock - 2 * H;
+  const int t = threadIdx.x;
+  const int N = (int)P.n_elem;
+  const int e0 = tile * T;
+  const int teff = (N - e0) < T ? (N - e0) : T;
+  const bool active = t < teff + 2 * H;
+  const bool owned = t >= H && t < H + teff;
+  const int e = wrap_elem(e0 - H + t, N);
+  const int64_t ld = P.ld;
+  const double* __restrict__ u = uin + P.u_off;
+  const double a = P.speed;
+  const double dt = P.dt;
+  const double two_dx = P.two_over_dx;
+
+  double u0[NP], y[NP], ks[NP], k[NP];
+#pragma unroll
+  for (int j = 0; j < NP; ++j) u0[j] = active ? u[j * ld + e] : 0.0;
+
+  double Dm[NP][NP], ll[NP], lr[NP];
+  load_operators<NP>(P, Dm, ll, lr);
+
+  bool pe_left = false, pe_right = false;
+  uint32_t b_left = 0;
+  int slot_n = 0;
+  const double* rbase = ring;
+  if (P.async_faces) {
+    const uint32_t pes = P.pe_div.d;
+    b_left = fast_div((uint32_t)e, P.pe_div);
+    pe_left = active && ((uint32_t)e == b_left * pes);
+    const uint32_t e1 = (e + 1 == N) ? 0u : (uint32_t)(e + 1);
+    pe_right = active && (e1 == fast_div(e1, P.pe_div) * pes);
+    slot_n = (int)(n % (int64_t)P.depth);
+    rbase = ring + P.ring_off + (int64_t)b_left * S * P.depth;
+    if (pe_left) {
+      int kd = 0;
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        if (s == 0 || P.per_stage) kd = pe_delay(P, n, s, b_left);
+        sm.pek[s][t] = kd > 0 ? 1 : 0;
+        if (kd > 0) sm.pef[s][t] = at_past_sum(P, rbase + s * P.depth, kd, slot_n);
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < NP; ++j) y[j] = u0[j];
+
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    double(&tr)[2][kBlock] = sm.tr[s & 1];
+    tr[0][t] = y[0];
+    tr[1][t] = y[NP - 1];
+    __syncthreads();
+    const double um = t > 0 ? tr[1][t - 1] : y[0];
+    const double upr = t < kBlock - 1 ? tr[0][t + 1] : y[NP - 1];
+    double fl = Physics<PHYS>::fhat(um, y[0], a);
+    double fr = Physics<PHYS>::fhat(y[NP - 1], upr, a);
+    if (pe_left) {
+      if (owned) ring[P.ring_off + ((int64_t)b_left * S + s) * P.depth + slot_n] = fl;
+      if (sm.pek[s][t]) fl = sm.pef[s][t];
+    }
+    if (pe_right && t + 1 < kBlock) {
+      if (sm.pek[s][t + 1]) fr = sm.pef[s][t + 1];
+    }
+    element_rhs<NP, PHYS>(Dm, ll, lr, two_dx, a, y, fl, fr, k);
+    rk_update<NP, RK>(s, dt, u0, y, ks, k);
+  }
+  if (owned) {
+    double* __restrict__ uo = uout + P.u_off;
+#pragma unroll
+    for (int j = 0; j < NP; ++j) uo[j * ld + e] = y[j];
+  }
+}
+
+template <int RK, int PHYS>
+__global__ __launch_bounds__(kBlock) void k_fused_step(const DevProblem* __restrict__ probs,
+                                                       const WorkItem* __restrict__ work,
+                                                       const double* __restrict__ uin, double* __restrict__ uout,
+                                                       double* __restrict__ ring, const int64_t* __restrict__ ctr,
+                                                       int32_t step_offset) {
+  __shared__ FusedSmem sm;
+  const WorkItem wi = work[blockIdx.x];
+  const DevProblem& P = probs[wi.prob];
+  const int64_t n = ctr[0] + step_offset;
+  switch (P.np) {
+    case 2: fused_tile<2, RK, PHYS>(P, wi.tile, uin, uout, ring, n, sm); break;
+    case 3: fused_tile<3, RK, PHYS>(P, wi.tile, uin, uout, ring, n, sm); break;
+    case 4: fused_tile<4, RK, PHYS>(P, wi.tile, uin, uout, ring, n, sm); break;
+    default: fused_tile<5, RK, PHYS>(P, wi.tile, uin, uout, ring, n, sm); break;
+  }
+}
+
+// ------------------------------------------------------ per-stage kernel ---
+// One lane per element; the neighbours' traces are read from global memory
+// (the same cache lines the neighbouring lanes load).  RK registers in HBM:
+//   RK4:     A = k1 + 2k2 + 2k3 (accumulated), Y = next stage input
+//   SSP-RK3: Y = u1, then u2
+//   Heun:    A = k1 = dt L(u), Y = u + k1
+template <int NP, int RK, int PHYS, int SI>
+__device__ __forceinline__ void stage_elem(const DevProblem& P, int tile, const double* __restrict__ yin,
+                                           double* __restrict__ yout, double* __restrict__ U,
+                                           double* __restrict__ A, double* __restrict__ ring, int64_t n) {
+  constexpr int S = rk_stages(RK);
+  const int N = (int)P.n_elem;
+  const int e = tile * kBlock + (int)threadIdx.x;
+  if (e >= N) return;
+  const int64_t ld = P.ld;
+  const int64_t off = P.u_off;
+  const double a = P.speed;
+  const double dt = P.dt;
+  const int em = e == 0 ? N - 1 : e - 1;
+  const int e1 = e + 1 == N ? 0 : e + 1;
+  double Dm[NP][NP], ll[NP], lr[NP];
+  load_operators<NP>(P, Dm, ll, lr);
+  double y[NP], k[NP];
+#pragma unroll
+  for (int j = 0; j < NP; ++j) y[j] = yin[off + j * ld + e];
+  const double um = yin[off + (NP - 1) * ld + em];
+  const double upr = yin[off + e1];
+  double fl = Physics<PHYS>::fhat(um, y[0], a);
+  double fr = Physics<PHYS>::fhat(y[NP - 1], upr, a);
+  if (P.async_faces) {
+    const uint32_t pes = P.pe_div.d;
+    const int slot_n = (int)(n % (int64_t)P.depth);
+    const uint32_t bl = fast_div((uint32_t)e, P.pe_div);
+    if ((uint32_t)e == bl * pes) {
+      const double* r = ring + P.ring_off + ((int64_t)bl * S + SI) * P.depth;
+      const int kd = pe_delay(P, n, SI, bl);
+      ring[P.ring_off + ((int64_t)bl * S + SI) * P.depth + slot_n] = fl;
+      if (kd > 0) fl = at_past_sum(P, r, kd, slot_n);
+    }
+    const uint32_t br = fast_div((uint32_t)e1, P.pe_div);
+    if ((uint32_t)e1 == br * pes) {
+      const double* r = ring + P.ring_off + ((int64_t)br * S + SI) * P.depth;
+      const int kd = pe_delay(P, n, SI, br);
+      if (kd > 0) fr = at_past_sum(P, r, kd, slot_n);
+    }
+  }
+  element_rhs<NP, PHYS>(Dm, ll, lr, P.two_over_dx, a, y, fl, fr, k);
+
+  double* __restrict__ Uo = U + off;
+  double* __restrict__ Ao = A + off;
+  double* __restrict__ Yo = yout + off;
+  if constexpr (RK == RK_RK4) {
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+      const int64_t i = j * ld + e;
+      if constexpr (SI == 0) {
+        Ao[i] = k[j];
+        Yo[i] = y[j] + (0.5 * dt) * k[j];  // stage-0 input is u
+      } else if constexpr (SI == 1) {
+        Ao[i] = Ao[i] + 2.0 * k[j];
+        Yo[i] = Uo[i] + (0.5 * dt) * k[j];
+      } else if constexpr (SI == 2) {
+        Ao[i] = Ao[i] + 2.0 * k[j];
+        Yo[i] = Uo[i] + dt * k[j];
+      } else {
+        Uo[i] = Uo[i] + (dt / 6.0) * (Ao[i] + k[j]);
+      }
+    }
+  } else if constexpr (RK == RK_SSP3) {
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+      const int64_t i = j * ld + e;
+      if constexpr (SI == 0) {
+        Yo[i] = y[j] + dt * k[j];
+      } else if constexpr (SI == 1) {
+        Yo[i] = 0.75 * Uo[i] + 0.25 * (y[j] + dt * k[j]);
+      } else {
+        Uo[i] = Uo[i] / 3.0 + (2.0 / 3.0) * (y[j] + dt * k[j]);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+      const int64_t i = j * ld + e;
+      if constexpr (SI == 0) {
+        const double k1 = dt * k[j];
+        Ao[i] = k1;
+        Yo[i] = y[j] + k1;
+      } else {
+        Uo[i] = Uo[i] + 0.5 * (Ao[i] + dt * k[j]);
+      }
+    }
+  }
+}
+
+template <int RK, int PHYS, int SI>
+__global__ __launch_bounds__(kBlock) void k_stage(const DevProblem* __restrict__ probs,
+                                                  const WorkItem* __restrict__ work, const double* yin,
+                                                  double* yout, double* U, double* A, double* __restrict__ ring,
+                                                  const int64_t* __restrict__ ctr, int32_t step_offset) {
+  const WorkItem wi = work[blockIdx.x];
+  const DevProblem& P = probs[wi.prob];
+  const int64_t n = ctr[0] + step_offset;
+  switch (P.np) {
+    case 2: stage_elem<2, RK, PHYS, SI>(P, wi.tile, yin, yout, U, A, ring, n); break;
+    case 3: stage_elem<3, RK, PHYS, SI>(P, wi.tile, yin, yout, U, A, ring, n); break;
+    case 4: stage_elem<4, RK, PHYS, SI>(P, wi.tile, yin, yout, U, A, ring, n); break;
+    default: stage_elem<5, RK, PHYS, SI>(P, wi.tile, yin, yout, U, A, ring, n); break;
+  }
+}
+
+// ----------------------------------------------------------- statistics ---
+__global__ __launch_bounds__(kBlock) void k_stats_partial(const DevProblem* __restrict__ probs,
+                                                          const WorkItem* __restrict__ work,
+                                                          const double* __restrict__ u,
+                                                          const double* __restrict__ ref,
+                                                          double* __restrict__ part) {
+  __shared__ double red[3][kBlock];
+  const WorkItem wi = work[blockIdx.x];
+  const DevProblem& P = probs[wi.prob];
+  const int64_t e = (int64_t)wi.tile * kBlock + threadIdx.x;
+  double sabs = 0.0, mabs = 0.0, integ = 0.0;
+  if (e < P.n_elem) {
+    for (int j = 0; j < P.np; ++j) {
+      const int64_t i = P.u_off + j * P.ld + e;
+      const double d = fabs(u[i] - ref[i]);
+      sabs += d;
+      mabs = fmax(mabs, d);
+      integ += P.wq[j] * u[i];
+    }
+  }
+  red[0][threadIdx.x] = sabs;
+  red[1][threadIdx.x] = mabs;
+  red[2][threadIdx.x] = integ;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + w];
+      red[1][threadIdx.x] = fmax(red[1][threadIdx.x], red[1][threadIdx.x + w]);
+      red[2][threadIdx.x] += red[2][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[3 * blockIdx.x + 0] = red[0][0];
+    part[3 * blockIdx.x + 1] = red[1][0];
+    part[3 * blockIdx.x + 2] = red[2][0];
+  }
+}
+
+// One workgroup per problem: lane l sums items first+l, first+l+256, ... in
+// order, then a fixed tree.
+__global__ __launch_bounds__(kBlock) void k_stats_final(const DevProblem* __restrict__ probs,
+                                                        const int32_t* __restrict__ first_item,
+                                                        const double* __restrict__ part, double* __restrict__ out) {
+  __shared__ double red[3][kBlock];
+  const int p = blockIdx.x;
+  const DevProblem& P = probs[p];
+  const int32_t i0 = first_item[p], i1 = first_item[p + 1];
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  for (int32_t i = i0 + threadIdx.x; i < i1; i += kBlock) {
+    s0 += part[3 * i];
+    s1 = fmax(s1, part[3 * i + 1]);
+    s2 += part[3 * i + 2];
+  }
+  red[0][threadIdx.x] = s0;
+  red[1][threadIdx.x] = s1;
+  red[2][threadIdx.x] = s2;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + w];
+      red[1][threadIdx.x] = fmax(red[1][threadIdx.x], red[1][threadIdx.x + w]);
+      red[2][threadIdx.x] += red[2][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[3 * p + 0] = red[0][0] / (double)(P.n_elem * P.np);
+    out[3 * p + 1] = red[1][0];
+    out[3 * p + 2] = P.half_dx * red[2][0];
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_check_finite(const DevProblem* __restrict__ probs,
+                                                         const WorkItem* __restrict__ work,
+                                                         const double* __restrict__ u, int64_t* __restrict__ ctr) {
+  const WorkItem wi = work[blockIdx.x];
+  const DevProblem& P = probs[wi.prob];
+  const int64_t e = (int64_t)wi.tile * kBlock + threadIdx.x;
+  if (e >= P.n_elem) return;
+  bool bad = false;
+  for (int j = 0; j < P.np; ++j) bad |= !isfinite(u[P.u_off + j * P.ld + e]);
+  if (bad) ctr[2] = 1;
+}
+
+// ---------------------------------------------------------------- launch ---
+template <int RK>
+static hipError_t fused_phys(int phys, const StepArgs& a, const double* uin, double* uout, int32_t off,
+                             hipStream_t st) {
+  const dim3 g(a.n_work), b(kBlock);
+  switch (phys) {
+    case PHYS_ADV_UPWIND:
+      hipLaunchKernelGGL((k_fused_step<RK, PHYS_ADV_UPWIND>), g, b, 0, st, a.probs, a.work, uin, uout, a.ring, a.ctr,
+                         off);
+      break;
+    case PHYS_ADV_CENTRAL:
+      hipLaunchKernelGGL((k_fused_step<RK, PHYS_ADV_CENTRAL>), g, b, 0, st, a.probs, a.work, uin, uout, a.ring, a.ctr,
+                         off);
+      break;
+    default:
+      hipLaunchKernelGGL((k_fused_step<RK, PHYS_BURGERS_LLF>), g, b, 0, st, a.probs, a.work, uin, uout, a.ring, a.ctr,
+                         off);
+      break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_fused_step(int rk, int phys, const StepArgs& a, const double* uin, double* uout, int32_t step_offset,
+                             hipStream_t stream) {
+  switch (rk) {
+    case RK_HEUN: return fused_phys<RK_HEUN>(phys, a, uin, uout, step_offset, stream);
+    case RK_SSP3: return fused_phys<RK_SSP3>(phys, a, uin, uout, step_offset, stream);
+    default: return fused_phys<RK_RK4>(phys, a, uin, uout, step_offset, stream);
+  }
+}
+
+template <int RK, int PHYS, int SI>
+static void stage_go(const StepArgs& a, const double* yin, double* yout, double* U, double* A, int32_t off,
+                     hipStream_t st) {
+  hipLaunchKernelGGL((k_stage<RK, PHYS, SI>), dim3(a.n_work), dim3(kBlock), 0, st, a.probs, a.work, yin, yout, U, A,
+                     a.ring, a.ctr, off);
+}
+
+template <int RK, int PHYS>
+static void stage_si(int si, const StepArgs& a, const double* yin, double* yout, double* U, double* A, int32_t off,
+                     hipStream_t st) {
+  switch (si) {
+    case 0: stage_go<RK, PHYS, 0>(a, yin, yout, U, A, off, st); break;
+    case 1: stage_go<RK, PHYS, 1>(a, yin, yout, U, A, off, st); break;
+    case 2: if constexpr (rk_stages(RK) > 2) stage_go<RK, PHYS, 2>(a, yin, yout, U, A, off, st); break;
+    default: if constexpr (rk_stages(RK) > 3) stage_go<RK, PHYS, 3>(a, yin, yout, U, A, off, st); break;
+  }
+}
+
+template <int RK>
+static void stage_phys(int phys, int si, const StepArgs& a, const double* yin, double* yout, double* U, double* A,
+                       int32_t off, hipStream_t st) {
+  switch (phys) {
+    case PHYS_ADV_UPWIND: stage_si<RK, PHYS_ADV_UPWIND>(si, a, yin, yout, U, A, off, st); break;
+    case PHYS_ADV_CENTRAL: stage_si<RK, PHYS_ADV_CENTRAL>(si, a, yin, yout, U, A, off, st); break;
+    default: stage_si<RK, PHYS_BURGERS_LLF>(si, a, yin, yout, U, A, off, st); break;
+  }
+}
+
+hipError_t launch_stage(int rk, int phys, int stage, const StepArgs& a, const double* yin, double* yout, double* U,
+                        double* A, int32_t step_offset, hipStream_t stream) {
+  switch (rk) {
+    case RK_HEUN: stage_phys<RK_HEUN>(phys, stage, a, yin, yout, U, A, step_offset, stream); break;
+    case RK_SSP3: stage_phys<RK_SSP3>(phys, stage, a, yin, yout, U, A, step_offset, stream); break;
+    default: stage_phys<RK_RK4>(phys, stage, a, yin, yout, U, A, step_offset, stream); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_advance(int64_t* ctr, int64_t n_steps, hipStream_t stream) {
+  hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, stream, ctr, n_steps);
+  return hipGetLastError();
+}
+
+hipError_t launch_stats(const StepArgs& a, const double* u, const double* ref, double* partials,
+                        const int32_t* first_item, int32_t n_probs, double* out, hipStream_t stream) {
+  hipLaunchKernelGGL(k_stats_partial, dim3(a.n_work), dim3(kBlock), 0, stream, a.probs, a.work, u, ref, partials);
+  hipLaunchKernelGGL(k_stats_final, dim3(n_probs), dim3(kBlock), 0, stream, a.probs, first_item, partials, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_finite(const StepArgs& a, const double* u, hipStream_t stream) {
+  hipLaunchKernelGGL(k_check_finite, dim3(a.n_work), dim3(kBlock), 0, stream, a.probs, a.work, u, a.ctr);
+  return hipGetLastError();
+}
+
+}  // namespace adg

@@ -1,0 +1,40 @@
+// Internal launch interface between the C ABI layer and the HIP kernels.
+#pragma once
+
+#include "adg_common.hpp"
+
+namespace adg {
+
+struct StepArgs {
+  const DevProblem* probs;   // device descriptors
+  const WorkItem* work;      // device work list, one item per workgroup
+  int32_t n_work;
+  double* ring;              // delay ring (fluxes), may be null when no PE faces
+  int64_t* ctr;              // ctr[0] = steps completed by earlier batches, ctr[2] = non-finite flag
+};
+
+// Owned elements per workgroup of the fused step kernel for an RK scheme.
+inline int fused_tile(int rk) { return kBlock - 2 * rk_stages(rk); }
+
+// One full RK step, all stages on chip: state uin -> uout (distinct buffers).
+// The step index is ctr[0] + step_offset.
+hipError_t launch_fused_step(int rk, int phys, const StepArgs& a, const double* uin, double* uout,
+                             int32_t step_offset, hipStream_t stream);
+
+// One RK stage with the RK registers in HBM.  Stage 0 reads its input from U;
+// the last stage writes U in place.  yin/yout alternate between two buffers.
+hipError_t launch_stage(int rk, int phys, int stage, const StepArgs& a, const double* yin, double* yout,
+                        double* U, double* A, int32_t step_offset, hipStream_t stream);
+
+// ctr[0] += n_steps (one lane), closing a batch of launches.
+hipError_t launch_advance(int64_t* ctr, int64_t n_steps, hipStream_t stream);
+
+// Per-workgroup partial error sums (work list with kBlock elements per item),
+// then per-problem reduction in a fixed order.
+hipError_t launch_stats(const StepArgs& a, const double* u, const double* ref, double* partials,
+                        const int32_t* first_item, int32_t n_probs, double* out, hipStream_t stream);
+
+// Sets ctr[2] = 1 if any owned state entry is NaN or Inf.
+hipError_t launch_check_finite(const StepArgs& a, const double* u, hipStream_t stream);
+
+}  // namespace adg

@@ -1,0 +1,161 @@
+"""PyTorch plumbing around the C ABI: device memory, streams, state packing.
+
+torch supplies the device buffers (state, workspace) and the current HIP
+stream; all arithmetic of the method runs in libadg's kernels.
+"""
+from __future__ import annotations
+
+import math
+from fractions import Fraction
+from typing import List, Sequence
+
+import numpy as np
+import torch
+
+from . import adg
+
+
+def delay_thresholds(probs: Sequence) -> List[int]:
+    """Bin edges T_k = floor(2^53 (p_0 + ... + p_{k-1})), k = 1..L-1, from exact
+    decimal/rational probabilities (delay = number of edges <= the uniform)."""
+    ps = [Fraction(p) for p in probs]
+    if any(p < 0 for p in ps) or sum(ps) != 1:
+        raise ValueError("delay probabilities must be >= 0 and sum to 1")
+    out, acc = [], Fraction(0)
+    for p in ps[:-1]:
+        acc += p
+        out.append(math.floor(acc * (1 << 53)))
+    return out
+
+
+def to_problem(w) -> adg.adg_problem:
+    """C descriptor of a workloads.Workload."""
+    p = adg.adg_problem()
+    p.abi_version = adg.ADG_ABI_VERSION
+    p.equation = adg.EQUATION[w.equation]
+    p.scheme = adg.SCHEME[w.scheme]
+    p.flux = adg.FLUX[w.flux]
+    p.rk = adg.RK[w.rk]
+    p.degree = w.degree
+    p.at_levels = w.at_levels if w.scheme == "adg_at" else 0
+    p.n_delays = len(w.probs)
+    p.delay_granularity = 1 if w.per_stage else 0
+    p.reserved = 0
+    p.n_elem = w.n_elem
+    p.pe_size = w.pe_size
+    p.seed = w.seed & ((1 << 64) - 1)
+    thr = delay_thresholds(w.probs)
+    for i, t in enumerate(thr):
+        p.delay_threshold[i] = t
+    p.x_left = w.x_left
+    p.length = w.length
+    p.speed = w.speed
+    p.dt = w.dt
+    return p
+
+
+def _stream_handle(stream) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+class Solver:
+    """One context over one or more problems (batched when more than one)."""
+
+    def __init__(self, workloads, kernel: str = "fused", n_steps_record: int = 0, ckpt_every: int = 0,
+                 device: str = "cuda", stream=None):
+        if not isinstance(workloads, (list, tuple)):
+            workloads = [workloads]
+        self.workloads = list(workloads)
+        self.probs = [to_problem(w) for w in self.workloads]
+        self.offsets, self.lds, self.total = adg.adg_state_layout(self.probs)
+        self.opt = adg.adg_options()
+        self.opt.kernel = adg.KERNEL[kernel]
+        self.opt.ckpt_every = ckpt_every
+        self.device = torch.device(device)
+        self.ws_bytes = adg.adg_workspace_size(self.probs, self.opt, n_steps_record)
+        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream
+        self.ctx = adg.adg_init(self.probs, self.opt, n_steps_record, self.workspace.data_ptr(),
+                                self.ws_bytes, _stream_handle(stream))
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None:
+            adg.adg_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- state packing ---------------------------------------------------
+    def empty_state(self) -> torch.Tensor:
+        return torch.zeros(self.total, dtype=torch.float64, device=self.device)
+
+    def pack(self, arrays) -> torch.Tensor:
+        """Per-problem (n_elem, degree+1) arrays -> device state vector."""
+        if not isinstance(arrays, (list, tuple)):
+            arrays = [arrays]
+        host = np.zeros(self.total, dtype=np.float64)
+        for w, off, ld, a in zip(self.workloads, self.offsets, self.lds, arrays):
+            a = np.asarray(a, dtype=np.float64)
+            view = host[off:off + ld * (w.degree + 1)].reshape(w.degree + 1, ld)
+            view[:, :w.n_elem] = a.T
+        return torch.from_numpy(host).to(self.device)
+
+    def view(self, u: torch.Tensor, i: int = 0) -> torch.Tensor:
+        """(degree+1, n_elem) view of problem i inside the state vector."""
+        w = self.workloads[i]
+        off, ld = self.offsets[i], self.lds[i]
+        return u[off:off + ld * (w.degree + 1)].view(w.degree + 1, ld)[:, :w.n_elem]
+
+    def unpack(self, u: torch.Tensor):
+        host = u.detach().cpu().numpy()
+        out = []
+        for w, off, ld in zip(self.workloads, self.offsets, self.lds):
+            out.append(host[off:off + ld * (w.degree + 1)].reshape(w.degree + 1, ld)[:, :w.n_elem].T.copy())
+        return out
+
+    def nodes(self, i: int = 0) -> torch.Tensor:
+        """Physical node coordinates of problem i, (degree+1, n_elem), on the device."""
+        w = self.workloads[i]
+        xi = torch.tensor(adg.adg_nodes(w.degree), dtype=torch.float64, device=self.device)
+        dx = w.length / w.n_elem
+        e = torch.arange(w.n_elem, dtype=torch.float64, device=self.device)
+        return w.x_left + e[None, :] * dx + (xi[:, None] + 1.0) * (dx / 2.0)
+
+    def initial_state(self) -> torch.Tensor:
+        """Nodal interpolation of each workload's multi-sine initial data."""
+        u = self.empty_state()
+        for i, w in enumerate(self.workloads):
+            x = self.nodes(i)
+            v = torch.full_like(x, w.ic.offset)
+            for k, a, ph in zip(w.ic.kappa, w.ic.amp, w.ic.phase):
+                v = v + a * torch.sin(k * x + ph)
+            self.view(u, i).copy_(v)
+        return u
+
+    # ---- stepping ----------------------------------------------------------
+    def reset(self):
+        adg.adg_reset(self.ctx)
+
+    def step(self, u: torch.Tensor):
+        adg.adg_step(self.ctx, u.data_ptr())
+
+    def run(self, u: torch.Tensor, n_steps: int, graph: bool = True, record: bool = False,
+            check_finite: bool = False):
+        flags = (adg.ADG_RUN_GRAPH if graph else 0) | (adg.ADG_RUN_RECORD if record else 0) | \
+                (adg.ADG_RUN_CHECK_FINITE if check_finite else 0)
+        adg.adg_run(self.ctx, u.data_ptr(), n_steps, flags)
+
+    def steps_taken(self) -> int:
+        return adg.adg_step_count(self.ctx)
+
+    def error_stats(self, u: torch.Tensor, ref: torch.Tensor):
+        return adg.adg_error_stats(self.ctx, u.data_ptr(), ref.data_ptr(), len(self.probs))
+
+    def delay_schedule(self, i: int, step0: int, n_steps: int):
+        w = self.workloads[i]
+        return adg.adg_delay_schedule(self.probs[i], step0, n_steps, adg.RK_STAGES[w.rk], w.n_pe)
