@@ -217,10 +217,11 @@ int validate(const adg_problem* probs, int32_t n) {
 }
 
 struct Layout {
-  int64_t probs, work_f, work_s, first_s, ctr, ring, state2, y0, y1, acc, part, stats_out, total;
+  int64_t probs, work_f, work_s, first_s, ctr, ring, atsum, atk, state2, y0, y1, acc, part, stats_out, total;
   int32_t n_work_f, n_work_s;
   int64_t total_doubles;
   int64_t ring_doubles;
+  int64_t at_entries;  // boundaries x 2 parities (x S for the sums)
 };
 
 int kernel_of(const adg_options* opt) {
@@ -232,14 +233,18 @@ Layout make_layout(const adg_problem* probs, int32_t n, const adg_options* opt) 
   Layout L{};
   const int S = rk_stages((int)probs[0].rk);
   const int T = fused_tile((int)probs[0].rk);
-  int64_t nwf = 0, nws = 0, tot = 0, ring = 0;
+  int64_t nwf = 0, nws = 0, tot = 0, ring = 0, at = 0;
   for (int32_t i = 0; i < n; ++i) {
     const adg_problem& p = probs[i];
     nwf += (p.n_elem + T - 1) / T;
     nws += (p.n_elem + kBlock - 1) / kBlock;
     tot += ld_of(p) * (p.degree + 1);
-    if (async_of(p)) ring += (p.n_elem / p.pe_size) * S * (int64_t)(p.n_delays + q_of(p) - 1);
+    if (async_of(p)) {
+      ring += (p.n_elem / p.pe_size) * S * (int64_t)(p.n_delays + q_of(p) - 1);
+      at += 2 * (p.n_elem / p.pe_size);
+    }
   }
+  L.at_entries = at;
   L.n_work_f = (int32_t)nwf;
   L.n_work_s = (int32_t)nws;
   L.total_doubles = tot;
@@ -253,6 +258,8 @@ Layout make_layout(const adg_problem* probs, int32_t n, const adg_options* opt) 
   L.first_s = take((int64_t)sizeof(int32_t) * (n + 1));
   L.ctr = take(8 * sizeof(int64_t));
   L.ring = take(8 * std::max<int64_t>(ring, 1));
+  L.atsum = take(8 * S * std::max<int64_t>(at, 1));
+  L.atk = take(4 * std::max<int64_t>(at, 1));
   L.state2 = kern == ADG_KERNEL_FUSED ? take(8 * tot) : -1;
   L.y0 = kern == ADG_KERNEL_STAGE ? take(8 * tot) : -1;
   L.y1 = kern == ADG_KERNEL_STAGE ? take(8 * tot) : -1;
@@ -280,14 +287,24 @@ struct adg_ctx {
   const double* graph_u = nullptr;
   int graph_steps = 0;
 
-  StepArgs fused_args() const {
-    return StepArgs{(const DevProblem*)(ws + L.probs), (const WorkItem*)(ws + L.work_f), L.n_work_f,
-                    (double*)(ws + L.ring), (int64_t*)(ws + L.ctr)};
+  int32_t group[5] = {0, 0, 0, 0, 0};
+  int32_t grid[4] = {1, 1, 1, 1};
+
+  StepArgs base_args(int64_t work_off, int32_t n_work) const {
+    StepArgs a{};
+    a.probs = (const DevProblem*)(ws + L.probs);
+    a.work = (const WorkItem*)(ws + work_off);
+    a.n_work = n_work;
+    a.ring = (double*)(ws + L.ring);
+    a.ctr = (int64_t*)(ws + L.ctr);
+    a.atsum = (double*)(ws + L.atsum);
+    a.atk = (int32_t*)(ws + L.atk);
+    for (int i = 0; i < 5; ++i) a.group[i] = group[i];
+    for (int i = 0; i < 4; ++i) a.grid[i] = grid[i];
+    return a;
   }
-  StepArgs stage_args() const {
-    return StepArgs{(const DevProblem*)(ws + L.probs), (const WorkItem*)(ws + L.work_s), L.n_work_s,
-                    (double*)(ws + L.ring), (int64_t*)(ws + L.ctr)};
-  }
+  StepArgs fused_args() const { return base_args(L.work_f, L.n_work_f); }
+  StepArgs stage_args() const { return base_args(L.work_s, L.n_work_s); }
   double* state2() const { return (double*)(ws + L.state2); }
 };
 
@@ -318,6 +335,8 @@ int enqueue_step(adg_ctx* c, double** cur, double** other, int32_t step_offset, 
 int reset_device(adg_ctx* c) {
   ADG_HIP(hipMemsetAsync(c->ws + c->L.ctr, 0, 8 * sizeof(int64_t), c->stream));
   ADG_HIP(hipMemsetAsync(c->ws + c->L.ring, 0, 8 * std::max<int64_t>(c->L.ring_doubles, 1), c->stream));
+  ADG_HIP(hipMemsetAsync(c->ws + c->L.atsum, 0, 8 * c->S * std::max<int64_t>(c->L.at_entries, 1), c->stream));
+  ADG_HIP(hipMemsetAsync(c->ws + c->L.atk, 0, 4 * std::max<int64_t>(c->L.at_entries, 1), c->stream));
   c->steps = 0;
   return ADG_OK;
 }
@@ -426,7 +445,7 @@ int adg_init(adg_ctx** out, const adg_problem* probs, int32_t n_probs, const adg
 
   // descriptors
   c->dev.resize(n_probs);
-  int64_t uoff = 0, roff = 0;
+  int64_t uoff = 0, roff = 0, aoff = 0;
   for (int32_t i = 0; i < n_probs; ++i) {
     const adg_problem& p = probs[i];
     DevProblem& d = c->dev[i];
@@ -453,7 +472,12 @@ int adg_init(adg_ctx** out, const adg_problem* probs, int32_t n_probs, const adg
       }
     }
     d.ring_off = roff;
-    if (d.async_faces) roff += d.n_pe * c->S * (int64_t)d.depth;
+    d.at_off = aoff * c->S;
+    d.atk_off = aoff;
+    if (d.async_faces) {
+      roff += d.n_pe * c->S * (int64_t)d.depth;
+      aoff += 2 * d.n_pe;
+    }
     d.seed = p.seed;
     for (int k = 0; k + 1 < d.n_delays; ++k) d.thr[k] = p.delay_threshold[k];
     const double dx = p.length / (double)p.n_elem;
@@ -462,6 +486,14 @@ int adg_init(adg_ctx** out, const adg_problem* probs, int32_t n_probs, const adg
     d.speed = p.equation == ADG_EQ_ADVECTION ? p.speed : 1.0;
     d.dt = p.dt;
     element_operators((int)p.degree, &d);
+    {
+      const double fac = p.equation == ADG_EQ_ADVECTION ? p.speed : 0.5;
+      for (int i = 0; i < kMaxNp * kMaxNp; ++i) d.Kd[i] = d.two_over_dx * fac * d.D[i];
+      for (int i = 0; i < kMaxNp; ++i) {
+        d.Kl[i] = d.two_over_dx * d.lift_l[i];
+        d.Kr[i] = d.two_over_dx * d.lift_r[i];
+      }
+    }
     for (int k = 0; k < d.n_delays; ++k)
       for (int j = 0; j < d.q; ++j) d.atc[k][j] = at_coefficient(d.q, k, j);
   }
@@ -473,10 +505,17 @@ int adg_init(adg_ctx** out, const adg_problem* probs, int32_t n_probs, const adg
   std::vector<WorkItem> wf, ws_;
   std::vector<int32_t> first(n_probs + 1, 0);
   wf.reserve(c->L.n_work_f);
-  for (int32_t i : order) {
-    const int64_t nt = (probs[i].n_elem + T - 1) / T;
-    for (int64_t t = 0; t < nt; ++t) wf.push_back(WorkItem{i, (int32_t)t});
+  // ranges per degree, np = 5, 4, 3, 2 (order is sorted by degree, descending)
+  for (int np = 5, gi = 0; np >= 2; --np, ++gi) {
+    c->group[gi] = (int32_t)wf.size();
+    for (int32_t i : order) {
+      if ((int)probs[i].degree + 1 != np) continue;
+      const int64_t nt = (probs[i].n_elem + T - 1) / T;
+      for (int64_t t = 0; t < nt; ++t) wf.push_back(WorkItem{i, (int32_t)t});
+    }
   }
+  c->group[4] = (int32_t)wf.size();
+  for (int gi = 0; gi < 4; ++gi) c->grid[gi] = fused_grid(c->group[gi + 1] - c->group[gi]);
   for (int32_t i = 0; i < n_probs; ++i) {  // stage/stats list in problem order (contiguous per problem)
     first[i] = (int32_t)ws_.size();
     const int64_t nt = (probs[i].n_elem + kBlock - 1) / kBlock;

@@ -52,6 +52,8 @@ struct DevProblem {
   int64_t ld;            // plane stride of the state
   int64_t u_off;         // offset of the problem in the state vector
   int64_t ring_off;      // offset of the problem's delay ring (doubles)
+  int64_t at_off;        // offset of the problem's AT sums ([2][P][S] doubles)
+  int64_t atk_off;       // offset of the problem's packed delays ([2][P] int32, 3 bits per stage)
   int32_t np;            // degree + 1
   int32_t q;             // AT levels (1 for ADG)
   int32_t n_delays;      // L
@@ -71,6 +73,13 @@ struct DevProblem {
   double lift_l[kMaxNp];       // M^-1 phi(-1)
   double lift_r[kMaxNp];       // M^-1 phi(+1)
   double wq[kMaxNp];           // M 1 (quadrature weights)
+  // Element operator with the metric (2/dx) and the flux constant folded in:
+  //   (2/dx) (D f(y) + l_l fl - l_r fr) = Kd g(y) + Kl fl - Kr fr,
+  // g(y) = y, Kd = (2/dx) a D for advection; g(y) = y^2, Kd = (2/dx) D / 2 for
+  // Burgers; Kl = (2/dx) l_l, Kr = (2/dx) l_r.
+  double Kd[kMaxNp * kMaxNp];
+  double Kl[kMaxNp];
+  double Kr[kMaxNp];
   double atc[kMaxL][kMaxQ];    // c_j(k), j < q, k < L
 };
 
@@ -88,18 +97,28 @@ __host__ __device__ inline uint64_t splitmix64(uint64_t x) {
   return z ^ (z >> 31);
 }
 
-// Delay drawn for (seed, step, stage key, boundary), before clamping:
-// number of thresholds at or below the 53-bit uniform h >> 11.
-__host__ __device__ inline int draw_delay(uint64_t seed, int64_t step, int32_t key, int64_t boundary,
-                                          const uint64_t* thr, int n_delays) {
+// The delay hash chains SplitMix64 over (seed, step, stage key, boundary):
+// h = mix(mix(mix(mix(seed) ^ step) ^ key) ^ boundary).  The first three
+// links do not depend on the boundary.
+__host__ __device__ inline uint64_t delay_prefix(uint64_t seed, int64_t step, int32_t key) {
   uint64_t h = splitmix64(seed);
   h = splitmix64(h ^ (uint64_t)step);
-  h = splitmix64(h ^ (uint64_t)(int64_t)key);
-  h = splitmix64(h ^ (uint64_t)boundary);
-  const uint64_t u = h >> 11;
+  return splitmix64(h ^ (uint64_t)(int64_t)key);
+}
+
+// Delay before clamping: number of thresholds at or below the 53-bit
+// uniform u = h >> 11.
+__host__ __device__ inline int delay_from_prefix(uint64_t prefix, int64_t boundary, const uint64_t* thr,
+                                                 int n_delays) {
+  const uint64_t u = splitmix64(prefix ^ (uint64_t)boundary) >> 11;
   int k = 0;
   for (int i = 0; i < n_delays - 1; ++i) k += (u >= thr[i]) ? 1 : 0;
   return k;
+}
+
+__host__ __device__ inline int draw_delay(uint64_t seed, int64_t step, int32_t key, int64_t boundary,
+                                          const uint64_t* thr, int n_delays) {
+  return delay_from_prefix(delay_prefix(seed, step, key), boundary, thr, n_delays);
 }
 
 // Usable delay: every level n-k-j, j < q, must exist.

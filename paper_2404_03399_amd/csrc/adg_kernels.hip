@@ -152,115 +152,220 @@ __device__ __forceinline__ int wrap_elem(int x, int N) {
 
 // ------------------------------------------------------ fused step kernel ---
 constexpr int kMaxStages = 4;
+constexpr int kR = kElemsPerLane;
 
-struct FusedSmem {
-  double tr[2][2][kBlock];             // stage traces, double buffered: [buf][first|last][lane]
-  double pef[kMaxStages][kBlock];      // AT sum of past levels at the left face of lane t
-  unsigned char pek[kMaxStages][kBlock];  // 1: delayed (use pef), 0: synchronous
+// Lane shifts across the whole wave64 (DPP wave_shr:1 / wave_shl:1): lane l
+// receives lane l-1 (resp. l+1); the lane without a source receives 0.
+__device__ __forceinline__ double lane_from_left(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x138, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x138, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double lane_from_right(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x130, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x130, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Per-lane PE-face records of the current step (written and read by the
+// same lane only).
+struct WaveSmem {
+  double at[kWavesPerBlock][kMaxStages][kR][kWave];
+  int32_t kp[kWavesPerBlock][kR][kWave];
 };
 
-// One workgroup = T owned elements plus H = S halo elements per side, one
-// element per lane.  Each stage shrinks the valid range by one element per
-// side; after S stages the owned elements are exact.  Halo values are
-// recomputed with the same instructions as by their owners, so a shared face
-// gets bitwise-identical fluxes on both sides.  Delays and the AT sums over
-// past levels only depend on earlier steps, so they are computed in a
-// prologue that overlaps the state loads.
-template <int NP, int RK, int PHYS>
-__device__ __forceinline__ void fused_tile(const DevProblem& P, int tile, const double* __restrict__ uin,
-                                           double* __restrict__ uout, double* __restrict__ ring, int64_t n,
-                                           FusedSmem& sm) {
-  constexpr int S = rk_stages(RK);
-  constexpr int H = S;
-  constexpr int T = kBlock - 2 * H;
-  const int t = threadIdx.x;
-  const int N = (int)P.n_elem;
-  const int e0 = tile * T;
-  const int teff = (N - e0) < T ? (N - e0) : T;
-  const bool active = t < teff + 2 * H;
-  const bool owned = t >= H && t < H + teff;
-  const int e = wrap_elem(e0 - H + t, N);
-  const int64_t ld = P.ld;
-  const double* __restrict__ u = uin + P.u_off;
-  const double a = P.speed;
-  const double dt = P.dt;
-  const double two_dx = P.two_over_dx;
-
-  double u0[NP], y[NP], ks[NP], k[NP];
+template <int NP, int PHYS>
+__device__ __forceinline__ void folded_rhs(const DevProblem& P, const double (&y)[NP], double fl, double fr,
+                                           double (&k)[NP]) {
+  double g[NP];
 #pragma unroll
-  for (int j = 0; j < NP; ++j) u0[j] = active ? u[j * ld + e] : 0.0;
-
-  double Dm[NP][NP], ll[NP], lr[NP];
-  load_operators<NP>(P, Dm, ll, lr);
-
-  bool pe_left = false, pe_right = false;
-  uint32_t b_left = 0;
-  int slot_n = 0;
-  const double* rbase = ring;
-  if (P.async_faces) {
-    const uint32_t pes = P.pe_div.d;
-    b_left = fast_div((uint32_t)e, P.pe_div);
-    pe_left = active && ((uint32_t)e == b_left * pes);
-    const uint32_t e1 = (e + 1 == N) ? 0u : (uint32_t)(e + 1);
-    pe_right = active && (e1 == fast_div(e1, P.pe_div) * pes);
-    slot_n = (int)(n % (int64_t)P.depth);
-    rbase = ring + P.ring_off + (int64_t)b_left * S * P.depth;
-    if (pe_left) {
-      int kd = 0;
+  for (int j = 0; j < NP; ++j) g[j] = PHYS == PHYS_BURGERS_LLF ? y[j] * y[j] : y[j];
 #pragma unroll
-      for (int s = 0; s < S; ++s) {
-        if (s == 0 || P.per_stage) kd = pe_delay(P, n, s, b_left);
-        sm.pek[s][t] = kd > 0 ? 1 : 0;
-        if (kd > 0) sm.pef[s][t] = at_past_sum(P, rbase + s * P.depth, kd, slot_n);
-      }
-    }
-  }
+  for (int i = 0; i < NP; ++i) {
+    double v = P.Kl[i] * fl - P.Kr[i] * fr;
 #pragma unroll
-  for (int j = 0; j < NP; ++j) y[j] = u0[j];
-
-#pragma unroll
-  for (int s = 0; s < S; ++s) {
-    double(&tr)[2][kBlock] = sm.tr[s & 1];
-    tr[0][t] = y[0];
-    tr[1][t] = y[NP - 1];
-    __syncthreads();
-    const double um = t > 0 ? tr[1][t - 1] : y[0];
-    const double upr = t < kBlock - 1 ? tr[0][t + 1] : y[NP - 1];
-    double fl = Physics<PHYS>::fhat(um, y[0], a);
-    double fr = Physics<PHYS>::fhat(y[NP - 1], upr, a);
-    if (pe_left) {
-      if (owned) ring[P.ring_off + ((int64_t)b_left * S + s) * P.depth + slot_n] = fl;
-      if (sm.pek[s][t]) fl = sm.pef[s][t];
-    }
-    if (pe_right && t + 1 < kBlock) {
-      if (sm.pek[s][t + 1]) fr = sm.pef[s][t + 1];
-    }
-    element_rhs<NP, PHYS>(Dm, ll, lr, two_dx, a, y, fl, fr, k);
-    rk_update<NP, RK>(s, dt, u0, y, ks, k);
-  }
-  if (owned) {
-    double* __restrict__ uo = uout + P.u_off;
-#pragma unroll
-    for (int j = 0; j < NP; ++j) uo[j * ld + e] = y[j];
+    for (int j = 0; j < NP; ++j) v += P.Kd[i * kMaxNp + j] * g[j];
+    k[i] = v;
   }
 }
 
-template <int RK, int PHYS>
+// One wave64 = one tile of T owned elements plus HL halo lanes per side,
+// kR consecutive elements per lane (16-byte loads and stores).  Each stage
+// shrinks the valid range by one element per side, so after S stages the
+// owned lanes are exact.  Halo elements are recomputed with the same
+// instructions as by their owners, so a face shared by two waves gets a
+// bitwise-identical flux on both sides.  Each lane computes the fluxes of
+// the left faces of its elements; the right face of its last element is the
+// next lane's first left face, received by a lane shift.  No workgroup
+// barrier: the waves of a workgroup are independent.
+//
+// PE faces (Secs. 3-5): at step n the lane owning the element right of PE
+// face b writes the level-n flux of every stage into the ring, and at the end
+// of the step computes the delays of step n+1 and the AT sums
+// sum_j c_j(k) F^{n+1-k-j} over past levels (all <= n when k >= 1) into record
+// parity (n+1)&1.  Both neighbours of the face read parity n&1 at step n; a
+// delay of 0 selects the synchronous level-n flux.
+struct FusedPtrs {
+  double* __restrict__ ring;
+  double* __restrict__ atsum;
+  int32_t* __restrict__ atk;
+};
+
+template <int NP, int RK, int PHYS>
+__device__ __forceinline__ void wave_tile(const DevProblem& P, const WorkItem wi, const FusedPtrs& A, int64_t n,
+                                          const double* __restrict__ uin, double* __restrict__ uout, WaveSmem& sm,
+                                          int wv, int lane) {
+  constexpr int S = rk_stages(RK);
+  constexpr int HL = halo_lanes(RK);
+  constexpr int T = fused_tile(RK);
+  const int N = (int)P.n_elem;
+  const int e0 = wi.tile * T;
+  const int teff = (N - e0) < T ? (N - e0) : T;
+  const int xb = e0 - kR * HL;                       // element position of lane 0, element 0
+  const bool fast = xb >= 0 && xb + kR * kWave <= N;  // no periodic wrap inside this wave
+  const int64_t ld = P.ld;
+  const double* __restrict__ u = uin + P.u_off;
+  const bool lane_owned = lane >= HL && lane < kWave - HL;
+
+  int e[kR];
+  bool owned[kR];
+#pragma unroll
+  for (int r = 0; r < kR; ++r) {
+    const int x = xb + kR * lane + r;
+    e[r] = fast ? x : wrap_elem(x, N);
+    owned[r] = lane_owned && (x - e0) < teff;
+  }
+  double u0[kR][NP];
+  if (fast) {
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+      const double2 v = *reinterpret_cast<const double2*>(u + j * ld + e[0]);
+      u0[0][j] = v.x;
+      u0[1][j] = v.y;
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < kR; ++r)
+#pragma unroll
+      for (int j = 0; j < NP; ++j) u0[r][j] = u[j * ld + e[r]];
+  }
+
+  // PE faces among this lane's left faces and their records for step n
+  const int par = (int)(n & 1);
+  bool pe[kR];
+  uint32_t b[kR];
+  int32_t kp[kR];
+#pragma unroll
+  for (int r = 0; r < kR; ++r) {
+    pe[r] = false;
+    b[r] = 0;
+    kp[r] = 0;
+  }
+  int depth = 1, slot_n = 0;
+  if (P.async_faces) {
+    depth = P.depth;
+    slot_n = (int)(n % (int64_t)depth);
+    const uint32_t pes = P.pe_div.d;
+#pragma unroll
+    for (int r = 0; r < kR; ++r) {
+      b[r] = fast_div((uint32_t)e[r], P.pe_div);
+      pe[r] = (uint32_t)e[r] == b[r] * pes;
+      if (pe[r]) {
+        kp[r] = A.atk[P.atk_off + (int64_t)par * P.n_pe + b[r]];
+        const double* __restrict__ src = A.atsum + P.at_off + ((int64_t)par * P.n_pe + b[r]) * S;
+#pragma unroll
+        for (int s = 0; s < S; ++s) sm.at[wv][s][r][lane] = src[s];
+      }
+    }
+  }
+
+  double y[kR][NP], ks[kR][NP], k[NP];
+#pragma unroll
+  for (int r = 0; r < kR; ++r)
+#pragma unroll
+    for (int j = 0; j < NP; ++j) y[r][j] = u0[r][j];
+  const double a = P.speed;
+  const double dt = P.dt;
+
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    double F[kR];
+    const double um = lane_from_left(y[kR - 1][NP - 1]);
+    F[0] = Physics<PHYS>::fhat(um, y[0][0], a);
+#pragma unroll
+    for (int r = 1; r < kR; ++r) F[r] = Physics<PHYS>::fhat(y[r - 1][NP - 1], y[r][0], a);
+#pragma unroll
+    for (int r = 0; r < kR; ++r) {
+      if (pe[r]) {
+        if (owned[r]) A.ring[P.ring_off + ((int64_t)b[r] * S + s) * depth + slot_n] = F[r];
+        if ((kp[r] >> (3 * s)) & 7) F[r] = sm.at[wv][s][r][lane];
+      }
+    }
+    const double f_last = lane_from_right(F[0]);
+#pragma unroll
+    for (int r = 0; r < kR; ++r) {
+      folded_rhs<NP, PHYS>(P, y[r], F[r], r + 1 < kR ? F[r + 1] : f_last, k);
+      rk_update<NP, RK>(s, dt, u0[r], y[r], ks[r], k);
+    }
+  }
+
+  double* __restrict__ uo = uout + P.u_off;
+  if (fast && owned[0] && owned[kR - 1]) {
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+      double2 v;
+      v.x = y[0][j];
+      v.y = y[1][j];
+      *reinterpret_cast<double2*>(uo + j * ld + e[0]) = v;
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < kR; ++r)
+      if (owned[r])
+#pragma unroll
+        for (int j = 0; j < NP; ++j) uo[j * ld + e[r]] = y[r][j];
+  }
+
+  // owners of PE faces: records of step n+1
+#pragma unroll
+  for (int r = 0; r < kR; ++r) {
+    if (!(pe[r] && owned[r])) continue;
+    const int64_t n1 = n + 1;
+    const double* __restrict__ rb = A.ring + P.ring_off + (int64_t)b[r] * S * depth;
+    int32_t kpn = 0;
+    int kd = 0;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      if (s == 0 || P.per_stage) {
+        const uint64_t pre = delay_prefix(P.seed, n1, P.per_stage ? s : 0);
+        kd = clamp_delay(delay_from_prefix(pre, b[r], P.thr, P.n_delays), n1, P.q);
+      }
+      kpn |= kd << (3 * s);
+      double acc = 0.0;
+      for (int j = 0; kd > 0 && j < P.q; ++j)  // level n1 - kd - j = n - (kd + j - 1)
+        acc += P.atc[kd][j] * rb[s * depth + ring_slot(slot_n, kd + j - 1, depth)];
+      A.atsum[P.at_off + ((int64_t)(par ^ 1) * P.n_pe + b[r]) * S + s] = acc;
+    }
+    A.atk[P.atk_off + (int64_t)(par ^ 1) * P.n_pe + b[r]] = kpn;
+  }
+}
+
+template <int NP, int RK, int PHYS>
 __global__ __launch_bounds__(kBlock) void k_fused_step(const DevProblem* __restrict__ probs,
                                                        const WorkItem* __restrict__ work,
-                                                       const double* __restrict__ uin, double* __restrict__ uout,
-                                                       double* __restrict__ ring, const int64_t* __restrict__ ctr,
-                                                       int32_t step_offset) {
-  __shared__ FusedSmem sm;
-  const WorkItem wi = work[blockIdx.x];
-  const DevProblem& P = probs[wi.prob];
+                                                       const int64_t* __restrict__ ctr, double* __restrict__ ring,
+                                                       double* __restrict__ atsum, int32_t* __restrict__ atk,
+                                                       int32_t w_begin, int32_t w_end, const double* __restrict__ uin,
+                                                       double* __restrict__ uout, int32_t step_offset) {
+  __shared__ WaveSmem sm;
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+  const int lane = (int)(threadIdx.x % kWave);
+  const int w = w_begin + (int)blockIdx.x * kWavesPerBlock + wv;
+  if (w >= w_end) return;  // whole wave
   const int64_t n = ctr[0] + step_offset;
-  switch (P.np) {
-    case 2: fused_tile<2, RK, PHYS>(P, wi.tile, uin, uout, ring, n, sm); break;
-    case 3: fused_tile<3, RK, PHYS>(P, wi.tile, uin, uout, ring, n, sm); break;
-    case 4: fused_tile<4, RK, PHYS>(P, wi.tile, uin, uout, ring, n, sm); break;
-    default: fused_tile<5, RK, PHYS>(P, wi.tile, uin, uout, ring, n, sm); break;
-  }
+  const WorkItem wi = work[w];
+  const FusedPtrs A{ring, atsum, atk};
+  wave_tile<NP, RK, PHYS>(probs[wi.prob], wi, A, n, uin, uout, sm, wv, lane);
 }
 
 // ------------------------------------------------------ per-stage kernel ---
@@ -460,34 +565,38 @@ __global__ __launch_bounds__(kBlock) void k_check_finite(const DevProblem* __res
 }
 
 // ---------------------------------------------------------------- launch ---
+template <int NP, int RK, int PHYS>
+static void fused_go(const StepArgs& a, int gi, const double* uin, double* uout, int32_t off, hipStream_t st) {
+  hipLaunchKernelGGL((k_fused_step<NP, RK, PHYS>), dim3(a.grid[gi]), dim3(kBlock), 0, st, a.probs, a.work, a.ctr,
+                     a.ring, a.atsum, a.atk, a.group[gi], a.group[gi + 1], uin, uout, off);
+}
+
+template <int RK, int PHYS>
+static void fused_np(const StepArgs& a, const double* uin, double* uout, int32_t off, hipStream_t st) {
+  // degree ranges np = 5, 4, 3, 2
+  if (a.group[1] > a.group[0]) fused_go<5, RK, PHYS>(a, 0, uin, uout, off, st);
+  if (a.group[2] > a.group[1]) fused_go<4, RK, PHYS>(a, 1, uin, uout, off, st);
+  if (a.group[3] > a.group[2]) fused_go<3, RK, PHYS>(a, 2, uin, uout, off, st);
+  if (a.group[4] > a.group[3]) fused_go<2, RK, PHYS>(a, 3, uin, uout, off, st);
+}
+
 template <int RK>
-static hipError_t fused_phys(int phys, const StepArgs& a, const double* uin, double* uout, int32_t off,
-                             hipStream_t st) {
-  const dim3 g(a.n_work), b(kBlock);
+static void fused_phys(int phys, const StepArgs& a, const double* uin, double* uout, int32_t off, hipStream_t st) {
   switch (phys) {
-    case PHYS_ADV_UPWIND:
-      hipLaunchKernelGGL((k_fused_step<RK, PHYS_ADV_UPWIND>), g, b, 0, st, a.probs, a.work, uin, uout, a.ring, a.ctr,
-                         off);
-      break;
-    case PHYS_ADV_CENTRAL:
-      hipLaunchKernelGGL((k_fused_step<RK, PHYS_ADV_CENTRAL>), g, b, 0, st, a.probs, a.work, uin, uout, a.ring, a.ctr,
-                         off);
-      break;
-    default:
-      hipLaunchKernelGGL((k_fused_step<RK, PHYS_BURGERS_LLF>), g, b, 0, st, a.probs, a.work, uin, uout, a.ring, a.ctr,
-                         off);
-      break;
+    case PHYS_ADV_UPWIND: fused_np<RK, PHYS_ADV_UPWIND>(a, uin, uout, off, st); break;
+    case PHYS_ADV_CENTRAL: fused_np<RK, PHYS_ADV_CENTRAL>(a, uin, uout, off, st); break;
+    default: fused_np<RK, PHYS_BURGERS_LLF>(a, uin, uout, off, st); break;
   }
-  return hipGetLastError();
 }
 
 hipError_t launch_fused_step(int rk, int phys, const StepArgs& a, const double* uin, double* uout, int32_t step_offset,
                              hipStream_t stream) {
   switch (rk) {
-    case RK_HEUN: return fused_phys<RK_HEUN>(phys, a, uin, uout, step_offset, stream);
-    case RK_SSP3: return fused_phys<RK_SSP3>(phys, a, uin, uout, step_offset, stream);
-    default: return fused_phys<RK_RK4>(phys, a, uin, uout, step_offset, stream);
+    case RK_HEUN: fused_phys<RK_HEUN>(phys, a, uin, uout, step_offset, stream); break;
+    case RK_SSP3: fused_phys<RK_SSP3>(phys, a, uin, uout, step_offset, stream); break;
+    default: fused_phys<RK_RK4>(phys, a, uin, uout, step_offset, stream); break;
   }
+  return hipGetLastError();
 }
 
 template <int RK, int PHYS, int SI>

@@ -11,10 +11,27 @@ struct StepArgs {
   int32_t n_work;
   double* ring;              // delay ring (fluxes), may be null when no PE faces
   int64_t* ctr;              // ctr[0] = steps completed by earlier batches, ctr[2] = non-finite flag
+  double* atsum;             // fused kernel: AT sums of past levels, [2][P][S] per problem
+  int32_t* atk;              // fused kernel: clamped delays, [2][P][S] per problem
+  int32_t group[5];          // fused kernel: work-item ranges per degree (below)
+  int32_t grid[4];           // fused kernel: workgroups per degree range
 };
 
-// Owned elements per workgroup of the fused step kernel for an RK scheme.
-inline int fused_tile(int rk) { return kBlock - 2 * rk_stages(rk); }
+// Work items of the fused kernel are sorted by descending np; items with
+// np = 5, 4, 3, 2 occupy [group[0], group[1]), [group[1], group[2]),
+// [group[2], group[3]), [group[3], group[4]).
+
+// Fused step kernel geometry: one wave64 per work item, kElemsPerLane
+// consecutive elements per lane, halo of ceil(S / kElemsPerLane) lanes per
+// side; owned elements per work item:
+constexpr int kWave = 64;
+constexpr int kElemsPerLane = 2;
+constexpr int kWavesPerBlock = kBlock / kWave;
+__host__ __device__ constexpr int halo_lanes(int rk) { return (rk_stages(rk) + kElemsPerLane - 1) / kElemsPerLane; }
+__host__ __device__ constexpr int fused_tile(int rk) { return kElemsPerLane * (kWave - 2 * halo_lanes(rk)); }
+
+// Workgroups of the fused kernel for n_work items (kWavesPerBlock per group).
+inline int fused_grid(int n_work) { return n_work < 1 ? 1 : (n_work + kWavesPerBlock - 1) / kWavesPerBlock; }
 
 // One full RK step, all stages on chip: state uin -> uout (distinct buffers).
 // The step index is ctr[0] + step_offset.
