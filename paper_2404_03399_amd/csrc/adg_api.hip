@@ -217,19 +217,29 @@ int validate(const adg_problem* probs, int32_t n) {
 }
 
 struct Layout {
-  int64_t probs, work_f, work_s, first_s, ctr, ring, atsum, atk, state2, y0, y1, acc, part, stats_out, total;
+  int64_t probs, work_f, work_s, first_s, ctr, ring, atsum, atk, state2, y0, y1, acc, part, stats_out;
+  // adjoint recording (-1 if not recording)
+  int64_t ckpt, useg, ybuf, lam, q, adjring, cpart;
+  int64_t total;
   int32_t n_work_f, n_work_s;
   int64_t total_doubles;
   int64_t ring_doubles;
   int64_t at_entries;  // boundaries x 2 parities (x S for the sums)
+  int64_t n_rec, ckpt_every, n_ckpt;
 };
+
+// Ring slots per (boundary, stage): the AT window L + q - 1, or, when an
+// adjoint recording horizon is given, the whole run (every level is kept).
+int64_t depth_of(const adg_problem& p, int64_t n_rec) {
+  return n_rec > 0 ? n_rec + p.n_delays + q_of(p) : (int64_t)p.n_delays + q_of(p) - 1;
+}
 
 int kernel_of(const adg_options* opt) {
   if (!opt || opt->kernel == ADG_KERNEL_AUTO) return ADG_KERNEL_FUSED;
   return opt->kernel;
 }
 
-Layout make_layout(const adg_problem* probs, int32_t n, const adg_options* opt) {
+Layout make_layout(const adg_problem* probs, int32_t n, const adg_options* opt, int64_t n_rec) {
   Layout L{};
   const int S = rk_stages((int)probs[0].rk);
   const int T = fused_tile((int)probs[0].rk);
@@ -240,7 +250,7 @@ Layout make_layout(const adg_problem* probs, int32_t n, const adg_options* opt) 
     nws += (p.n_elem + kBlock - 1) / kBlock;
     tot += ld_of(p) * (p.degree + 1);
     if (async_of(p)) {
-      ring += (p.n_elem / p.pe_size) * S * (int64_t)(p.n_delays + q_of(p) - 1);
+      ring += (p.n_elem / p.pe_size) * S * depth_of(p, n_rec);
       at += 2 * (p.n_elem / p.pe_size);
     }
   }
@@ -260,12 +270,27 @@ Layout make_layout(const adg_problem* probs, int32_t n, const adg_options* opt) 
   L.ring = take(8 * std::max<int64_t>(ring, 1));
   L.atsum = take(8 * S * std::max<int64_t>(at, 1));
   L.atk = take(4 * std::max<int64_t>(at, 1));
+  const bool rec = n_rec > 0;
   L.state2 = kern == ADG_KERNEL_FUSED ? take(8 * tot) : -1;
-  L.y0 = kern == ADG_KERNEL_STAGE ? take(8 * tot) : -1;
-  L.y1 = kern == ADG_KERNEL_STAGE ? take(8 * tot) : -1;
-  L.acc = kern == ADG_KERNEL_STAGE ? take(8 * tot) : -1;
+  L.y0 = (kern == ADG_KERNEL_STAGE || rec) ? take(8 * tot) : -1;
+  L.y1 = (kern == ADG_KERNEL_STAGE || rec) ? take(8 * tot) : -1;
+  L.acc = (kern == ADG_KERNEL_STAGE || rec) ? take(8 * tot) : -1;
   L.part = take(3 * 8 * nws);
   L.stats_out = take(3 * 8 * (int64_t)n);
+  L.n_rec = n_rec;
+  L.ckpt_every = (opt && opt->ckpt_every > 0) ? opt->ckpt_every : 64;
+  L.n_ckpt = rec ? (n_rec + L.ckpt_every - 1) / L.ckpt_every : 0;
+  L.ckpt = L.useg = L.ybuf = L.lam = L.q = L.adjring = L.cpart = -1;
+  if (rec) {
+    const int64_t seg = std::min<int64_t>(L.ckpt_every, n_rec);
+    L.ckpt = take(8 * tot * L.n_ckpt);
+    L.useg = take(8 * tot * seg);
+    L.ybuf = take(8 * tot * (S - 1));
+    L.lam = take(8 * tot * 2);
+    L.q = take(8 * tot * (S - 1));
+    L.adjring = take(8 * std::max<int64_t>(ring, 1));
+    L.cpart = take(8 * nws);
+  }
   L.total = off;
   return L;
 }
@@ -282,6 +307,8 @@ struct adg_ctx {
   char* ws = nullptr;
   Layout L{};
   int64_t steps = 0;
+  // adjoint recording: steps recorded by the last ADG_RUN_RECORD run (0: none)
+  int64_t rec_steps = 0;
   // graph cache
   hipGraphExec_t graph = nullptr;
   const double* graph_u = nullptr;
@@ -338,6 +365,7 @@ int reset_device(adg_ctx* c) {
   ADG_HIP(hipMemsetAsync(c->ws + c->L.atsum, 0, 8 * c->S * std::max<int64_t>(c->L.at_entries, 1), c->stream));
   ADG_HIP(hipMemsetAsync(c->ws + c->L.atk, 0, 4 * std::max<int64_t>(c->L.at_entries, 1), c->stream));
   c->steps = 0;
+  c->rec_steps = 0;
   return ADG_OK;
 }
 
@@ -414,10 +442,11 @@ int adg_workspace_size(const adg_problem* probs, int32_t n_probs, const adg_opti
   int rc = validate(probs, n_probs);
   if (rc) return rc;
   if (!bytes_out) return fail(ADG_E_INVALID, "bytes_out is null");
-  if (n_steps_record != 0) return fail(ADG_E_UNSUPPORTED, "adjoint recording is not available in this build");
+  if (n_steps_record < 0 || n_steps_record > (1 << 28)) return fail(ADG_E_INVALID, "n_steps_record out of range");
+  if (opt && opt->ckpt_every < 0) return fail(ADG_E_INVALID, "ckpt_every < 0");
   const int k = kernel_of(opt);
   if (k != ADG_KERNEL_FUSED && k != ADG_KERNEL_STAGE) return fail(ADG_E_INVALID, "unknown kernel family");
-  *bytes_out = make_layout(probs, n_probs, opt).total;
+  *bytes_out = make_layout(probs, n_probs, opt, n_steps_record).total;
   return ADG_OK;
 }
 
@@ -441,7 +470,7 @@ int adg_init(adg_ctx** out, const adg_problem* probs, int32_t n_probs, const adg
   c->S = rk_stages(c->rk);
   c->stream = (hipStream_t)hip_stream;
   c->ws = (char*)d_workspace;
-  c->L = make_layout(probs, n_probs, opt);
+  c->L = make_layout(probs, n_probs, opt, n_steps_record);
 
   // descriptors
   c->dev.resize(n_probs);
@@ -459,7 +488,7 @@ int adg_init(adg_ctx** out, const adg_problem* probs, int32_t n_probs, const adg
     d.np = (int)p.degree + 1;
     d.q = q_of(p);
     d.n_delays = (int)p.n_delays;
-    d.depth = d.n_delays + d.q - 1;
+    d.depth = (int32_t)depth_of(p, n_steps_record);
     d.per_stage = p.delay_granularity == ADG_DELAY_PER_STAGE;
     d.scheme = (int)p.scheme;
     d.async_faces = async_of(p) ? 1 : 0;
@@ -559,7 +588,24 @@ int adg_run(adg_ctx* c, double* d_u, int64_t n_steps, uint32_t flags) {
   if (!c || !d_u) return fail(ADG_E_INVALID, "null argument");
   if (n_steps < 0) return fail(ADG_E_INVALID, "n_steps < 0");
   if (flags & ~(ADG_RUN_GRAPH | ADG_RUN_RECORD | ADG_RUN_CHECK_FINITE)) return fail(ADG_E_INVALID, "unknown flags");
-  if (flags & ADG_RUN_RECORD) return fail(ADG_E_UNSUPPORTED, "adjoint recording is not available in this build");
+  if (flags & ADG_RUN_RECORD) {
+    if (c->L.n_rec <= 0) return fail(ADG_E_STATE, "context was created without a recording horizon");
+    if (c->steps != 0) return fail(ADG_E_STATE, "ADG_RUN_RECORD must start at step 0 (call adg_reset)");
+    if (n_steps > c->L.n_rec) return fail(ADG_E_INVALID, "n_steps exceeds the recording horizon");
+    const int64_t C = c->L.ckpt_every, tot = c->L.total_doubles;
+    int64_t done = 0;
+    int rc;
+    for (int64_t k = 0; done < n_steps; ++k) {
+      ADG_HIP(hipMemcpyAsync(c->ws + c->L.ckpt + 8 * tot * k, d_u, 8 * tot, hipMemcpyDeviceToDevice, c->stream));
+      const int64_t m = std::min<int64_t>(C, n_steps - done);
+      if ((rc = adg_run(c, d_u, m, flags & ~(ADG_RUN_RECORD | ADG_RUN_CHECK_FINITE)))) return rc;
+      done += m;
+    }
+    c->rec_steps = n_steps;
+    if (flags & ADG_RUN_CHECK_FINITE) return adg_run(c, d_u, 0, ADG_RUN_CHECK_FINITE);
+    return ADG_OK;
+  }
+  c->rec_steps = 0;  // any further step invalidates a recording
   double* cur = d_u;
   double* other = c->kernel == ADG_KERNEL_FUSED ? c->state2() : nullptr;
   int64_t left = n_steps;
@@ -600,9 +646,84 @@ int adg_run(adg_ctx* c, double* d_u, int64_t n_steps, uint32_t flags) {
 int adg_step(adg_ctx* c, double* d_u) { return adg_run(c, d_u, 1, 0); }
 
 int adg_adjoint(adg_ctx* c, const double* d_cot_uT, double* d_grad_u0, double* h_grad_speed) {
-  (void)d_cot_uT; (void)d_grad_u0; (void)h_grad_speed;
-  if (!c) return fail(ADG_E_INVALID, "null context");
-  return fail(ADG_E_STATE, "adg_adjoint needs a run recorded with ADG_RUN_RECORD");
+  if (!c || !d_cot_uT || !d_grad_u0) return fail(ADG_E_INVALID, "null argument");
+  if (c->rec_steps <= 0) return fail(ADG_E_STATE, "adg_adjoint needs a run recorded with ADG_RUN_RECORD");
+  const Layout& L = c->L;
+  const int64_t tot = L.total_doubles, C = L.ckpt_every, N = c->rec_steps;
+  const int S = c->S;
+  char* ws = c->ws;
+  hipStream_t st = c->stream;
+  const StepArgs sa = c->stage_args();
+  double* lam = (double*)(ws + L.lam);
+  double* lamu = lam + tot;
+  double* Q = (double*)(ws + L.q);
+  double* adjring = (double*)(ws + L.adjring);
+  double* cpart = (double*)(ws + L.cpart);
+  double* ring = (double*)(ws + L.ring);
+  double* useg = (double*)(ws + L.useg);
+  double* ybuf = (double*)(ws + L.ybuf);
+  double* abuf = (double*)(ws + L.acc);
+  double* y0 = (double*)(ws + L.y0);
+  double* y1 = (double*)(ws + L.y1);
+  int64_t* ctr = (int64_t*)(ws + L.ctr);
+  const size_t bytes = 8 * (size_t)tot;
+
+  ADG_HIP(hipMemcpyAsync(lam, d_cot_uT, bytes, hipMemcpyDeviceToDevice, st));
+  ADG_HIP(hipMemsetAsync(adjring, 0, 8 * std::max<int64_t>(L.ring_doubles, 1), st));
+  ADG_HIP(hipMemsetAsync(cpart, 0, 8 * (size_t)L.n_work_s, st));
+  ADG_HIP(launch_set_counter(ctr, 0, st));  // launches below pass absolute step indices
+
+  for (int64_t k = L.n_ckpt - 1; k >= 0; --k) {
+    const int64_t n0 = k * C;
+    const int64_t len = std::min<int64_t>(C, N - n0);
+    if (len <= 0) continue;
+    // recompute the segment's states u^{n0}, ..., u^{n0+len-1}
+    ADG_HIP(hipMemcpyAsync(useg, ws + L.ckpt + 8 * tot * k, bytes, hipMemcpyDeviceToDevice, st));
+    for (int64_t i = 1; i < len; ++i) {
+      double* u = useg + tot * i;
+      ADG_HIP(hipMemcpyAsync(u, u - tot, bytes, hipMemcpyDeviceToDevice, st));
+      for (int s = 0; s < S; ++s) {
+        const double* yin = s == 0 ? u : ((s & 1) ? y0 : y1);
+        double* yout = (s & 1) ? y1 : y0;
+        ADG_HIP(launch_stage(c->rk, c->phys, s, sa, yin, yout, u, abuf, (int32_t)(n0 + i - 1), st));
+      }
+    }
+    for (int64_t i = len - 1; i >= 0; --i) {
+      const int32_t n = (int32_t)(n0 + i);
+      double* u = useg + tot * i;
+      // stage inputs Y_1 = u^n, Y_2..Y_S
+      for (int s = 0; s + 1 < S; ++s) {
+        const double* yin = s == 0 ? u : ybuf + tot * (s - 1);
+        ADG_HIP(launch_stage(c->rk, c->phys, s, sa, yin, ybuf + tot * s, u, abuf, n, st));
+      }
+      if (S > 1) ADG_HIP(hipMemsetAsync(Q, 0, bytes * (S - 1), st));
+      ADG_HIP(hipMemcpyAsync(lamu, lam, bytes, hipMemcpyDeviceToDevice, st));
+      for (int s = S - 1; s >= 0; --s) {
+        const double* Y = s == 0 ? u : ybuf + tot * (s - 1);
+        ADG_HIP(launch_adj_stage(c->rk, c->phys, s, sa, Y, lam, lamu, Q, tot, ring, adjring, cpart, n, st));
+      }
+      std::swap(lam, lamu);
+    }
+  }
+  ADG_HIP(hipMemcpyAsync(d_grad_u0, lam, bytes, hipMemcpyDeviceToDevice, st));
+  ADG_HIP(launch_set_counter(ctr, c->steps, st));
+  if (h_grad_speed) {
+    std::vector<double> part(L.n_work_s);
+    ADG_HIP(hipMemcpyAsync(part.data(), cpart, 8 * part.size(), hipMemcpyDeviceToHost, st));
+    ADG_HIP(hipStreamSynchronize(st));
+    const WorkItem* dummy = nullptr;
+    (void)dummy;
+    // stage work list is contiguous per problem, in problem order
+    int64_t item = 0;
+    for (size_t i = 0; i < c->probs.size(); ++i) {
+      const int64_t nt = (c->probs[i].n_elem + kBlock - 1) / kBlock;
+      double acc = 0.0;
+      for (int64_t t = 0; t < nt; ++t) acc += part[item + t];
+      item += nt;
+      h_grad_speed[i] = c->probs[i].equation == ADG_EQ_ADVECTION ? acc : 0.0;
+    }
+  }
+  return ADG_OK;
 }
 
 int adg_error_stats(adg_ctx* c, const double* d_u, const double* d_ref, double* h_out) {

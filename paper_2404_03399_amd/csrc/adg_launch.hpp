@@ -43,6 +43,16 @@ hipError_t launch_fused_step(int rk, int phys, const StepArgs& a, const double* 
 hipError_t launch_stage(int rk, int phys, int stage, const StepArgs& a, const double* yin, double* yout,
                         double* U, double* A, int32_t step_offset, hipStream_t stream);
 
+// Reverse of RK stage `stage` of step n (absolute index) for all problems:
+// lamu += mu, Q_i += a_{stage,i} mu, adjoint-ring deposits for delayed AT
+// levels, cpart[workgroup] += dJ/da share.  Stage work list (kBlock per item).
+hipError_t launch_adj_stage(int rk, int phys, int stage, const StepArgs& a, const double* Y, const double* lam,
+                            double* lamu, double* Q, int64_t qstride, const double* ring, double* adjring,
+                            double* cpart, int32_t n, hipStream_t stream);
+
+// ctr[0] := value (one lane).
+hipError_t launch_set_counter(int64_t* ctr, int64_t value, hipStream_t stream);
+
 // ctr[0] += n_steps (one lane), closing a batch of launches.
 hipError_t launch_advance(int64_t* ctr, int64_t n_steps, hipStream_t stream);
 

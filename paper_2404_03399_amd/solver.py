@@ -150,6 +150,13 @@ class Solver:
                 (adg.ADG_RUN_CHECK_FINITE if check_finite else 0)
         adg.adg_run(self.ctx, u.data_ptr(), n_steps, flags)
 
+    def adjoint(self, cot: torch.Tensor):
+        """dJ/du0 (device, state layout) and dJ/da per problem (host list) for
+        the last recorded run, given cot = dJ/du(T)."""
+        grad = torch.empty_like(cot)
+        gs = adg.adg_adjoint(self.ctx, cot.contiguous().data_ptr(), grad.data_ptr(), len(self.probs))
+        return grad, gs
+
     def steps_taken(self) -> int:
         return adg.adg_step_count(self.ctx)
 
