@@ -90,16 +90,101 @@ def cpu_baseline(w, steps: int):
             "sample": f"{steps} RK4 steps of the same 2^20-element ADG-AT problem ({dt:.1f} s, numpy FP64, 1 thread)"}
 
 
+def bench_adjoint(torch, W, Solver, n_steps: int, n_elem: int):
+    """Recorded forward + discrete adjoint of J = 1/2 ||u(T) - u_exact(T)||^2
+    (linear advection, ADG-AT, p=3, RK4, checkpoint every 64 steps)."""
+    w = W.c5_adjoint_advection(n_elem=n_elem, n_steps=n_steps)
+    s = Solver(w, n_steps_record=n_steps, ckpt_every=64)
+    u = s.initial_state()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.run(u, n_steps, graph=True, record=True)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    cot = u - s.exact_advection_state(n_steps * w.dt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g, ga = s.adjoint(cot)
+    torch.cuda.synchronize()
+    t_adj = time.perf_counter() - t0
+    dofs = w.n_elem * (w.degree + 1)
+    out = {"workload": f"ADG-AT(q=4) RK4 N_E={n_elem} p=3, {n_steps} steps, checkpoint every 64",
+           "reverse_dof_stage_per_s": dofs * 4 * n_steps / t_adj, "adjoint_s": t_adj,
+           "recorded_forward_s": t_fwd, "dJ_da": ga[0],
+           "grad_finite": bool(torch.isfinite(g).all().item())}
+    s.close()
+    return out
+
+
+def bench_ensemble(torch, W, Solver, n_steps: int, n_real: int, plain: bool):
+    """Batched ensemble (12 meshes x n_real delay realizations, one context,
+    one launch per degree per step) against one context per problem."""
+    ws = W.c4_ensemble(n_real=n_real, n_steps=n_steps)
+    group = [int(w.name.split("_")[1][1:]) for w in ws]
+    dofs = sum(w.n_elem * (w.degree + 1) for w in ws)
+    s = Solver(ws)
+    u_init = s.initial_state()
+    u = u_init.clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.run(u, n_steps, graph=True)
+    torch.cuda.synchronize()
+    t_batched = time.perf_counter() - t0
+    # reference: exact solution of each problem at its own final time
+    ref = s.empty_state()
+    for i, w in enumerate(ws):
+        x = s.nodes(i) - w.speed * n_steps * w.dt
+        v = torch.zeros_like(x)
+        for k, a, ph in zip(w.ic.kappa, w.ic.amp, w.ic.phase):
+            v = v + a * torch.sin(k * x + ph)
+        s.view(ref, i).copy_(v)
+    gstats = s.ensemble_stats(u, ref, group, max(group) + 1)
+    out = {"workload": f"{len(set(group))} meshes x {n_real} realizations ({len(ws)} problems), "
+                       f"{dofs} DOFs, {n_steps} RK4 steps, ADG-AT q=p+1",
+           "batched_dof_stage_per_s": dofs * 4 * n_steps / t_batched, "batched_s": t_batched,
+           "per_mesh": [{"n_elem": ws[group.index(g)].n_elem, "degree": ws[group.index(g)].degree,
+                         "mean_err": st[0], "var_err": st[1], "mean_linf": st[2], "var_linf": st[3]}
+                        for g, st in enumerate(gstats)]}
+    if plain:
+        # one context per problem, same problems, same kernels (init excluded)
+        total = 0.0
+        max_diff = 0.0
+        for i, w in enumerate(ws):
+            sp = Solver(w)
+            up = s.view(u_init, i)
+            uu = sp.empty_state()
+            sp.view(uu, 0).copy_(up)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sp.run(uu, n_steps, graph=True)
+            torch.cuda.synchronize()
+            total += time.perf_counter() - t0
+            max_diff = max(max_diff, float((sp.view(uu, 0) - s.view(u, i)).abs().max()))
+            sp.close()
+        out["plain_dof_stage_per_s"] = dofs * 4 * n_steps / total
+        out["plain_s"] = total
+        out["batched_over_plain"] = total / t_batched
+        out["max_abs_diff_batched_vs_plain"] = max_diff
+    s.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--cpu-steps", type=int, default=8)
+    ap.add_argument("--cpu-steps", type=int, default=40)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--kernel", default="fused", choices=["fused", "stage"])
     ap.add_argument("--n-elem", type=int, default=1 << 20)
     ap.add_argument("--extras", action="store_true", help="also time DG/ADG, per-stage kernel, 2^24 mesh")
+    ap.add_argument("--adjoint-steps", type=int, default=2000)
+    ap.add_argument("--ensemble-real", type=int, default=256)
+    ap.add_argument("--ensemble-steps", type=int, default=500)
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-ensemble", action="store_true")
+    ap.add_argument("--no-plain", action="store_true", help="skip the one-context-per-problem ensemble run")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -174,6 +259,11 @@ def main():
         ex["n2^24_hbm_frac"] = (BYTES_PER_DOF_STEP_FUSED * d24 + ring_bytes_per_step(wl)) / (g / 100) / 1e9 / HBM_PEAK_GBS
         so.close()
         out["extras"] = ex
+    if not args.no_adjoint:
+        out["adjoint"] = bench_adjoint(torch, W, Solver, args.adjoint_steps, args.n_elem)
+    if not args.no_ensemble:
+        out["ensemble"] = bench_ensemble(torch, W, Solver, args.ensemble_steps, args.ensemble_real,
+                                         not args.no_plain)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
         out["cpu_baseline"]["host"] = {"cpu_count": os.cpu_count()}

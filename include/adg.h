@@ -171,6 +171,17 @@ int adg_adjoint(adg_ctx* ctx, const double* d_cot_uT, double* d_grad_u0, double*
  * Synchronises the stream. */
 int adg_error_stats(adg_ctx* ctx, const double* d_u, const double* d_ref, double* h_out);
 
+/* Ensemble statistics over groups of problems (Sec. 4.3: spatial average
+ * <E> = mean |u - ref| over all nodal values of a problem, and its ensemble
+ * average over realizations).  h_group_of[i] in [0, n_groups) assigns
+ * problem i to a group (e.g. one mesh, many delay realizations).  For each
+ * group g writes h_out[4*g + 0] = mean of <E> over the group,
+ * h_out[4*g + 1] = population variance of <E>, h_out[4*g + 2] = mean of
+ * max |u - ref|, h_out[4*g + 3] = its population variance.  Two-pass,
+ * fixed summation order (deterministic).  Synchronises the stream. */
+int adg_ensemble_stats(adg_ctx* ctx, const double* d_u, const double* d_ref, const int32_t* h_group_of,
+                       int32_t n_groups, double* h_out);
+
 /* Host-side delay schedule of one problem (same integers the kernels use):
  * h_k[((n - step0) * S + s) * P + b] = clamped delay at step n, RK stage s,
  * boundary b, for n in [step0, step0 + n_steps).  S = number of RK stages,

@@ -36,7 +36,7 @@ ADG_RUN_CHECK_FINITE = 4
 SYMBOLS = [
     "adg_abi_version", "adg_last_error", "adg_nodes", "adg_state_layout", "adg_workspace_size",
     "adg_init", "adg_reset", "adg_step_count", "adg_step", "adg_run", "adg_adjoint",
-    "adg_error_stats", "adg_delay_schedule", "adg_destroy",
+    "adg_error_stats", "adg_ensemble_stats", "adg_delay_schedule", "adg_destroy",
 ]
 
 
@@ -92,6 +92,7 @@ def lib() -> C.CDLL:
             "adg_run": ([vp, vp, I64, U32], C.c_int),
             "adg_adjoint": ([vp, vp, vp, P(D)], C.c_int),
             "adg_error_stats": ([vp, vp, vp, P(D)], C.c_int),
+            "adg_ensemble_stats": ([vp, vp, vp, P(I32), I32, P(D)], C.c_int),
             "adg_delay_schedule": ([P(adg_problem), I64, I64, P(I32)], C.c_int),
             "adg_destroy": ([vp], C.c_int),
         }
@@ -176,6 +177,14 @@ def adg_error_stats(ctx, d_u: int, d_ref: int, n_probs: int):
     out = (C.c_double * (3 * n_probs))()
     check(lib().adg_error_stats(ctx, C.c_void_p(d_u), C.c_void_p(d_ref), out), "adg_error_stats")
     return [tuple(out[3 * i:3 * i + 3]) for i in range(n_probs)]
+
+
+def adg_ensemble_stats(ctx, d_u: int, d_ref: int, group_of, n_groups: int):
+    n = len(group_of)
+    g = (C.c_int32 * n)(*group_of)
+    out = (C.c_double * (4 * n_groups))()
+    check(lib().adg_ensemble_stats(ctx, C.c_void_p(d_u), C.c_void_p(d_ref), g, n_groups, out), "adg_ensemble_stats")
+    return [tuple(out[4 * i:4 * i + 4]) for i in range(n_groups)]
 
 
 def adg_delay_schedule(prob: adg_problem, step0: int, n_steps: int, n_stages: int, n_pe: int):

@@ -218,6 +218,7 @@ int validate(const adg_problem* probs, int32_t n) {
 
 struct Layout {
   int64_t probs, work_f, work_s, first_s, ctr, ring, atsum, atk, state2, y0, y1, acc, part, stats_out;
+  int64_t groups, gstats;  // ensemble statistics: group CSR (2n+1 int32) and 4 doubles per group
   // adjoint recording (-1 if not recording)
   int64_t ckpt, useg, ybuf, lam, q, adjring, cpart;
   int64_t total;
@@ -277,6 +278,8 @@ Layout make_layout(const adg_problem* probs, int32_t n, const adg_options* opt, 
   L.acc = (kern == ADG_KERNEL_STAGE || rec) ? take(8 * tot) : -1;
   L.part = take(3 * 8 * nws);
   L.stats_out = take(3 * 8 * (int64_t)n);
+  L.groups = take(4 * (2 * (int64_t)n + 1));
+  L.gstats = take(4 * 8 * (int64_t)n);
   L.n_rec = n_rec;
   L.ckpt_every = (opt && opt->ckpt_every > 0) ? opt->ckpt_every : 64;
   L.n_ckpt = rec ? (n_rec + L.ckpt_every - 1) / L.ckpt_every : 0;
@@ -733,6 +736,35 @@ int adg_error_stats(adg_ctx* c, const double* d_u, const double* d_ref, double* 
   double* dout = (double*)(c->ws + c->L.stats_out);
   ADG_HIP(launch_stats(c->stage_args(), d_u, d_ref, part, (const int32_t*)(c->ws + c->L.first_s), n, dout, c->stream));
   ADG_HIP(hipMemcpyAsync(h_out, dout, 3 * sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
+  ADG_HIP(hipStreamSynchronize(c->stream));
+  return ADG_OK;
+}
+
+int adg_ensemble_stats(adg_ctx* c, const double* d_u, const double* d_ref, const int32_t* h_group_of,
+                       int32_t n_groups, double* h_out) {
+  if (!c || !d_u || !d_ref || !h_group_of || !h_out) return fail(ADG_E_INVALID, "null argument");
+  const int32_t n = (int32_t)c->probs.size();
+  if (n_groups < 1 || n_groups > n) return fail(ADG_E_INVALID, "n_groups must be in 1..n_probs");
+  std::vector<int32_t> csr(2 * (size_t)n + 1, 0);  // [gstart (n_groups+1) | members (n)]
+  std::vector<int32_t> count(n_groups, 0);
+  for (int32_t i = 0; i < n; ++i) {
+    if (h_group_of[i] < 0 || h_group_of[i] >= n_groups) return fail(ADG_E_INVALID, "group index out of range");
+    ++count[h_group_of[i]];
+  }
+  int32_t* gstart = csr.data();
+  int32_t* members = csr.data() + n + 1;
+  for (int32_t g = 0; g < n_groups; ++g) gstart[g + 1] = gstart[g] + count[g];
+  std::vector<int32_t> fill(gstart, gstart + n_groups);
+  for (int32_t i = 0; i < n; ++i) members[fill[h_group_of[i]]++] = i;
+  int32_t* d_csr = (int32_t*)(c->ws + c->L.groups);
+  double* part = (double*)(c->ws + c->L.part);
+  double* pstats = (double*)(c->ws + c->L.stats_out);
+  double* gout = (double*)(c->ws + c->L.gstats);
+  ADG_HIP(hipMemcpyAsync(d_csr, csr.data(), 4 * csr.size(), hipMemcpyHostToDevice, c->stream));
+  ADG_HIP(launch_stats(c->stage_args(), d_u, d_ref, part, (const int32_t*)(c->ws + c->L.first_s), n, pstats,
+                       c->stream));
+  ADG_HIP(launch_group_stats(pstats, d_csr, d_csr + n + 1, n_groups, gout, c->stream));
+  ADG_HIP(hipMemcpyAsync(h_out, gout, 4 * sizeof(double) * n_groups, hipMemcpyDeviceToHost, c->stream));
   ADG_HIP(hipStreamSynchronize(c->stream));
   return ADG_OK;
 }

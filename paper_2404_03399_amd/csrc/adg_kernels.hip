@@ -727,6 +727,39 @@ __global__ __launch_bounds__(kBlock) void k_stats_final(const DevProblem* __rest
   }
 }
 
+// One workgroup per group: two passes over the group's problems in list
+// order (mean, then mean squared deviation) of <E> and of max|u - ref|.
+__global__ void k_group_stats(const double* __restrict__ pstats, const int32_t* __restrict__ gstart,
+                              const int32_t* __restrict__ gmembers, double* __restrict__ out) {
+  if (threadIdx.x != 0) return;
+  const int g = blockIdx.x;
+  const int32_t b = gstart[g], e = gstart[g + 1];
+  const double m = (double)(e - b);
+  double s0 = 0.0, s1 = 0.0;
+  for (int32_t i = b; i < e; ++i) {
+    s0 += pstats[3 * gmembers[i] + 0];
+    s1 += pstats[3 * gmembers[i] + 1];
+  }
+  const double mean0 = e > b ? s0 / m : 0.0, mean1 = e > b ? s1 / m : 0.0;
+  double v0 = 0.0, v1 = 0.0;
+  for (int32_t i = b; i < e; ++i) {
+    const double d0 = pstats[3 * gmembers[i] + 0] - mean0;
+    const double d1 = pstats[3 * gmembers[i] + 1] - mean1;
+    v0 += d0 * d0;
+    v1 += d1 * d1;
+  }
+  out[4 * g + 0] = mean0;
+  out[4 * g + 1] = e > b ? v0 / m : 0.0;
+  out[4 * g + 2] = mean1;
+  out[4 * g + 3] = e > b ? v1 / m : 0.0;
+}
+
+hipError_t launch_group_stats(const double* pstats, const int32_t* gstart, const int32_t* gmembers, int32_t n_groups,
+                              double* out, hipStream_t stream) {
+  hipLaunchKernelGGL(k_group_stats, dim3(n_groups), dim3(64), 0, stream, pstats, gstart, gmembers, out);
+  return hipGetLastError();
+}
+
 __global__ __launch_bounds__(kBlock) void k_check_finite(const DevProblem* __restrict__ probs,
                                                          const WorkItem* __restrict__ work,
                                                          const double* __restrict__ u, int64_t* __restrict__ ctr) {

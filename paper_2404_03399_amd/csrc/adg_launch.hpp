@@ -61,6 +61,11 @@ hipError_t launch_advance(int64_t* ctr, int64_t n_steps, hipStream_t stream);
 hipError_t launch_stats(const StepArgs& a, const double* u, const double* ref, double* partials,
                         const int32_t* first_item, int32_t n_probs, double* out, hipStream_t stream);
 
+// Per-group mean / variance of the per-problem statistics (3 doubles per
+// problem: mean |u-ref|, max |u-ref|, integral) -> 4 doubles per group.
+hipError_t launch_group_stats(const double* pstats, const int32_t* gstart, const int32_t* gmembers, int32_t n_groups,
+                              double* out, hipStream_t stream);
+
 // Sets ctr[2] = 1 if any owned state entry is NaN or Inf.
 hipError_t launch_check_finite(const StepArgs& a, const double* u, hipStream_t stream);
 

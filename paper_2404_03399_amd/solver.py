@@ -163,6 +163,21 @@ class Solver:
     def error_stats(self, u: torch.Tensor, ref: torch.Tensor):
         return adg.adg_error_stats(self.ctx, u.data_ptr(), ref.data_ptr(), len(self.probs))
 
+    def ensemble_stats(self, u: torch.Tensor, ref: torch.Tensor, group_of, n_groups: int):
+        """Per group: (mean <E>, var <E>, mean max-err, var max-err)."""
+        return adg.adg_ensemble_stats(self.ctx, u.data_ptr(), ref.data_ptr(), list(group_of), n_groups)
+
+    def exact_advection_state(self, t: float) -> torch.Tensor:
+        """Nodal values of the exact linear-advection solution u0(x - a t)."""
+        u = self.empty_state()
+        for i, w in enumerate(self.workloads):
+            x = self.nodes(i) - w.speed * t
+            v = torch.full_like(x, w.ic.offset)
+            for k, a, ph in zip(w.ic.kappa, w.ic.amp, w.ic.phase):
+                v = v + a * torch.sin(k * x + ph)
+            self.view(u, i).copy_(v)
+        return u
+
     def delay_schedule(self, i: int, step0: int, n_steps: int):
         w = self.workloads[i]
         return adg.adg_delay_schedule(self.probs[i], step0, n_steps, adg.RK_STAGES[w.rk], w.n_pe)

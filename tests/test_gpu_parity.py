@@ -261,3 +261,48 @@ def test_check_finite_reports_nan(torch_cuda):
         s.run(u, 1, graph=False, check_finite=True)
     assert ei.value.code == adg.ADG_E_NONFINITE
     s.close()
+
+
+def test_ensemble_stats_match_oracle(torch_cuda):
+    """Batched ensemble (meshes x delay realizations in one context): every
+    problem matches its own oracle run, and the per-mesh mean / variance of
+    the spatially averaged error over realizations matches the oracle's
+    statistics (Sec. 4.3 averages)."""
+    torch = torch_cuda
+    from paper_2404_03399_amd.solver import Solver
+    from oracle import basis, exact
+    ws = W.c4_ensemble(n_meshes=3, n_real=5, n_steps=40, log2_min=7, log2_max=9, mesh_seed=1)
+    group = [int(w.name.split("_")[1][1:]) for w in ws]
+    n = 40
+    u0s = [stepper.initial_state(w) for w in ws]
+    _say(f"ensemble {len(ws)} problems, {n} steps")
+    s = Solver(ws)
+    u = s.pack(u0s)
+    s.run(u, n, graph=True)
+    refs = [exact.solution(w, basis.element_nodes(w.x_left, w.length, w.n_elem, w.degree), n * w.dt) for w in ws]
+    ref = s.pack(refs)
+    got = s.ensemble_stats(u, ref, group, 3)
+    outs = s.unpack(u)
+    s.close()
+    per, per_gpu, slacks = [], [], []
+    for w, u0, o, rf in zip(ws, u0s, outs, refs):
+        oref = oracle_run(w, u0, n)
+        assert stats.rel_l2(o, oref) <= TOL
+        # |mean|a-r| - mean|b-r|| <= max|a-b| (triangle inequality)
+        slack = stats.max_abs(o, oref)
+        slacks.append(slack)
+        assert abs(stats.mean_abs(o, rf) - stats.mean_abs(oref, rf)) <= slack
+        per.append((stats.mean_abs(oref, rf), stats.max_abs(oref, rf)))
+        per_gpu.append((stats.mean_abs(o, rf), stats.max_abs(o, rf)))
+    for g in range(3):
+        vals = [per_gpu[i] for i in range(len(ws)) if group[i] == g]
+        m0, v0 = stats.ensemble_mean_var([v[0] for v in vals])
+        m1, v1 = stats.ensemble_mean_var([v[1] for v in vals])
+        # the kernel's two-pass statistics of the GPU errors
+        assert abs(got[g][0] - m0) <= 1e-13 * m0 and abs(got[g][2] - m1) <= 1e-13 * m1
+        assert abs(got[g][1] - v0) <= 1e-12 * (m0 * m0 + v0)
+        assert abs(got[g][3] - v1) <= 1e-12 * (m1 * m1 + v1)
+        # and the oracle runs' ensemble mean within the solution-parity slack
+        om0, _ = stats.ensemble_mean_var([per[i][0] for i in range(len(ws)) if group[i] == g])
+        gslack = max(slacks[i] for i in range(len(ws)) if group[i] == g)
+        assert abs(got[g][0] - om0) <= gslack + 1e-13 * om0
