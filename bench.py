@@ -49,7 +49,7 @@ def ring_bytes_per_step(w) -> float:
 def read_traffic(workload_name: str):
     """HBM bytes per launch from the committed rocprofv3 PMC summary, if it was
     taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", "pmc_fused_step_c2.md")
+    path = os.path.join(ROOT, "profiles", "pmc_fused_step_advection_2p20.md")
     if not os.path.exists(path):
         return None
     text = open(path).read()
@@ -185,6 +185,8 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the one-context-per-problem ensemble run")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -259,6 +261,14 @@ def main():
         ex["n2^24_hbm_frac"] = (BYTES_PER_DOF_STEP_FUSED * d24 + ring_bytes_per_step(wl)) / (g / 100) / 1e9 / HBM_PEAK_GBS
         so.close()
         out["extras"] = ex
+    if args.calib_copy_mib > 0:
+        n = args.calib_copy_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["calib_copy_bytes_each_way"] = n * 8
     if not args.no_adjoint:
         out["adjoint"] = bench_adjoint(torch, W, Solver, args.adjoint_steps, args.n_elem)
     if not args.no_ensemble:
