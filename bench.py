@@ -178,6 +178,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--kernel", default="fused", choices=["fused", "stage"])
     ap.add_argument("--n-elem", type=int, default=1 << 20)
+    ap.add_argument("--lane-elems", type=int, default=0, help="fused kernel elements per lane (0: default)")
     ap.add_argument("--extras", action="store_true", help="also time DG/ADG, per-stage kernel, 2^24 mesh")
     ap.add_argument("--adjoint-steps", type=int, default=2000)
     ap.add_argument("--ensemble-real", type=int, default=256)
@@ -197,7 +198,7 @@ def main():
     from paper_2404_03399_amd.solver import Solver
 
     w = W.c2_advection_large("adg_at", n_elem=args.n_elem)
-    s = Solver(w, kernel=args.kernel)
+    s = Solver(w, kernel=args.kernel, lane_elems=args.lane_elems)
     u = s.initial_state()
     gpu_s, wall = time_solver(torch, s, u, args.steps, args.warmup)
     dofs = w.n_elem * (w.degree + 1)

@@ -104,7 +104,8 @@ typedef struct adg_problem {
 typedef struct adg_options {
   int64_t ckpt_every;          /* adjoint checkpoint interval in steps; 0 -> 64 */
   int32_t kernel;              /* adg_kernel; AUTO -> FUSED */
-  int32_t tile_elems;          /* owned elements per workgroup for the fused kernel; 0 -> default */
+  int32_t lane_elems;          /* fused kernel: consecutive elements per lane, 1, 2 or 4 (<= every
+                                  asynchronous problem's pe_size); 0 -> 1 */
   uint32_t flags;              /* reserved, 0 */
   uint32_t reserved;
 } adg_options;

@@ -235,6 +235,17 @@ int64_t depth_of(const adg_problem& p, int64_t n_rec) {
   return n_rec > 0 ? n_rec + p.n_delays + q_of(p) : (int64_t)p.n_delays + q_of(p) - 1;
 }
 
+// Elements per lane of the fused kernel (0 if the request is invalid).
+int lane_elems_of(const adg_problem* probs, int32_t n, const adg_options* opt) {
+  int64_t min_pes = (int64_t)1 << 62;
+  for (int32_t i = 0; i < n; ++i)
+    if (async_of(probs[i])) min_pes = std::min(min_pes, probs[i].pe_size);
+  const int req = opt ? opt->lane_elems : 0;
+  if (req == 0) return 1;
+  if (req != 1 && req != 2 && req != 4) return 0;
+  return req <= min_pes ? req : 0;
+}
+
 int kernel_of(const adg_options* opt) {
   if (!opt || opt->kernel == ADG_KERNEL_AUTO) return ADG_KERNEL_FUSED;
   return opt->kernel;
@@ -243,7 +254,7 @@ int kernel_of(const adg_options* opt) {
 Layout make_layout(const adg_problem* probs, int32_t n, const adg_options* opt, int64_t n_rec) {
   Layout L{};
   const int S = rk_stages((int)probs[0].rk);
-  const int T = fused_tile((int)probs[0].rk);
+  const int T = fused_tile((int)probs[0].rk, std::max(1, lane_elems_of(probs, n, opt)));
   int64_t nwf = 0, nws = 0, tot = 0, ring = 0, at = 0;
   for (int32_t i = 0; i < n; ++i) {
     const adg_problem& p = probs[i];
@@ -306,6 +317,7 @@ struct adg_ctx {
   adg_options opt{};
   int kernel = ADG_KERNEL_FUSED;
   int rk = 0, phys = 0, S = 0;
+  int fused_phys = 0;  // phys of the fused kernel (upwind with a > 0 specialised)
   hipStream_t stream = nullptr;
   char* ws = nullptr;
   Layout L{};
@@ -319,6 +331,7 @@ struct adg_ctx {
 
   int32_t group[5] = {0, 0, 0, 0, 0};
   int32_t grid[4] = {1, 1, 1, 1};
+  int32_t lane_elems = 2;
 
   StepArgs base_args(int64_t work_off, int32_t n_work) const {
     StepArgs a{};
@@ -331,6 +344,7 @@ struct adg_ctx {
     a.atk = (int32_t*)(ws + L.atk);
     for (int i = 0; i < 5; ++i) a.group[i] = group[i];
     for (int i = 0; i < 4; ++i) a.grid[i] = grid[i];
+    a.lane_elems = lane_elems;
     return a;
   }
   StepArgs fused_args() const { return base_args(L.work_f, L.n_work_f); }
@@ -345,7 +359,7 @@ namespace {
 int enqueue_step(adg_ctx* c, double** cur, double** other, int32_t step_offset, hipStream_t st) {
   if (c->kernel == ADG_KERNEL_FUSED) {
     const StepArgs a = c->fused_args();
-    ADG_HIP(launch_fused_step(c->rk, c->phys, a, *cur, *other, step_offset, st));
+    ADG_HIP(launch_fused_step(c->rk, c->fused_phys, a, *cur, *other, step_offset, st));
     std::swap(*cur, *other);
     return ADG_OK;
   }
@@ -449,6 +463,8 @@ int adg_workspace_size(const adg_problem* probs, int32_t n_probs, const adg_opti
   if (opt && opt->ckpt_every < 0) return fail(ADG_E_INVALID, "ckpt_every < 0");
   const int k = kernel_of(opt);
   if (k != ADG_KERNEL_FUSED && k != ADG_KERNEL_STAGE) return fail(ADG_E_INVALID, "unknown kernel family");
+  if (lane_elems_of(probs, n_probs, opt) == 0)
+    return fail(ADG_E_INVALID, "lane_elems must be 1, 2 or 4 and not exceed the PE size");
   *bytes_out = make_layout(probs, n_probs, opt, n_steps_record).total;
   return ADG_OK;
 }
@@ -462,7 +478,6 @@ int adg_init(adg_ctx** out, const adg_problem* probs, int32_t n_probs, const adg
   if (rc) return rc;
   if (!d_workspace || workspace_bytes < need) return fail(ADG_E_WORKSPACE, "workspace too small: need " + std::to_string(need));
   if (((uintptr_t)d_workspace) % kAlign) return fail(ADG_E_WORKSPACE, "workspace must be 256-byte aligned");
-  if (opt && opt->tile_elems != 0) return fail(ADG_E_UNSUPPORTED, "tile_elems override is not available");
 
   adg_ctx* c = new adg_ctx();
   c->probs.assign(probs, probs + n_probs);
@@ -470,6 +485,12 @@ int adg_init(adg_ctx** out, const adg_problem* probs, int32_t n_probs, const adg
   c->kernel = kernel_of(opt);
   c->rk = (int)probs[0].rk;
   c->phys = phys_of(probs[0]);
+  c->fused_phys = c->phys;
+  if (c->phys == PHYS_ADV_UPWIND) {
+    bool pos = true;
+    for (int32_t i = 0; i < n_probs; ++i) pos = pos && probs[i].speed > 0.0;
+    if (pos) c->fused_phys = PHYS_ADV_UPWIND_POS;
+  }
   c->S = rk_stages(c->rk);
   c->stream = (hipStream_t)hip_stream;
   c->ws = (char*)d_workspace;
@@ -525,7 +546,11 @@ int adg_init(adg_ctx** out, const adg_problem* probs, int32_t n_probs, const adg
         d.Kl[i] = d.two_over_dx * d.lift_l[i];
         d.Kr[i] = d.two_over_dx * d.lift_r[i];
       }
+      for (int i = 0; i < kMaxNp * kMaxNp; ++i) d.Kdu[i] = d.Kd[i];
+      const int pn = (int)p.degree;
+      for (int i = 0; i <= pn; ++i) d.Kdu[i * kMaxNp + pn] -= d.Kr[i] * p.speed;
     }
+    d.depth_div = make_fast_div((uint32_t)d.depth);
     for (int k = 0; k < d.n_delays; ++k)
       for (int j = 0; j < d.q; ++j) d.atc[k][j] = at_coefficient(d.q, k, j);
   }
@@ -533,7 +558,8 @@ int adg_init(adg_ctx** out, const adg_problem* probs, int32_t n_probs, const adg
   std::vector<int32_t> order(n_probs);
   for (int32_t i = 0; i < n_probs; ++i) order[i] = i;
   std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return probs[a].degree > probs[b].degree; });
-  const int T = fused_tile(c->rk);
+  c->lane_elems = lane_elems_of(probs, n_probs, opt);
+  const int T = fused_tile(c->rk, c->lane_elems);
   std::vector<WorkItem> wf, ws_;
   std::vector<int32_t> first(n_probs + 1, 0);
   wf.reserve(c->L.n_work_f);
@@ -590,6 +616,7 @@ int adg_step_count(const adg_ctx* c, int64_t* steps) {
 int adg_run(adg_ctx* c, double* d_u, int64_t n_steps, uint32_t flags) {
   if (!c || !d_u) return fail(ADG_E_INVALID, "null argument");
   if (n_steps < 0) return fail(ADG_E_INVALID, "n_steps < 0");
+  if (c->steps + n_steps >= ((int64_t)1 << 31)) return fail(ADG_E_INVALID, "step index would exceed 2^31 - 1");
   if (flags & ~(ADG_RUN_GRAPH | ADG_RUN_RECORD | ADG_RUN_CHECK_FINITE)) return fail(ADG_E_INVALID, "unknown flags");
   if (flags & ADG_RUN_RECORD) {
     if (c->L.n_rec <= 0) return fail(ADG_E_STATE, "context was created without a recording horizon");

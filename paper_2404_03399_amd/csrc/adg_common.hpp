@@ -11,7 +11,9 @@ constexpr int kMaxL = 8;      // delays 0..7
 constexpr int kMaxQ = 5;      // AT levels
 constexpr int kBlock = 256;   // threads per workgroup (4 wave64)
 
-enum Phys : int { PHYS_ADV_UPWIND = 0, PHYS_ADV_CENTRAL = 1, PHYS_BURGERS_LLF = 2 };
+// PHYS_ADV_UPWIND_POS: upwind advection with a > 0 in the fused kernel, which
+// folds the right-face flux a u_p into the volume operator.
+enum Phys : int { PHYS_ADV_UPWIND = 0, PHYS_ADV_CENTRAL = 1, PHYS_BURGERS_LLF = 2, PHYS_ADV_UPWIND_POS = 3 };
 enum Rk : int { RK_HEUN = 0, RK_SSP3 = 1, RK_RK4 = 2 };
 enum Scheme : int { SCH_DG = 0, SCH_ADG = 1, SCH_AT = 2 };
 
@@ -53,7 +55,7 @@ struct DevProblem {
   int64_t u_off;         // offset of the problem in the state vector
   int64_t ring_off;      // offset of the problem's delay ring (doubles)
   int64_t at_off;        // offset of the problem's AT sums ([2][P][S] doubles)
-  int64_t atk_off;       // offset of the problem's packed delays ([2][P] int32, 3 bits per stage)
+  int64_t atk_off;       // offset of the problem's delays ([2][P] words, byte s = stage s)
   int32_t np;            // degree + 1
   int32_t q;             // AT levels (1 for ADG)
   int32_t n_delays;      // L
@@ -80,6 +82,10 @@ struct DevProblem {
   double Kd[kMaxNp * kMaxNp];
   double Kl[kMaxNp];
   double Kr[kMaxNp];
+  // Kd with the interior upwind right-face term folded in (a > 0):
+  // Kdu[i][p] = Kd[i][p] - Kr[i] a, so Kd y - Kr (a y_p) = Kdu y.
+  double Kdu[kMaxNp * kMaxNp];
+  FastDiv depth_div;     // division by the ring depth (step indices < 2^31)
   double atc[kMaxL][kMaxQ];    // c_j(k), j < q, k < L
 };
 

@@ -28,6 +28,12 @@ struct Physics<PHYS_ADV_UPWIND> {
 };
 
 template <>
+struct Physics<PHYS_ADV_UPWIND_POS> {
+  __device__ static double f(double u, double a) { return a * u; }
+  __device__ static double fhat(double um, double, double a) { return a * um; }
+};
+
+template <>
 struct Physics<PHYS_ADV_CENTRAL> {
   __device__ static double f(double u, double a) { return a * u; }
   __device__ static double fhat(double um, double up, double a) { return a * (0.5 * um + 0.5 * up); }
@@ -150,28 +156,33 @@ __device__ __forceinline__ int wrap_elem(int x, int N) {
   return x;
 }
 
+// Same for -N <= x < 2N (one correction at most).
+__device__ __forceinline__ int wrap_once(int x, int N) {
+  const int y = x < 0 ? x + N : x;
+  return y >= N ? y - N : y;
+}
+
 // ------------------------------------------------------ fused step kernel ---
 constexpr int kMaxStages = 4;
-constexpr int kR = kElemsPerLane;
 
 // Lane shifts across the whole wave64 (DPP wave_shr:1 / wave_shl:1): lane l
-// receives lane l-1 (resp. l+1); the lane without a source receives 0.
+// receives lane l-1 (resp. l+1); the lane without a source receives 0
+// (bound_ctrl).
 __device__ __forceinline__ double lane_from_left(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x138, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x138, 0xf, 0xf, false);
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x138, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x138, 0xf, 0xf, true);
   return __hiloint2double(hi, lo);
 }
 __device__ __forceinline__ double lane_from_right(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x130, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x130, 0xf, 0xf, false);
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x130, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x130, 0xf, 0xf, true);
   return __hiloint2double(hi, lo);
 }
 
-// Per-lane PE-face records of the current step (written and read by the
-// same lane only).
+// Per-lane PE-face record of the current step (written and read by the same
+// lane only).  With R <= PE size a lane's R left faces hold at most one PE face.
 struct WaveSmem {
-  double at[kWavesPerBlock][kMaxStages][kR][kWave];
-  int32_t kp[kWavesPerBlock][kR][kWave];
+  double at[kWavesPerBlock][kMaxStages][kWave];
 };
 
 template <int NP, int PHYS>
@@ -189,10 +200,16 @@ __device__ __forceinline__ void folded_rhs(const DevProblem& P, const double (&y
   }
 }
 
+struct FusedPtrs {
+  double* __restrict__ ring;
+  double* __restrict__ atsum;
+  int32_t* __restrict__ atk;
+};
+
 // One wave64 = one tile of T owned elements plus HL halo lanes per side,
-// kR consecutive elements per lane (16-byte loads and stores).  Each stage
-// shrinks the valid range by one element per side, so after S stages the
-// owned lanes are exact.  Halo elements are recomputed with the same
+// R consecutive elements per lane (16- or 32-byte accesses per plane).  Each
+// stage shrinks the valid range by one element per side, so after S stages
+// the owned lanes are exact.  Halo elements are recomputed with the same
 // instructions as by their owners, so a face shared by two waves gets a
 // bitwise-identical flux on both sides.  Each lane computes the fluxes of
 // the left faces of its elements; the right face of its last element is the
@@ -205,152 +222,191 @@ __device__ __forceinline__ void folded_rhs(const DevProblem& P, const double (&y
 // sum_j c_j(k) F^{n+1-k-j} over past levels (all <= n when k >= 1) into record
 // parity (n+1)&1.  Both neighbours of the face read parity n&1 at step n; a
 // delay of 0 selects the synchronous level-n flux.
-struct FusedPtrs {
-  double* __restrict__ ring;
-  double* __restrict__ atsum;
-  int32_t* __restrict__ atk;
-};
-
-template <int NP, int RK, int PHYS>
+template <int NP, int RK, int PHYS, int R>
 __device__ __forceinline__ void wave_tile(const DevProblem& P, const WorkItem wi, const FusedPtrs& A, int64_t n,
                                           const double* __restrict__ uin, double* __restrict__ uout, WaveSmem& sm,
                                           int wv, int lane) {
   constexpr int S = rk_stages(RK);
-  constexpr int HL = halo_lanes(RK);
-  constexpr int T = fused_tile(RK);
+  constexpr int HL = halo_lanes(RK, R);
+  constexpr int T = fused_tile(RK, R);
   const int N = (int)P.n_elem;
   const int e0 = wi.tile * T;
   const int teff = (N - e0) < T ? (N - e0) : T;
-  const int xb = e0 - kR * HL;                       // element position of lane 0, element 0
-  const bool fast = xb >= 0 && xb + kR * kWave <= N;  // no periodic wrap inside this wave
+  const int xb = e0 - R * HL;  // element position of lane 0, element 0 (a multiple of R)
+  // With N a multiple of R a lane's R elements never straddle the periodic
+  // wrap, so one R*8-byte access per plane serves them all.
+  const bool grouped = R > 1 && (N % R) == 0;
   const int64_t ld = P.ld;
   const double* __restrict__ u = uin + P.u_off;
   const bool lane_owned = lane >= HL && lane < kWave - HL;
 
-  int e[kR];
-  bool owned[kR];
+  const bool tiny = N < kWave * R;  // the wave's extent may wrap more than once
+  int e[R];
+  bool owned[R];
 #pragma unroll
-  for (int r = 0; r < kR; ++r) {
-    const int x = xb + kR * lane + r;
-    e[r] = fast ? x : wrap_elem(x, N);
+  for (int r = 0; r < R; ++r) {
+    const int x = xb + R * lane + r;
+    e[r] = tiny ? wrap_elem(x, N) : wrap_once(x, N);
     owned[r] = lane_owned && (x - e0) < teff;
   }
-  double u0[kR][NP];
-  if (fast) {
+  double u0[R][NP];
+  if (grouped) {
+    const double2* __restrict__ u2 = reinterpret_cast<const double2*>(__builtin_assume_aligned(u, 16));
 #pragma unroll
-    for (int j = 0; j < NP; ++j) {
-      const double2 v = *reinterpret_cast<const double2*>(u + j * ld + e[0]);
-      u0[0][j] = v.x;
-      u0[1][j] = v.y;
-    }
+    for (int j = 0; j < NP; ++j)
+#pragma unroll
+      for (int r = 0; r < R; r += 2) {
+        const double2 v = u2[(j * ld + e[0] + r) >> 1];
+        u0[r][j] = v.x;
+        u0[r + 1 < R ? r + 1 : r][j] = R > 1 ? v.y : v.x;
+      }
   } else {
 #pragma unroll
-    for (int r = 0; r < kR; ++r)
+    for (int r = 0; r < R; ++r)
 #pragma unroll
       for (int j = 0; j < NP; ++j) u0[r][j] = u[j * ld + e[r]];
   }
 
-  // PE faces among this lane's left faces and their records for step n
+  // the PE face among this lane's left faces (if any) and its step-n record
   const int par = (int)(n & 1);
-  bool pe[kR];
-  uint32_t b[kR];
-  int32_t kp[kR];
-#pragma unroll
-  for (int r = 0; r < kR; ++r) {
-    pe[r] = false;
-    b[r] = 0;
-    kp[r] = 0;
-  }
+  bool pe[R];           // element r's left face is a PE face (at most one r)
+  bool pe_right = false;  // the right face of element R-1 is a PE face
+  bool any_pe = false;
+  uint32_t b = 0;       // its boundary index
+  int32_t kp = 0;       // delays of step n, byte s = stage s
   int depth = 1, slot_n = 0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) pe[r] = false;
   if (P.async_faces) {
     depth = P.depth;
-    slot_n = (int)(n % (int64_t)depth);
+    const uint32_t n32 = (uint32_t)n;  // step indices stay below 2^31
+    slot_n = (int)(n32 - fast_div(n32, P.depth_div) * (uint32_t)depth);
     const uint32_t pes = P.pe_div.d;
 #pragma unroll
-    for (int r = 0; r < kR; ++r) {
-      b[r] = fast_div((uint32_t)e[r], P.pe_div);
-      pe[r] = (uint32_t)e[r] == b[r] * pes;
-      if (pe[r]) {
-        kp[r] = A.atk[P.atk_off + (int64_t)par * P.n_pe + b[r]];
-        const double* __restrict__ src = A.atsum + P.at_off + ((int64_t)par * P.n_pe + b[r]) * S;
+    for (int r = 0; r < R; ++r) {
+      const uint32_t br = fast_div((uint32_t)e[r], P.pe_div);
+      pe[r] = (uint32_t)e[r] == br * pes;
+      if (pe[r]) b = br;
+      any_pe = any_pe || pe[r];
+    }
+    const uint32_t e1 = (e[R - 1] + 1 == N) ? 0u : (uint32_t)(e[R - 1] + 1);
+    pe_right = e1 == fast_div(e1, P.pe_div) * pes;
+    if (any_pe) {
+      kp = A.atk[P.atk_off + (int64_t)par * P.n_pe + b];
+      const double* __restrict__ src = A.atsum + P.at_off + ((int64_t)par * P.n_pe + b) * S;
 #pragma unroll
-        for (int s = 0; s < S; ++s) sm.at[wv][s][r][lane] = src[s];
-      }
+      for (int s = 0; s < S; ++s) sm.at[wv][s][lane] = src[s];
     }
   }
 
-  double y[kR][NP], ks[kR][NP], k[NP];
+  double y[R][NP], ks[R][NP], k[NP];
 #pragma unroll
-  for (int r = 0; r < kR; ++r)
+  for (int r = 0; r < R; ++r)
 #pragma unroll
     for (int j = 0; j < NP; ++j) y[r][j] = u0[r][j];
   const double a = P.speed;
   const double dt = P.dt;
 
+  // upwind, a > 0: the interior right-face flux a u_p is part of Kdu; only a
+  // delayed PE face on the right adds -Kr (F_right - a u_p)
+  const bool wave_pe_right = PHYS == PHYS_ADV_UPWIND_POS && __ballot(pe_right) != 0;
+
 #pragma unroll
   for (int s = 0; s < S; ++s) {
-    double F[kR];
-    const double um = lane_from_left(y[kR - 1][NP - 1]);
+    double F[R];
+    const double um = lane_from_left(y[R - 1][NP - 1]);
     F[0] = Physics<PHYS>::fhat(um, y[0][0], a);
 #pragma unroll
-    for (int r = 1; r < kR; ++r) F[r] = Physics<PHYS>::fhat(y[r - 1][NP - 1], y[r][0], a);
+    for (int r = 1; r < R; ++r) F[r] = Physics<PHYS>::fhat(y[r - 1][NP - 1], y[r][0], a);
 #pragma unroll
-    for (int r = 0; r < kR; ++r) {
+    for (int r = 0; r < R; ++r) {
       if (pe[r]) {
-        if (owned[r]) A.ring[P.ring_off + ((int64_t)b[r] * S + s) * depth + slot_n] = F[r];
-        if ((kp[r] >> (3 * s)) & 7) F[r] = sm.at[wv][s][r][lane];
+        if (owned[r]) A.ring[P.ring_off + ((int64_t)b * S + s) * depth + slot_n] = F[r];
+        if ((kp >> (8 * s)) & 0xff) F[r] = sm.at[wv][s][lane];
       }
     }
-    const double f_last = lane_from_right(F[0]);
+    if constexpr (PHYS == PHYS_ADV_UPWIND_POS) {
+      double f_last = 0.0;
+      if (wave_pe_right) f_last = lane_from_right(F[0]);
 #pragma unroll
-    for (int r = 0; r < kR; ++r) {
-      folded_rhs<NP, PHYS>(P, y[r], F[r], r + 1 < kR ? F[r + 1] : f_last, k);
-      rk_update<NP, RK>(s, dt, u0[r], y[r], ks[r], k);
+      for (int r = 0; r < R; ++r) {
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+          double v = P.Kl[i] * F[r];
+#pragma unroll
+          for (int j = 0; j < NP; ++j) v += P.Kdu[i * kMaxNp + j] * y[r][j];
+          k[i] = v;
+        }
+        const bool right_pe = r + 1 < R ? pe[r + 1] : pe_right;
+        if (right_pe) {
+          const double fr = r + 1 < R ? F[r + 1] : f_last;
+          const double corr = fr - a * y[r][NP - 1];  // exactly 0 unless the face is delayed
+#pragma unroll
+          for (int i = 0; i < NP; ++i) k[i] -= P.Kr[i] * corr;
+        }
+        rk_update<NP, RK>(s, dt, u0[r], y[r], ks[r], k);
+      }
+    } else {
+      const double f_last = lane_from_right(F[0]);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        folded_rhs<NP, PHYS>(P, y[r], F[r], r + 1 < R ? F[r + 1] : f_last, k);
+        rk_update<NP, RK>(s, dt, u0[r], y[r], ks[r], k);
+      }
     }
   }
 
   double* __restrict__ uo = uout + P.u_off;
-  if (fast && owned[0] && owned[kR - 1]) {
+  bool all_owned = true;
 #pragma unroll
-    for (int j = 0; j < NP; ++j) {
-      double2 v;
-      v.x = y[0][j];
-      v.y = y[1][j];
-      *reinterpret_cast<double2*>(uo + j * ld + e[0]) = v;
-    }
+  for (int r = 0; r < R; ++r) all_owned = all_owned && owned[r];
+  if (grouped && all_owned) {
+    double2* __restrict__ uo2 = reinterpret_cast<double2*>(__builtin_assume_aligned(uo, 16));
+#pragma unroll
+    for (int j = 0; j < NP; ++j)
+#pragma unroll
+      for (int r = 0; r < R; r += 2) {
+        double2 v;
+        v.x = y[r][j];
+        v.y = y[r + 1 < R ? r + 1 : r][j];
+        uo2[(j * ld + e[0] + r) >> 1] = v;
+      }
   } else {
 #pragma unroll
-    for (int r = 0; r < kR; ++r)
+    for (int r = 0; r < R; ++r)
       if (owned[r])
 #pragma unroll
         for (int j = 0; j < NP; ++j) uo[j * ld + e[r]] = y[r][j];
   }
 
-  // owners of PE faces: records of step n+1
+  // owners of PE faces: records of step n+1, one lane per (face, stage).
+  // For each owned PE face of this wave (uniform loop over the owner mask),
+  // lanes 0..S-1 draw the stage's delay and sum the AT weights over the
+  // past levels, independently of each other.
+  bool own = false;
 #pragma unroll
-  for (int r = 0; r < kR; ++r) {
-    if (!(pe[r] && owned[r])) continue;
-    const int64_t n1 = n + 1;
-    const double* __restrict__ rb = A.ring + P.ring_off + (int64_t)b[r] * S * depth;
-    int32_t kpn = 0;
-    int kd = 0;
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-      if (s == 0 || P.per_stage) {
-        const uint64_t pre = delay_prefix(P.seed, n1, P.per_stage ? s : 0);
-        kd = clamp_delay(delay_from_prefix(pre, b[r], P.thr, P.n_delays), n1, P.q);
-      }
-      kpn |= kd << (3 * s);
+  for (int r = 0; r < R; ++r) own = own || (pe[r] && owned[r]);
+  uint64_t owners = __ballot(own);
+  while (owners) {
+    const int src = __builtin_ctzll(owners);
+    owners &= owners - 1;
+    const uint32_t bo = (uint32_t)__builtin_amdgcn_readlane((int)b, src);
+    if (lane < S) {
+      const int s = lane;
+      const int64_t n1 = n + 1;
+      const uint64_t pre = delay_prefix(P.seed, n1, P.per_stage ? s : 0);
+      const int kd = clamp_delay(delay_from_prefix(pre, bo, P.thr, P.n_delays), n1, P.q);
+      const double* __restrict__ rb = A.ring + P.ring_off + ((int64_t)bo * S + s) * depth;
       double acc = 0.0;
       for (int j = 0; kd > 0 && j < P.q; ++j)  // level n1 - kd - j = n - (kd + j - 1)
-        acc += P.atc[kd][j] * rb[s * depth + ring_slot(slot_n, kd + j - 1, depth)];
-      A.atsum[P.at_off + ((int64_t)(par ^ 1) * P.n_pe + b[r]) * S + s] = acc;
+        acc += P.atc[kd][j] * rb[ring_slot(slot_n, kd + j - 1, depth)];
+      A.atsum[P.at_off + ((int64_t)(par ^ 1) * P.n_pe + bo) * S + s] = acc;
+      reinterpret_cast<uint8_t*>(A.atk + P.atk_off + (int64_t)(par ^ 1) * P.n_pe + bo)[s] = (uint8_t)kd;
     }
-    A.atk[P.atk_off + (int64_t)(par ^ 1) * P.n_pe + b[r]] = kpn;
   }
 }
 
-template <int NP, int RK, int PHYS>
+template <int NP, int RK, int PHYS, int R>
 __global__ __launch_bounds__(kBlock) void k_fused_step(const DevProblem* __restrict__ probs,
                                                        const WorkItem* __restrict__ work,
                                                        const int64_t* __restrict__ ctr, double* __restrict__ ring,
@@ -365,7 +421,7 @@ __global__ __launch_bounds__(kBlock) void k_fused_step(const DevProblem* __restr
   const int64_t n = ctr[0] + step_offset;
   const WorkItem wi = work[w];
   const FusedPtrs A{ring, atsum, atk};
-  wave_tile<NP, RK, PHYS>(probs[wi.prob], wi, A, n, uin, uout, sm, wv, lane);
+  wave_tile<NP, RK, PHYS, R>(probs[wi.prob], wi, A, n, uin, uout, sm, wv, lane);
 }
 
 // ------------------------------------------------------ per-stage kernel ---
@@ -775,8 +831,21 @@ __global__ __launch_bounds__(kBlock) void k_check_finite(const DevProblem* __res
 // ---------------------------------------------------------------- launch ---
 template <int NP, int RK, int PHYS>
 static void fused_go(const StepArgs& a, int gi, const double* uin, double* uout, int32_t off, hipStream_t st) {
-  hipLaunchKernelGGL((k_fused_step<NP, RK, PHYS>), dim3(a.grid[gi]), dim3(kBlock), 0, st, a.probs, a.work, a.ctr,
-                     a.ring, a.atsum, a.atk, a.group[gi], a.group[gi + 1], uin, uout, off);
+  const dim3 g(a.grid[gi]), b(kBlock);
+  switch (a.lane_elems) {
+    case 1:
+      hipLaunchKernelGGL((k_fused_step<NP, RK, PHYS, 1>), g, b, 0, st, a.probs, a.work, a.ctr, a.ring, a.atsum, a.atk,
+                         a.group[gi], a.group[gi + 1], uin, uout, off);
+      break;
+    case 4:
+      hipLaunchKernelGGL((k_fused_step<NP, RK, PHYS, 4>), g, b, 0, st, a.probs, a.work, a.ctr, a.ring, a.atsum, a.atk,
+                         a.group[gi], a.group[gi + 1], uin, uout, off);
+      break;
+    default:
+      hipLaunchKernelGGL((k_fused_step<NP, RK, PHYS, 2>), g, b, 0, st, a.probs, a.work, a.ctr, a.ring, a.atsum, a.atk,
+                         a.group[gi], a.group[gi + 1], uin, uout, off);
+      break;
+  }
 }
 
 template <int RK, int PHYS>
@@ -792,6 +861,7 @@ template <int RK>
 static void fused_phys(int phys, const StepArgs& a, const double* uin, double* uout, int32_t off, hipStream_t st) {
   switch (phys) {
     case PHYS_ADV_UPWIND: fused_np<RK, PHYS_ADV_UPWIND>(a, uin, uout, off, st); break;
+    case PHYS_ADV_UPWIND_POS: fused_np<RK, PHYS_ADV_UPWIND_POS>(a, uin, uout, off, st); break;
     case PHYS_ADV_CENTRAL: fused_np<RK, PHYS_ADV_CENTRAL>(a, uin, uout, off, st); break;
     default: fused_np<RK, PHYS_BURGERS_LLF>(a, uin, uout, off, st); break;
   }

@@ -15,20 +15,20 @@ struct StepArgs {
   int32_t* atk;              // fused kernel: clamped delays, [2][P][S] per problem
   int32_t group[5];          // fused kernel: work-item ranges per degree (below)
   int32_t grid[4];           // fused kernel: workgroups per degree range
+  int32_t lane_elems;        // fused kernel: elements per lane (1, 2 or 4)
 };
 
 // Work items of the fused kernel are sorted by descending np; items with
 // np = 5, 4, 3, 2 occupy [group[0], group[1]), [group[1], group[2]),
 // [group[2], group[3]), [group[3], group[4]).
 
-// Fused step kernel geometry: one wave64 per work item, kElemsPerLane
-// consecutive elements per lane, halo of ceil(S / kElemsPerLane) lanes per
-// side; owned elements per work item:
+// Fused step kernel geometry: one wave64 per work item, R in {1, 2, 4}
+// consecutive elements per lane, halo of ceil(S / R) lanes per side; owned
+// elements per work item:
 constexpr int kWave = 64;
-constexpr int kElemsPerLane = 2;
 constexpr int kWavesPerBlock = kBlock / kWave;
-__host__ __device__ constexpr int halo_lanes(int rk) { return (rk_stages(rk) + kElemsPerLane - 1) / kElemsPerLane; }
-__host__ __device__ constexpr int fused_tile(int rk) { return kElemsPerLane * (kWave - 2 * halo_lanes(rk)); }
+__host__ __device__ constexpr int halo_lanes(int rk, int R) { return (rk_stages(rk) + R - 1) / R; }
+__host__ __device__ constexpr int fused_tile(int rk, int R) { return R * (kWave - 2 * halo_lanes(rk, R)); }
 
 // Workgroups of the fused kernel for n_work items (kWavesPerBlock per group).
 inline int fused_grid(int n_work) { return n_work < 1 ? 1 : (n_work + kWavesPerBlock - 1) / kWavesPerBlock; }

@@ -31,9 +31,9 @@ def torch_cuda():
     return torch
 
 
-def gpu_run(torch, w, u0, n_steps, kernel="fused", graph=True):
+def gpu_run(torch, w, u0, n_steps, kernel="fused", graph=True, lane_elems=0):
     from paper_2404_03399_amd.solver import Solver
-    s = Solver(w, kernel=kernel)
+    s = Solver(w, kernel=kernel, lane_elems=lane_elems)
     u = s.pack(u0)
     s.run(u, n_steps, graph=graph)
     torch.cuda.synchronize()
@@ -47,12 +47,12 @@ def oracle_run(w, u0, n_steps):
     return stepper.Stepper(w).run(u0, n_steps)
 
 
-def _check(torch, w, n_steps, kernel="fused", graph=True, tol=TOL):
+def _check(torch, w, n_steps, kernel="fused", graph=True, tol=TOL, lane_elems=0):
     _say(f"{w.name} p={w.degree} rk={w.rk} flux={w.flux} N={w.n_elem} pe={w.pe_size} "
-         f"steps={n_steps} kernel={kernel} graph={graph}")
+         f"steps={n_steps} kernel={kernel} graph={graph} lane_elems={lane_elems}")
     u0 = stepper.initial_state(w)
     ref = oracle_run(w, u0, n_steps)
-    got = gpu_run(torch, w, u0, n_steps, kernel, graph)
+    got = gpu_run(torch, w, u0, n_steps, kernel, graph, lane_elems)
     err = stats.rel_l2(got, ref)
     assert err <= tol, (w.name, err)
     return got, ref
@@ -138,6 +138,28 @@ def test_edge_meshes(torch_cuda, ne, pe, p):
                    seed=3, dt=0.001 * W.TWO_PI / ne, ic=W.SINE)
     for kernel in ("fused", "stage"):
         _check(torch_cuda, w, 20, kernel, graph=False)
+
+
+@pytest.mark.parametrize("lane_elems", [1, 2, 4])
+@pytest.mark.parametrize("ne,pe,p,rk,phys", [(4096, 256, 3, "rk4", "upwind"), (1001, 77, 2, "ssprk3", "central"),
+                                             (1002, 6, 1, "heun", "llf"), (500, 4, 4, "rk4", "upwind"),
+                                             (130, 130, 2, "rk4", "central")])
+def test_lane_elems_variants(torch_cuda, lane_elems, ne, pe, p, rk, phys):
+    eq = "burgers" if phys == "llf" else "advection"
+    ic = W.MultiSine((1, 2), (1.0, 0.5), (0.3, 0.9), offset=0.5 if eq == "burgers" else 0.0)
+    sig = {1: 0.05, 2: 0.01, 3: 0.005, 4: 0.001}[p]
+    w = W.Workload(name=f"le{lane_elems}_{ne}", equation=eq, flux=phys, rk=rk, degree=p, n_elem=ne, pe_size=pe,
+                   probs=W.DELAYS_C2, seed=21, per_stage=(ne % 2 == 0), ic=ic,
+                   dt=sig * W.TWO_PI / ne / (1.5 if eq == "burgers" else 1.0))
+    _check(torch_cuda, w, 21, "fused", graph=True, lane_elems=lane_elems)
+
+
+def test_lane_elems_rejected_above_pe_size(torch_cuda):
+    from paper_2404_03399_amd import adg
+    from paper_2404_03399_amd.solver import Solver
+    w = W.Workload(name="bad", n_elem=12, pe_size=2, probs=("0.5", "0.5"), dt=1e-3)
+    with pytest.raises(adg.AdgError):
+        Solver(w, lane_elems=4)
 
 
 def test_negative_speed_upwind(torch_cuda):
