@@ -63,7 +63,7 @@ class Solver:
     """One context over one or more problems (batched when more than one)."""
 
     def __init__(self, workloads, kernel: str = "fused", n_steps_record: int = 0, ckpt_every: int = 0,
-                 device: str = "cuda", stream=None, lane_elems: int = 0):
+                 device: str = "cuda", stream=None, lane_elems=0):
         if not isinstance(workloads, (list, tuple)):
             workloads = [workloads]
         self.workloads = list(workloads)
@@ -72,7 +72,10 @@ class Solver:
         self.opt = adg.adg_options()
         self.opt.kernel = adg.KERNEL[kernel]
         self.opt.ckpt_every = ckpt_every
-        self.opt.lane_elems = lane_elems
+        if lane_elems == "auto":
+            from . import autotune
+            lane_elems = autotune.lane_elems(self.workloads) if kernel == "fused" else 0
+        self.opt.lane_elems = int(lane_elems)
         self.device = torch.device(device)
         self.ws_bytes = adg.adg_workspace_size(self.probs, self.opt, n_steps_record)
         self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)

@@ -328,3 +328,19 @@ def test_ensemble_stats_match_oracle(torch_cuda):
         om0, _ = stats.ensemble_mean_var([per[i][0] for i in range(len(ws)) if group[i] == g])
         gslack = max(slacks[i] for i in range(len(ws)) if group[i] == g)
         assert abs(got[g][0] - om0) <= gslack + 1e-13 * om0
+
+
+def test_autotuned_lane_elems(torch_cuda, tmp_path, monkeypatch):
+    """The tuner picks an admissible value, caches it, and the tuned solver
+    still matches the oracle."""
+    import json
+    from paper_2404_03399_amd import autotune
+    monkeypatch.setenv("ADG_TUNE_CACHE", str(tmp_path / "tune.json"))
+    w = W.c2_advection_large("adg_at", n_elem=8192)
+    _say("autotune lane_elems N=8192")
+    r = autotune.lane_elems(w, steps=8)
+    assert r in autotune.admissible([w])
+    cache = json.load(open(tmp_path / "tune.json"))
+    assert len(cache) == 1 and list(cache.values())[0]["lane_elems"] == r
+    assert autotune.lane_elems(w) == r
+    _check(torch_cuda, w, 12, "fused", graph=True, lane_elems=r)

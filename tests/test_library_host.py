@@ -121,3 +121,11 @@ def test_workspace_size_grows_with_problems(L):
     one = adg.adg_workspace_size([solver.to_problem(W.c1_advection_small())], adg.adg_options())
     two = adg.adg_workspace_size([solver.to_problem(W.c1_advection_small())] * 2, adg.adg_options())
     assert two > one > 0
+
+
+def test_autotune_admissible_candidates():
+    from paper_2404_03399_amd import autotune
+    w = W.c1_advection_small()
+    assert autotune.admissible([w]) == [1, 2, 4]
+    assert autotune.admissible([replace(w, pe_size=2, n_elem=64)]) == [1, 2]
+    assert autotune.admissible([replace(w, scheme="dg", pe_size=1)]) == [1, 2, 4]
