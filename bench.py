@@ -90,29 +90,68 @@ def cpu_baseline(w, steps: int):
             "sample": f"{steps} RK4 steps of the same 2^20-element ADG-AT problem ({dt:.1f} s, numpy FP64, 1 thread)"}
 
 
-def bench_adjoint(torch, W, Solver, n_steps: int, n_elem: int):
-    """Recorded forward + discrete adjoint of J = 1/2 ||u(T) - u_exact(T)||^2
-    (linear advection, ADG-AT, p=3, RK4, checkpoint every 64 steps)."""
-    w = W.c5_adjoint_advection(n_elem=n_elem, n_steps=n_steps)
-    s = Solver(w, n_steps_record=n_steps, ckpt_every=64)
+def _timed_adjoint(torch, s, n_steps, cot_of):
     u = s.initial_state()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     s.run(u, n_steps, graph=True, record=True)
     torch.cuda.synchronize()
     t_fwd = time.perf_counter() - t0
-    cot = u - s.exact_advection_state(n_steps * w.dt)
+    cot = cot_of(u)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     g, ga = s.adjoint(cot)
     torch.cuda.synchronize()
-    t_adj = time.perf_counter() - t0
+    return g, ga[0], t_fwd, time.perf_counter() - t0
+
+
+def bench_adjoint(torch, W, Solver, n_steps: int, n_elem: int, stage: bool):
+    """Recorded forward + discrete adjoint of the misfit J = 1/2 ||u(T) - u_ref||^2
+    against the exact solution for a speed 1% larger, u_ref = u0(x - 1.01 a T)
+    (linear advection, ADG-AT, p=3, RK4, checkpoint every 64 steps): fused
+    reverse-step kernel, and for comparison the per-stage reverse kernels on
+    the same cotangent.  dJ/da is compared with its continuous-in-space-and-time
+    value sum_nodes (u0(x - aT) - u_ref) (-T) u0'(x - aT)."""
+    w = W.c5_adjoint_advection(n_elem=n_elem, n_steps=n_steps)
+    T = n_steps * w.dt
+    s = Solver(w, n_steps_record=n_steps, ckpt_every=64)
+    u_ref = s.exact_advection_state(1.01 * T)
+    cot_holder = {}
+
+    def cot_of(u):
+        cot_holder["cot"] = u - u_ref
+        return cot_holder["cot"]
+
+    g, ga, t_fwd, t_adj = _timed_adjoint(torch, s, n_steps, cot_of)
+    xs = s.nodes(0) - w.speed * T
+    du0 = torch.zeros_like(xs)
+    for k, amp, ph in zip(w.ic.kappa, w.ic.amp, w.ic.phase):
+        du0 = du0 + amp * k * torch.cos(k * xs + ph)
+    ga_cont = float(((s.view(s.exact_advection_state(T)) - s.view(u_ref)) * (-T) * du0).sum())
     dofs = w.n_elem * (w.degree + 1)
-    out = {"workload": f"ADG-AT(q=4) RK4 N_E={n_elem} p=3, {n_steps} steps, checkpoint every 64",
+    out = {"workload": f"ADG-AT(q=4) RK4 N_E={n_elem} p=3, {n_steps} steps, checkpoint every 64, "
+                       f"J = 1/2 ||u(T) - u0(x - 1.01 a T)||^2",
            "reverse_dof_stage_per_s": dofs * 4 * n_steps / t_adj, "adjoint_s": t_adj,
-           "recorded_forward_s": t_fwd, "dJ_da": ga[0],
+           "recorded_forward_s": t_fwd, "dJ_da": ga, "dJ_da_continuous": ga_cont,
+           "dJ_da_rel_diff": abs(ga - ga_cont) / abs(ga_cont),
            "grad_finite": bool(torch.isfinite(g).all().item())}
+    # dJ/du0 only: linear advection needs no forward recomputation
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g0, _ = s.adjoint(cot_holder["cot"], want_speed=False)
+    torch.cuda.synchronize()
+    t_u0 = time.perf_counter() - t0
+    out["u0_only"] = {"reverse_dof_stage_per_s": dofs * 4 * n_steps / t_u0, "adjoint_s": t_u0,
+                      "bitwise_equal_to_full": bool(torch.equal(s.view(g0), s.view(g)))}
     s.close()
+    if stage:
+        s = Solver(w, kernel="stage", n_steps_record=n_steps, ckpt_every=64)
+        g2, ga2, _, t2 = _timed_adjoint(torch, s, n_steps, lambda u: cot_holder["cot"])
+        out["stage_kernels"] = {"reverse_dof_stage_per_s": dofs * 4 * n_steps / t2, "adjoint_s": t2,
+                                "grad_rel_l2_vs_fused": float(torch.linalg.vector_norm(g2 - g)
+                                                              / torch.linalg.vector_norm(g)),
+                                "dJ_da": ga2}
+        s.close()
     return out
 
 
@@ -186,6 +225,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the one-context-per-problem ensemble run")
+    ap.add_argument("--no-adjoint-stage", action="store_true", help="skip the per-stage adjoint comparison")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -271,7 +311,8 @@ def main():
         torch.cuda.synchronize()
         out["calib_copy_bytes_each_way"] = n * 8
     if not args.no_adjoint:
-        out["adjoint"] = bench_adjoint(torch, W, Solver, args.adjoint_steps, args.n_elem)
+        out["adjoint"] = bench_adjoint(torch, W, Solver, args.adjoint_steps, args.n_elem,
+                                       not args.no_adjoint_stage)
     if not args.no_ensemble:
         out["ensemble"] = bench_ensemble(torch, W, Solver, args.ensemble_steps, args.ensemble_real,
                                          not args.no_plain)

@@ -35,7 +35,8 @@
  *   - State layout: structure of arrays per problem.  Problem i owns
  *     u[offset_i + j * ld_i + e], node plane j in [0, degree], element
  *     e in [0, n_elem); ld_i = n_elem rounded up to 64.  Padding entries are
- *     never read or written.  Offsets/lds come from adg_state_layout.
+ *     never read; their contents after a stepping call are unspecified.
+ *     Offsets/lds come from adg_state_layout.
  *   - A context is not thread-safe.  All problems of one context advance
  *     together and must share equation, flux, rk and scheme; degree, mesh,
  *     PE size, delays, seed, speed and dt may differ (batched ensembles).
@@ -162,7 +163,12 @@ int adg_run(adg_ctx* ctx, double* d_u, int64_t n_steps, uint32_t flags);
  * J(u(T)) with cotangent d_cot_uT = dJ/du(T) (device, state layout).
  * Writes dJ/du(0) to d_grad_u0 (device, state layout) and, for advection,
  * dJ/da per problem to the host array h_grad_speed (n_probs doubles; dt is
- * held fixed).  Requires the last adg_run to have used ADG_RUN_RECORD. */
+ * held fixed; 0 for Burgers).  h_grad_speed may be NULL: for linear
+ * advection the reverse sweep then skips the forward recomputation, which
+ * only dJ/da needs.  Requires the last adg_run to have used ADG_RUN_RECORD;
+ * the recording stays valid (the adjoint may be called again) and the
+ * context may keep stepping afterwards.  Synchronises the stream when
+ * h_grad_speed is given. */
 int adg_adjoint(adg_ctx* ctx, const double* d_cot_uT, double* d_grad_u0, double* h_grad_speed);
 
 /* Per-problem error statistics against a reference state (same layout):

@@ -167,10 +167,12 @@ def adg_run(ctx, d_u: int, n_steps: int, flags: int = 0) -> None:
     check(lib().adg_run(ctx, C.c_void_p(d_u), n_steps, flags), "adg_run")
 
 
-def adg_adjoint(ctx, d_cot: int, d_grad_u0: int, n_probs: int):
-    out = (C.c_double * n_probs)()
+def adg_adjoint(ctx, d_cot: int, d_grad_u0: int, n_probs: int, want_speed: bool = True):
+    """dJ/du0 into d_grad_u0; returns dJ/da per problem, or None when not
+    requested (h_grad_speed = NULL)."""
+    out = (C.c_double * n_probs)() if want_speed else None
     check(lib().adg_adjoint(ctx, C.c_void_p(d_cot), C.c_void_p(d_grad_u0), out), "adg_adjoint")
-    return list(out)
+    return list(out) if want_speed else None
 
 
 def adg_error_stats(ctx, d_u: int, d_ref: int, n_probs: int):

@@ -5,7 +5,9 @@ adjoint of libadg (delay schedule held fixed, dt held fixed).
 
 u0 is a state vector in the library's layout (Solver.pack / initial_state)
 and speed a 0-d float64 tensor (the advection speed a).  backward() returns
-dJ/du0 and dJ/da from adg_adjoint.
+dJ/du0 and dJ/da from adg_adjoint; when speed needs no gradient the adjoint
+is asked for dJ/du0 only (for linear advection that skips the forward
+recomputation).
 """
 from __future__ import annotations
 
@@ -30,9 +32,10 @@ class ADGFunction(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, grad_out):
-        g, gs = ctx.solver.adjoint(grad_out)
+        want_speed = ctx.speed_is_tensor and ctx.needs_input_grad[1]
+        g, gs = ctx.solver.adjoint(grad_out, want_speed=want_speed)
         gspeed = None
-        if ctx.speed_is_tensor:
+        if want_speed:
             gspeed = torch.tensor(gs[0], dtype=torch.float64, device=ctx.speed_device)
         ctx.solver.close()
         ctx.solver = None

@@ -219,10 +219,12 @@ int validate(const adg_problem* probs, int32_t n) {
 struct Layout {
   int64_t probs, work_f, work_s, first_s, ctr, ring, atsum, atk, state2, y0, y1, acc, part, stats_out;
   int64_t groups, gstats;  // ensemble statistics: group CSR (2n+1 int32) and 4 doubles per group
-  // adjoint recording (-1 if not recording)
-  int64_t ckpt, useg, ybuf, lam, q, adjring, cpart;
+  // adjoint recording (-1 if not recording); ckrec holds the fused kernel's
+  // PE-face records (AT sums, delays) at every checkpoint plus one spare slot
+  int64_t ckpt, useg, ybuf, lam, q, adjring, cpart, ckrec, work_a;
   int64_t total;
-  int32_t n_work_f, n_work_s;
+  int32_t n_work_f, n_work_s, n_work_a;
+  int64_t rec_atsum_bytes, rec_atk_bytes, rec_bytes;
   int64_t total_doubles;
   int64_t ring_doubles;
   int64_t at_entries;  // boundaries x 2 parities (x S for the sums)
@@ -255,10 +257,12 @@ Layout make_layout(const adg_problem* probs, int32_t n, const adg_options* opt, 
   Layout L{};
   const int S = rk_stages((int)probs[0].rk);
   const int T = fused_tile((int)probs[0].rk, std::max(1, lane_elems_of(probs, n, opt)));
-  int64_t nwf = 0, nws = 0, tot = 0, ring = 0, at = 0;
+  const int T1 = adj_tile_elems((int)probs[0].rk, probs[0].equation == ADG_EQ_BURGERS);
+  int64_t nwf = 0, nws = 0, nwa = 0, tot = 0, ring = 0, at = 0;
   for (int32_t i = 0; i < n; ++i) {
     const adg_problem& p = probs[i];
     nwf += (p.n_elem + T - 1) / T;
+    nwa += (p.n_elem + T1 - 1) / T1;
     nws += (p.n_elem + kBlock - 1) / kBlock;
     tot += ld_of(p) * (p.degree + 1);
     if (async_of(p)) {
@@ -269,6 +273,7 @@ Layout make_layout(const adg_problem* probs, int32_t n, const adg_options* opt, 
   L.at_entries = at;
   L.n_work_f = (int32_t)nwf;
   L.n_work_s = (int32_t)nws;
+  L.n_work_a = n_rec > 0 ? (int32_t)nwa : 0;
   L.total_doubles = tot;
   L.ring_doubles = ring;
   const int kern = kernel_of(opt);
@@ -284,9 +289,9 @@ Layout make_layout(const adg_problem* probs, int32_t n, const adg_options* opt, 
   L.atk = take(4 * std::max<int64_t>(at, 1));
   const bool rec = n_rec > 0;
   L.state2 = kern == ADG_KERNEL_FUSED ? take(8 * tot) : -1;
-  L.y0 = (kern == ADG_KERNEL_STAGE || rec) ? take(8 * tot) : -1;
-  L.y1 = (kern == ADG_KERNEL_STAGE || rec) ? take(8 * tot) : -1;
-  L.acc = (kern == ADG_KERNEL_STAGE || rec) ? take(8 * tot) : -1;
+  L.y0 = kern == ADG_KERNEL_STAGE ? take(8 * tot) : -1;
+  L.y1 = kern == ADG_KERNEL_STAGE ? take(8 * tot) : -1;
+  L.acc = kern == ADG_KERNEL_STAGE ? take(8 * tot) : -1;
   L.part = take(3 * 8 * nws);
   L.stats_out = take(3 * 8 * (int64_t)n);
   L.groups = take(4 * (2 * (int64_t)n + 1));
@@ -294,16 +299,25 @@ Layout make_layout(const adg_problem* probs, int32_t n, const adg_options* opt, 
   L.n_rec = n_rec;
   L.ckpt_every = (opt && opt->ckpt_every > 0) ? opt->ckpt_every : 64;
   L.n_ckpt = rec ? (n_rec + L.ckpt_every - 1) / L.ckpt_every : 0;
-  L.ckpt = L.useg = L.ybuf = L.lam = L.q = L.adjring = L.cpart = -1;
+  L.ckpt = L.useg = L.ybuf = L.lam = L.q = L.adjring = L.cpart = L.ckrec = L.work_a = -1;
+  L.rec_atsum_bytes = 8 * S * std::max<int64_t>(at, 1);
+  L.rec_atk_bytes = 4 * std::max<int64_t>(at, 1);
+  L.rec_bytes = align_up(L.rec_atsum_bytes, kAlign) + align_up(L.rec_atk_bytes, kAlign);
   if (rec) {
     const int64_t seg = std::min<int64_t>(L.ckpt_every, n_rec);
     L.ckpt = take(8 * tot * L.n_ckpt);
     L.useg = take(8 * tot * seg);
-    L.ybuf = take(8 * tot * (S - 1));
     L.lam = take(8 * tot * 2);
-    L.q = take(8 * tot * (S - 1));
     L.adjring = take(8 * std::max<int64_t>(ring, 1));
-    L.cpart = take(8 * nws);
+    if (kern == ADG_KERNEL_STAGE) {
+      L.ybuf = take(8 * tot * (S - 1));
+      L.q = take(8 * tot * (S - 1));
+      L.cpart = take(8 * nws);
+    } else {
+      L.ckrec = take(L.rec_bytes * (L.n_ckpt + 1));
+      L.work_a = take((int64_t)sizeof(WorkItem) * nwa);
+      L.cpart = take(8 * nwa);
+    }
   }
   L.total = off;
   return L;
@@ -332,6 +346,10 @@ struct adg_ctx {
   int32_t group[5] = {0, 0, 0, 0, 0};
   int32_t grid[4] = {1, 1, 1, 1};
   int32_t lane_elems = 2;
+  // fused adjoint work list (recording contexts of the fused kernel)
+  std::vector<WorkItem> work_a;
+  int32_t group_a[5] = {0, 0, 0, 0, 0};
+  int32_t grid_a[4] = {1, 1, 1, 1};
 
   StepArgs base_args(int64_t work_off, int32_t n_work) const {
     StepArgs a{};
@@ -349,6 +367,27 @@ struct adg_ctx {
   }
   StepArgs fused_args() const { return base_args(L.work_f, L.n_work_f); }
   StepArgs stage_args() const { return base_args(L.work_s, L.n_work_s); }
+  AdjArgs adj_args() const {
+    AdjArgs a{};
+    a.probs = (const DevProblem*)(ws + L.probs);
+    a.work = (const WorkItem*)(ws + L.work_a);
+    for (int i = 0; i < 5; ++i) a.group[i] = group_a[i];
+    for (int i = 0; i < 4; ++i) a.grid[i] = grid_a[i];
+    return a;
+  }
+  // copy the fused kernel's PE-face records to / from checkpoint slot k
+  int save_records(int64_t k, bool restore) {
+    if (L.ckrec < 0) return ADG_OK;
+    char* rec = ws + L.ckrec + L.rec_bytes * k;
+    char* sum = ws + L.atsum;
+    char* kk = ws + L.atk;
+    char* rk_ = rec + align_up(L.rec_atsum_bytes, kAlign);
+    ADG_HIP(hipMemcpyAsync(restore ? sum : rec, restore ? rec : sum, L.rec_atsum_bytes, hipMemcpyDeviceToDevice,
+                           stream));
+    ADG_HIP(hipMemcpyAsync(restore ? kk : rk_, restore ? rk_ : kk, L.rec_atk_bytes, hipMemcpyDeviceToDevice, stream));
+    return ADG_OK;
+  }
+
   double* state2() const { return (double*)(ws + L.state2); }
 };
 
@@ -580,6 +619,20 @@ int adg_init(adg_ctx** out, const adg_problem* probs, int32_t n_probs, const adg
     for (int64_t t = 0; t < nt; ++t) ws_.push_back(WorkItem{i, (int32_t)t});
   }
   first[n_probs] = (int32_t)ws_.size();
+  if (c->L.work_a >= 0) {  // fused adjoint: one element per lane, same degree grouping
+    const int T1 = adj_tile_elems(c->rk, probs[0].equation == ADG_EQ_BURGERS);
+    c->work_a.reserve(c->L.n_work_a);
+    for (int np = 5, gi = 0; np >= 2; --np, ++gi) {
+      c->group_a[gi] = (int32_t)c->work_a.size();
+      for (int32_t i : order) {
+        if ((int)probs[i].degree + 1 != np) continue;
+        const int64_t nt = (probs[i].n_elem + T1 - 1) / T1;
+        for (int64_t t = 0; t < nt; ++t) c->work_a.push_back(WorkItem{i, (int32_t)t});
+      }
+    }
+    c->group_a[4] = (int32_t)c->work_a.size();
+    for (int gi = 0; gi < 4; ++gi) c->grid_a[gi] = fused_grid(c->group_a[gi + 1] - c->group_a[gi]);
+  }
 
   auto up = [&](int64_t off, const void* src, int64_t bytes) -> int {
     ADG_HIP(hipMemcpyAsync(c->ws + off, src, bytes, hipMemcpyHostToDevice, c->stream));
@@ -589,6 +642,8 @@ int adg_init(adg_ctx** out, const adg_problem* probs, int32_t n_probs, const adg
       (rc = up(c->L.work_f, wf.data(), (int64_t)sizeof(WorkItem) * wf.size())) ||
       (rc = up(c->L.work_s, ws_.data(), (int64_t)sizeof(WorkItem) * ws_.size())) ||
       (rc = up(c->L.first_s, first.data(), (int64_t)sizeof(int32_t) * first.size())) ||
+      (c->L.work_a >= 0 &&
+       (rc = up(c->L.work_a, c->work_a.data(), (int64_t)sizeof(WorkItem) * c->work_a.size()))) ||
       (rc = reset_device(c))) {
     delete c;
     return rc;
@@ -627,6 +682,7 @@ int adg_run(adg_ctx* c, double* d_u, int64_t n_steps, uint32_t flags) {
     int rc;
     for (int64_t k = 0; done < n_steps; ++k) {
       ADG_HIP(hipMemcpyAsync(c->ws + c->L.ckpt + 8 * tot * k, d_u, 8 * tot, hipMemcpyDeviceToDevice, c->stream));
+      if ((rc = c->save_records(k, false))) return rc;
       const int64_t m = std::min<int64_t>(C, n_steps - done);
       if ((rc = adg_run(c, d_u, m, flags & ~(ADG_RUN_RECORD | ADG_RUN_CHECK_FINITE)))) return rc;
       done += m;
@@ -675,9 +731,20 @@ int adg_run(adg_ctx* c, double* d_u, int64_t n_steps, uint32_t flags) {
 
 int adg_step(adg_ctx* c, double* d_u) { return adg_run(c, d_u, 1, 0); }
 
-int adg_adjoint(adg_ctx* c, const double* d_cot_uT, double* d_grad_u0, double* h_grad_speed) {
-  if (!c || !d_cot_uT || !d_grad_u0) return fail(ADG_E_INVALID, "null argument");
-  if (c->rec_steps <= 0) return fail(ADG_E_STATE, "adg_adjoint needs a run recorded with ADG_RUN_RECORD");
+namespace {
+
+// Per-problem sums of the per-work-item dJ/da shares, in work-list order.
+void sum_speed_parts(const adg_ctx* c, const std::vector<double>& part, const std::vector<WorkItem>& items,
+                     double* h_grad_speed) {
+  std::vector<double> acc(c->probs.size(), 0.0);
+  for (size_t t = 0; t < items.size(); ++t) acc[items[t].prob] += part[t];
+  for (size_t i = 0; i < c->probs.size(); ++i)
+    h_grad_speed[i] = c->probs[i].equation == ADG_EQ_ADVECTION ? acc[i] : 0.0;
+}
+
+// Adjoint with the per-stage kernels: the segment is recomputed stage by
+// stage, and every reverse stage is one launch with its RK registers in HBM.
+int adjoint_stage(adg_ctx* c, const double* d_cot_uT, double* d_grad_u0, double* h_grad_speed) {
   const Layout& L = c->L;
   const int64_t tot = L.total_doubles, C = L.ckpt_every, N = c->rec_steps;
   const int S = c->S;
@@ -741,19 +808,89 @@ int adg_adjoint(adg_ctx* c, const double* d_cot_uT, double* d_grad_u0, double* h
     std::vector<double> part(L.n_work_s);
     ADG_HIP(hipMemcpyAsync(part.data(), cpart, 8 * part.size(), hipMemcpyDeviceToHost, st));
     ADG_HIP(hipStreamSynchronize(st));
-    const WorkItem* dummy = nullptr;
-    (void)dummy;
-    // stage work list is contiguous per problem, in problem order
-    int64_t item = 0;
+    std::vector<WorkItem> items;  // stage work list: contiguous per problem, in problem order
+    items.reserve(L.n_work_s);
     for (size_t i = 0; i < c->probs.size(); ++i) {
       const int64_t nt = (c->probs[i].n_elem + kBlock - 1) / kBlock;
-      double acc = 0.0;
-      for (int64_t t = 0; t < nt; ++t) acc += part[item + t];
-      item += nt;
-      h_grad_speed[i] = c->probs[i].equation == ADG_EQ_ADVECTION ? acc : 0.0;
+      for (int64_t t = 0; t < nt; ++t) items.push_back(WorkItem{(int32_t)i, (int32_t)t});
     }
+    sum_speed_parts(c, part, items, h_grad_speed);
   }
   return ADG_OK;
+}
+
+// Adjoint with the fused kernels: each segment is recomputed out of place by
+// the fused step kernel (from the checkpointed state and PE-face records, so
+// the states are bitwise those of the recorded run), then every reverse step
+// is one launch per degree group.  The records of the current step are kept
+// in the spare checkpoint slot and restored at the end, so the context can
+// keep stepping afterwards.
+int adjoint_fused(adg_ctx* c, const double* d_cot_uT, double* d_grad_u0, double* h_grad_speed) {
+  const Layout& L = c->L;
+  const int64_t tot = L.total_doubles, C = L.ckpt_every, N = c->rec_steps;
+  char* ws = c->ws;
+  hipStream_t st = c->stream;
+  const StepArgs fa = c->fused_args();
+  const AdjArgs aa = c->adj_args();
+  double* lam = (double*)(ws + L.lam);
+  double* lamu = lam + tot;
+  double* adjring = (double*)(ws + L.adjring);
+  double* cpart = (double*)(ws + L.cpart);
+  const double* ring = (const double*)(ws + L.ring);
+  double* useg = (double*)(ws + L.useg);
+  int64_t* ctr = (int64_t*)(ws + L.ctr);
+  const size_t bytes = 8 * (size_t)tot;
+  int rc;
+
+  if ((rc = c->save_records(L.n_ckpt, false))) return rc;
+  ADG_HIP(hipMemcpyAsync(lam, d_cot_uT, bytes, hipMemcpyDeviceToDevice, st));
+  ADG_HIP(hipMemsetAsync(adjring, 0, 8 * std::max<int64_t>(L.ring_doubles, 1), st));
+  ADG_HIP(hipMemsetAsync(cpart, 0, 8 * (size_t)std::max<int32_t>(L.n_work_a, 1), st));
+  ADG_HIP(launch_set_counter(ctr, 0, st));  // launches below pass absolute step indices
+
+  // linear advection: the reverse sweep does not depend on the forward states;
+  // they are recomputed only for dJ/da
+  const bool need_fwd = c->phys == PHYS_BURGERS_LLF || h_grad_speed != nullptr;
+  if (!need_fwd) {
+    for (int64_t n = N - 1; n >= 0; --n) {
+      ADG_HIP(launch_adj_fused(c->rk, c->phys, aa, nullptr, lam, lamu, ring, adjring, cpart, (int32_t)n, st));
+      std::swap(lam, lamu);
+    }
+  }
+  for (int64_t k = need_fwd ? L.n_ckpt - 1 : -1; k >= 0; --k) {
+    const int64_t n0 = k * C;
+    const int64_t len = std::min<int64_t>(C, N - n0);
+    if (len <= 0) continue;
+    ADG_HIP(hipMemcpyAsync(useg, ws + L.ckpt + 8 * tot * k, bytes, hipMemcpyDeviceToDevice, st));
+    if ((rc = c->save_records(k, true))) return rc;
+    for (int64_t i = 1; i < len; ++i)
+      ADG_HIP(launch_fused_step(c->rk, c->fused_phys, fa, useg + tot * (i - 1), useg + tot * i,
+                                (int32_t)(n0 + i - 1), st));
+    for (int64_t i = len - 1; i >= 0; --i) {
+      ADG_HIP(launch_adj_fused(c->rk, c->phys, aa, useg + tot * i, lam, lamu, ring, adjring, cpart,
+                               (int32_t)(n0 + i), st));
+      std::swap(lam, lamu);
+    }
+  }
+  ADG_HIP(hipMemcpyAsync(d_grad_u0, lam, bytes, hipMemcpyDeviceToDevice, st));
+  if ((rc = c->save_records(L.n_ckpt, true))) return rc;
+  ADG_HIP(launch_set_counter(ctr, c->steps, st));
+  if (h_grad_speed) {
+    std::vector<double> part(c->work_a.size());
+    ADG_HIP(hipMemcpyAsync(part.data(), cpart, 8 * part.size(), hipMemcpyDeviceToHost, st));
+    ADG_HIP(hipStreamSynchronize(st));
+    sum_speed_parts(c, part, c->work_a, h_grad_speed);
+  }
+  return ADG_OK;
+}
+
+}  // namespace
+
+int adg_adjoint(adg_ctx* c, const double* d_cot_uT, double* d_grad_u0, double* h_grad_speed) {
+  if (!c || !d_cot_uT || !d_grad_u0) return fail(ADG_E_INVALID, "null argument");
+  if (c->rec_steps <= 0) return fail(ADG_E_STATE, "adg_adjoint needs a run recorded with ADG_RUN_RECORD");
+  return c->kernel == ADG_KERNEL_FUSED ? adjoint_fused(c, d_cot_uT, d_grad_u0, h_grad_speed)
+                                       : adjoint_stage(c, d_cot_uT, d_grad_u0, h_grad_speed);
 }
 
 int adg_error_stats(adg_ctx* c, const double* d_u, const double* d_ref, double* h_out) {

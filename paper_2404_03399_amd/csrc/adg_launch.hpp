@@ -50,6 +50,28 @@ hipError_t launch_adj_stage(int rk, int phys, int stage, const StepArgs& a, cons
                             double* lamu, double* Q, int64_t qstride, const double* ring, double* adjring,
                             double* cpart, int32_t n, hipStream_t stream);
 
+// Fused adjoint geometry: one element per lane, halo of S lanes per side for
+// a constant Jacobian (linear advection) and 2S - 1 when the Jacobian depends
+// on the stage inputs (Burgers).  Work items are grouped by descending np
+// like the fused step's list.
+__host__ __device__ constexpr int adj_halo(int rk, bool nonlinear) {
+  return nonlinear ? 2 * rk_stages(rk) - 1 : rk_stages(rk);
+}
+__host__ __device__ constexpr int adj_tile_elems(int rk, bool nonlinear) { return kWave - 2 * adj_halo(rk, nonlinear); }
+struct AdjArgs {
+  const DevProblem* probs;
+  const WorkItem* work;
+  int32_t group[5];
+  int32_t grid[4];
+};
+
+// Reverse of the whole RK step n (absolute index) for all problems in one
+// launch per degree group: lamo = lambda^n from lam = lambda^{n+1} and the
+// forward state u = u^n (stages recomputed on chip); adjoint-ring deposits for
+// delayed AT levels; cpart[work item] += dJ/da share (advection).
+hipError_t launch_adj_fused(int rk, int phys, const AdjArgs& a, const double* u, const double* lam, double* lamo,
+                            const double* ring, double* adjring, double* cpart, int32_t n, hipStream_t stream);
+
 // ctr[0] := value (one lane).
 hipError_t launch_set_counter(int64_t* ctr, int64_t value, hipStream_t stream);
 

@@ -154,11 +154,13 @@ class Solver:
                 (adg.ADG_RUN_CHECK_FINITE if check_finite else 0)
         adg.adg_run(self.ctx, u.data_ptr(), n_steps, flags)
 
-    def adjoint(self, cot: torch.Tensor):
-        """dJ/du0 (device, state layout) and dJ/da per problem (host list) for
-        the last recorded run, given cot = dJ/du(T)."""
+    def adjoint(self, cot: torch.Tensor, want_speed: bool = True):
+        """dJ/du0 (device, state layout) and dJ/da per problem (host list, or
+        None if want_speed is False) for the last recorded run, given
+        cot = dJ/du(T)."""
+        cot = cot.contiguous()
         grad = torch.empty_like(cot)
-        gs = adg.adg_adjoint(self.ctx, cot.contiguous().data_ptr(), grad.data_ptr(), len(self.probs))
+        gs = adg.adg_adjoint(self.ctx, cot.data_ptr(), grad.data_ptr(), len(self.probs), want_speed)
         return grad, gs
 
     def steps_taken(self) -> int:

@@ -67,31 +67,123 @@ def test_adjoint_matches_oracle(torch_cuda, kernel, scheme, rk, p, flux, ne, pe)
     assert abs(ga - ga_o) <= 1e-12 * max(1.0, abs(ga_o)), (ga, ga_o)
 
 
-@pytest.mark.parametrize("per_stage", [True, False])
-def test_burgers_adjoint_matches_oracle(torch_cuda, per_stage):
-    w = replace(W.c3_burgers(n_elem=128, n_steps=0, sigma=0.02), pe_size=16, per_stage=per_stage)
+@pytest.mark.parametrize("kernel", ["fused", "stage"])
+@pytest.mark.parametrize("rk,p,per_stage", [("ssprk3", 2, True), ("ssprk3", 2, False), ("rk4", 3, True),
+                                            ("heun", 1, False)])
+def test_burgers_adjoint_matches_oracle(torch_cuda, kernel, rk, p, per_stage):
+    # N = 128 spans several fused-adjoint tiles (64 - 2(2S - 1) elements each)
+    w = replace(W.c3_burgers(n_elem=128, n_steps=0, sigma=0.02), pe_size=16, per_stage=per_stage, rk=rk,
+                degree=p)
     n = 30
     u0 = stepper.initial_state(w)
     ref = 0.25 * np.ones_like(u0)
-    _say(f"burgers adjoint N=128 steps={n} per_stage={per_stage}")
+    _say(f"burgers adjoint N=128 {rk} p={p} steps={n} per_stage={per_stage} kernel={kernel}")
     _, g_o, _ = oadj.gradient(w, u0, n, oadj.misfit_cotangent(ref))
-    g, _, _ = _gpu_grad(torch_cuda, w, u0, n, lambda x: x - ref, ckpt=7)
+    g, _, _ = _gpu_grad(torch_cuda, w, u0, n, lambda x: x - ref, kernel=kernel, ckpt=7)
     assert stats.rel_l2(g, g_o) <= 1e-12
 
 
-def test_checkpoint_interval_does_not_change_gradient(torch_cuda):
-    # segments are recomputed with the per-stage kernel, the recorded run used
-    # the fused one: the gradients agree to rounding, not bitwise
+@pytest.mark.parametrize("kernel", ["fused", "stage"])
+def test_checkpoint_interval_does_not_change_gradient(torch_cuda, kernel):
+    # fused: segments are recomputed by the fused step kernel from the
+    # checkpointed state and PE-face records, so the states, and with them the
+    # gradients, are bitwise those of the recorded run for any interval.
+    # stage: the per-stage recompute rounds differently from the recorded
+    # run's kernel only in the order of operations: equal to rounding.
     w = W.c2_advection_large("adg_at", n_elem=2048)
     u0 = stepper.initial_state(w)
-    _say("checkpoint intervals 1, 7, 64 on N=2048, 40 steps")
-    outs = [_gpu_grad(torch_cuda, w, u0, 40, lambda x: x, ckpt=c) for c in (1, 7, 64)]
+    _say(f"checkpoint intervals 1, 7, 64 on N=2048, 40 steps, kernel={kernel}")
+    outs = [_gpu_grad(torch_cuda, w, u0, 40, lambda x: x, kernel=kernel, ckpt=c) for c in (1, 7, 64)]
     for g, ga, _ in outs[1:]:
-        assert stats.rel_l2(g, outs[0][0]) <= 1e-13
-        assert abs(ga - outs[0][1]) <= 1e-13 * max(1.0, abs(ga))
+        if kernel == "fused":
+            assert np.array_equal(g, outs[0][0]) and ga == outs[0][1]
+        else:
+            assert stats.rel_l2(g, outs[0][0]) <= 1e-13
+            assert abs(ga - outs[0][1]) <= 1e-13 * max(1.0, abs(ga))
     # same interval twice: bitwise reproducible
-    again = _gpu_grad(torch_cuda, w, u0, 40, lambda x: x, ckpt=7)
+    again = _gpu_grad(torch_cuda, w, u0, 40, lambda x: x, kernel=kernel, ckpt=7)
     assert np.array_equal(again[0], outs[1][0]) and again[1] == outs[1][1]
+
+
+@pytest.mark.parametrize("lane_elems", [1, 2, 4])
+def test_fused_adjoint_lane_elems_and_batch(torch_cuda, lane_elems):
+    """A batched recording (degrees 1..4, different speeds, meshes and PE
+    sizes, forward with R elements per lane) against the oracle problem by
+    problem; the adjoint always runs one element per lane."""
+    from paper_2404_03399_amd.solver import Solver
+    specs = [(1, 90, 15, 1.3, "ssprk3"), (2, 128, 16, 0.7, "ssprk3"), (3, 75, 5, -1.1, "ssprk3"),
+             (4, 64, 8, 2.0, "ssprk3")]
+    ws = []
+    for p, ne, pe, a, rk in specs:
+        dt = {1: 0.05, 2: 0.02, 3: 0.005, 4: 0.002}[p] * W.TWO_PI / ne / abs(a)
+        ws.append(W.Workload(name=f"b{p}", scheme="adg_at", rk=rk, degree=p, n_elem=ne, pe_size=pe,
+                             flux="upwind", probs=W.DELAYS_C2, seed=100 + p, dt=dt, speed=a,
+                             ic=W.PAPER_MULTISINE))
+    n = 17
+    _say(f"batched fused adjoint, 4 problems, R={lane_elems}, {n} steps")
+    s = Solver(ws, n_steps_record=n, ckpt_every=6, lane_elems=lane_elems)
+    u0s = [stepper.initial_state(w) for w in ws]
+    refs = [np.random.default_rng(7 + i).standard_normal(u.shape) for i, u in enumerate(u0s)]
+    u = s.pack(u0s)
+    s.run(u, n, graph=True, record=True)
+    uts = s.unpack(u)
+    g, gs = s.adjoint(s.pack([ut - r for ut, r in zip(uts, refs)]))
+    torch_cuda.cuda.synchronize()
+    gl = s.unpack(g)
+    s.close()
+    for i, w in enumerate(ws):
+        ut_o, g_o, ga_o = oadj.gradient(w, u0s[i], n, oadj.misfit_cotangent(refs[i]))
+        assert stats.rel_l2(uts[i], ut_o) <= 1e-12
+        assert stats.rel_l2(gl[i], g_o) <= 1e-12, (i, stats.rel_l2(gl[i], g_o))
+        assert abs(gs[i] - ga_o) <= 1e-12 * max(1.0, abs(ga_o)), (i, gs[i], ga_o)
+
+
+@pytest.mark.parametrize("kernel", ["fused", "stage"])
+@pytest.mark.parametrize("equation", ["advection", "burgers"])
+def test_gradient_without_speed_is_identical(torch_cuda, kernel, equation):
+    """adg_adjoint with h_grad_speed = NULL (linear advection: no forward
+    recomputation) gives bitwise the same dJ/du0, and a second adjoint call
+    on the same recording repeats the first bitwise."""
+    from paper_2404_03399_amd.solver import Solver
+    if equation == "advection":
+        w = replace(W.c2_advection_large("adg_at", n_elem=700), pe_size=10)
+    else:
+        w = replace(W.c3_burgers(n_elem=300, n_steps=0, sigma=0.02), pe_size=12)
+    n = 37
+    _say(f"adjoint without dJ/da, {equation}, kernel={kernel}")
+    s = Solver(w, kernel=kernel, n_steps_record=n, ckpt_every=9)
+    u = s.initial_state()
+    s.run(u, n, graph=True, record=True)
+    cot = s.pack(np.random.default_rng(3).standard_normal((w.n_elem, w.degree + 1)))
+    g1, gs1 = s.adjoint(cot)
+    g2, gs2 = s.adjoint(cot, want_speed=False)
+    g3, gs3 = s.adjoint(cot)
+    torch_cuda.cuda.synchronize()
+    assert gs2 is None
+    a1, a2, a3 = s.unpack(g1)[0], s.unpack(g2)[0], s.unpack(g3)[0]
+    assert np.array_equal(a1, a2) and np.array_equal(a1, a3) and gs1 == gs3
+    s.close()
+
+
+def test_stepping_after_adjoint_continues_the_run(torch_cuda):
+    """adg_adjoint restores the PE-face records of the current step: stepping
+    on afterwards gives bitwise the run that never called the adjoint."""
+    from paper_2404_03399_amd.solver import Solver
+    w = W.c2_advection_large("adg_at", n_elem=1000)
+    w = replace(w, pe_size=8)
+    _say("continue after adjoint, N=1000, 30 + 21 steps")
+    s = Solver(w, n_steps_record=30, ckpt_every=8)
+    u = s.initial_state()
+    s.run(u, 30, graph=True, record=True)
+    s.adjoint(u.clone())
+    s.run(u, 21, graph=False)
+    ref = Solver(w)
+    v = ref.initial_state()
+    ref.run(v, 51, graph=False)
+    torch_cuda.cuda.synchronize()
+    assert np.array_equal(s.unpack(u)[0], ref.unpack(v)[0])
+    s.close()
+    ref.close()
 
 
 def test_autograd_function(torch_cuda):
