@@ -29,11 +29,26 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
 BYTES_PER_DOF_STEP_FUSED = 16  # read u^n once, write u^{n+1} once (FP64)
 BYTES_PER_DOF_STAGE_STAGEK = {"rk4": 34.0, "ssprk3": 64.0 / 3, "heun": 28.0}
+FP64_VECTOR_PEAK_TFS = 78.6    # MI355X FP64 vector (no MFMA: the element operators are 4x4)
+
+
+def fused_flops_per_elem_step(np_: int) -> int:
+    """FP64 flops of one RK4 step of one element in the fused upwind kernel
+    (halo recompute excluded): per stage the upwind flux a u^- (1), the lift
+    and folded volume operator Kl F + Kdu y (np muls, np^2 FMAs); the RK4
+    updates 13 np (FMA = 2 flops)."""
+    return 4 * (2 * np_ * np_ + np_ + 1) + 13 * np_
+
+
+FUSED_SOURCES = ("adg_fused.hip", "adg_device.hpp", "adg_common.hpp")
 
 
 def kernel_source_hash() -> str:
-    path = os.path.join(ROOT, "paper_2404_03399_amd", "csrc", "adg_kernels.hip")
-    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+    """Hash of the sources the fused step kernel is compiled from."""
+    h = hashlib.sha256()
+    for name in FUSED_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_2404_03399_amd", "csrc", name), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def ring_bytes_per_step(w) -> float:
@@ -46,16 +61,19 @@ def ring_bytes_per_step(w) -> float:
     return w.n_pe * stages * 8.0 * (1 + q)
 
 
-def read_traffic(workload_name: str):
+def read_traffic(lane_elems: int, steps_per_launch: int):
     """HBM bytes per launch from the committed rocprofv3 PMC summary, if it was
-    taken on the current kernel source."""
+    taken on the current kernel source and the same launch shape."""
     path = os.path.join(ROOT, "profiles", "pmc_fused_step_advection_2p20.md")
     if not os.path.exists(path):
         return None
     text = open(path).read()
     m = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", text)
     t = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
-    if not m or not t or m.group(1) != kernel_source_hash():
+    shape = re.search(r"launch_shape:\s*R=(\d+)\s+K=(\d+)", text)
+    if not m or not t or not shape or m.group(1) != kernel_source_hash():
+        return None
+    if (int(shape.group(1)), int(shape.group(2))) != (lane_elems, steps_per_launch):
         return None
     return float(t.group(1))
 
@@ -144,6 +162,14 @@ def bench_adjoint(torch, W, Solver, n_steps: int, n_elem: int, stage: bool):
     out["u0_only"] = {"reverse_dof_stage_per_s": dofs * 4 * n_steps / t_u0, "adjoint_s": t_u0,
                       "bitwise_equal_to_full": bool(torch.equal(s.view(g0), s.view(g)))}
     s.close()
+    # every state resident (C = 1): the recorded forward writes each state
+    # into its slot and the adjoint recomputes nothing
+    s = Solver(w, n_steps_record=n_steps, ckpt_every=1)
+    g1, ga1, t_fwd1, t_adj1 = _timed_adjoint(torch, s, n_steps, lambda u: cot_holder["cot"])
+    out["all_states"] = {"reverse_dof_stage_per_s": dofs * 4 * n_steps / t_adj1, "adjoint_s": t_adj1,
+                         "recorded_forward_s": t_fwd1, "resident_state_bytes": 8 * dofs * n_steps,
+                         "bitwise_equal_to_c64": bool(torch.equal(s.view(g1), s.view(g))) and ga1 == ga}
+    s.close()
     if stage:
         s = Solver(w, kernel="stage", n_steps_record=n_steps, ckpt_every=64)
         g2, ga2, _, t2 = _timed_adjoint(torch, s, n_steps, lambda u: cot_holder["cot"])
@@ -217,7 +243,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--kernel", default="fused", choices=["fused", "stage"])
     ap.add_argument("--n-elem", type=int, default=1 << 20)
-    ap.add_argument("--lane-elems", type=int, default=0, help="fused kernel elements per lane (0: default)")
+    ap.add_argument("--lane-elems", type=int, default=-1,
+                    help="fused kernel elements per lane (default: autotuned together with --fused-steps)")
+    ap.add_argument("--fused-steps", type=int, default=0, help="fused kernel time steps per launch (0: default)")
     ap.add_argument("--extras", action="store_true", help="also time DG/ADG, per-stage kernel, 2^24 mesh")
     ap.add_argument("--adjoint-steps", type=int, default=2000)
     ap.add_argument("--ensemble-real", type=int, default=256)
@@ -238,22 +266,43 @@ def main():
     from paper_2404_03399_amd.solver import Solver
 
     w = W.c2_advection_large("adg_at", n_elem=args.n_elem)
-    s = Solver(w, kernel=args.kernel, lane_elems=args.lane_elems)
+    s = Solver(w, kernel=args.kernel, lane_elems="auto" if args.lane_elems < 0 else args.lane_elems,
+               fused_steps=args.fused_steps)
+    K = (s.opt.fused_steps or 2) if args.kernel == "fused" else 1
+    R = s.opt.lane_elems or 1
     u = s.initial_state()
     gpu_s, wall = time_solver(torch, s, u, args.steps, args.warmup)
     dofs = w.n_elem * (w.degree + 1)
     stages = 4
     value = dofs * stages * args.steps / gpu_s
-    launch_s = gpu_s / args.steps if args.kernel == "fused" else gpu_s / (args.steps * stages)
+    launch_s = gpu_s * K / args.steps if args.kernel == "fused" else gpu_s / (args.steps * stages)
     if args.kernel == "fused":
-        alg_bytes = BYTES_PER_DOF_STEP_FUSED * dofs + ring_bytes_per_step(w)
-        kname = "k_fused_step<RK4, upwind>"
+        # one launch reads u^n and writes u^{n+K} once, and moves K steps of ring traffic
+        alg_bytes = BYTES_PER_DOF_STEP_FUSED * dofs + K * ring_bytes_per_step(w)
+        kname = f"k_fused_step<p=3, RK4, upwind a>0, R={R} element(s) per lane, K={K} step(s) per launch>"
     else:
         alg_bytes = BYTES_PER_DOF_STAGE_STAGEK["rk4"] * dofs + ring_bytes_per_step(w) / stages
         kname = "k_stage<RK4, upwind, s> (mean over stages)"
     achieved = alg_bytes / launch_s / 1e9
-    traffic = read_traffic(w.name) if args.kernel == "fused" and args.n_elem == (1 << 20) else None
+    traffic = read_traffic(R, K) if args.kernel == "fused" and args.n_elem == (1 << 20) else None
     finite = bool(torch.isfinite(u).all().item())
+    hbm = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": achieved / HBM_PEAK_GBS, "traffic": traffic}
+    roof = dict(hbm)
+    if args.kernel == "fused":
+        # the same launch against the FP64 vector peak; the binding roof is the larger fraction
+        flops = fused_flops_per_elem_step(w.degree + 1) * w.n_elem * K
+        alu = {"bound": "alu", "achieved": flops / launch_s / 1e12, "peak": FP64_VECTOR_PEAK_TFS,
+               "unit": "TFLOP/s", "frac": flops / launch_s / 1e12 / FP64_VECTOR_PEAK_TFS, "traffic": traffic,
+               "alg_flops_per_launch": flops}
+        if alu["frac"] > hbm["frac"]:
+            roof, other = dict(alu), hbm
+        else:
+            other = alu
+        roof["other_roof"] = {k: other[k] for k in ("bound", "achieved", "peak", "unit", "frac")}
+    roof.update({"kernel": kname, "alg_bytes_per_launch": alg_bytes, "launch_us": launch_s * 1e6,
+                 "steps_per_launch": K, "lane_elems": R,
+                 "note": "working set 2 x 33.6 MB fits the 256 MB Infinity Cache"})
 
     out = {
         "metric": "DOF-stage updates/s (fwd, adjoint) vs HBM roofline; batched vs plain",
@@ -272,10 +321,7 @@ def main():
                                f"PE size 256 (P={w.n_pe}), delays {{0..3}} p=(0.5,0.25,0.15,0.1) per stage",
                    "n_elem": w.n_elem, "degree": 3, "pe_size": 256, "rk": "rk4", "scheme": "adg_at",
                    "kernel": args.kernel, "dofs": dofs},
-        "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "alg_bytes_per_launch": alg_bytes, "launch_us": launch_s * 1e6,
-                     "note": "working set 2 x 33.6 MB fits the 256 MB Infinity Cache"},
+        "roofline": roof,
         "wall_s": wall,
         "state_finite": finite,
     }
@@ -299,7 +345,10 @@ def main():
         g, _ = time_solver(torch, so, uu, 100, 10)
         d24 = wl.n_elem * 4
         ex["n2^24_dof_stage_per_s"] = d24 * stages * 100 / g
-        ex["n2^24_hbm_frac"] = (BYTES_PER_DOF_STEP_FUSED * d24 + ring_bytes_per_step(wl)) / (g / 100) / 1e9 / HBM_PEAK_GBS
+        k24 = so.opt.fused_steps or 2  # library default shape (R = 1)
+        ex["n2^24_hbm_frac"] = ((BYTES_PER_DOF_STEP_FUSED * d24 + k24 * ring_bytes_per_step(wl))
+                                / (g * k24 / 100) / 1e9 / HBM_PEAK_GBS)
+        ex["n2^24_steps_per_launch"] = k24
         so.close()
         out["extras"] = ex
     if args.calib_copy_mib > 0:

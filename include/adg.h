@@ -103,12 +103,17 @@ typedef struct adg_problem {
 } adg_problem;
 
 typedef struct adg_options {
-  int64_t ckpt_every;          /* adjoint checkpoint interval in steps; 0 -> 64 */
+  int64_t ckpt_every;          /* adjoint checkpoint interval C in steps; 0 -> 64.  The recording keeps
+                                  ceil(n_steps_record / C) states and adg_adjoint recomputes each segment
+                                  once; C = 1 keeps every state (fused kernel: each recorded step writes
+                                  straight into its slot, and the adjoint recomputes nothing) */
   int32_t kernel;              /* adg_kernel; AUTO -> FUSED */
   int32_t lane_elems;          /* fused kernel: consecutive elements per lane, 1, 2 or 4 (<= every
                                   asynchronous problem's pe_size); 0 -> 1 */
   uint32_t flags;              /* reserved, 0 */
-  uint32_t reserved;
+  uint32_t fused_steps;        /* fused kernel: time steps per launch, 1 or 2 (halo of 2S elements per side,
+                                  half the state traffic per step); 0 -> 2.  Results are bitwise the same
+                                  with lane_elems 1, equal to rounding otherwise. */
 } adg_options;
 
 typedef struct adg_ctx adg_ctx;  /* opaque, host side, library owned */

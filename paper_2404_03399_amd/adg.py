@@ -53,7 +53,7 @@ class adg_problem(C.Structure):
 
 class adg_options(C.Structure):
     _fields_ = [("ckpt_every", C.c_int64), ("kernel", C.c_int32), ("lane_elems", C.c_int32),
-                ("flags", C.c_uint32), ("reserved", C.c_uint32)]
+                ("flags", C.c_uint32), ("fused_steps", C.c_uint32)]
 
 
 class AdgError(RuntimeError):

@@ -1,13 +1,18 @@
-"""Autotuner for the fused step kernel's elements per lane (1, 2 or 4).
+"""Autotuner for the fused step kernel's launch shape: elements per lane
+(1, 2 or 4) and time steps per launch (1 or 2).
 
-The best value depends on the problem set: register pressure grows with the
-elements per lane (fewer resident waves), while larger tiles cut the halo
-recompute and the number of waves.  The tuner times each admissible
-candidate on the caller's own problems (same kernels, a few graph-replayed
-steps on a scratch copy of the initial state) and caches the winner in a
-JSON file keyed by device, integrator, equation/flux, degrees and size.
+The best pair depends on the problem set: register pressure grows with the
+elements per lane (fewer resident waves), larger tiles cut the halo
+recompute and the number of waves, and two steps per launch halve the state
+traffic per step at the price of a wider halo.  The tuner times each
+admissible pair on the caller's own problems (same kernels, a few
+graph-replayed steps on a scratch copy of the initial state) and caches the
+winner in a JSON file keyed by device, integrator, equation/flux, degrees
+and size.  Every pair agrees with the others to rounding (bitwise across
+steps per launch with one element per lane).
 
-    R = autotune.lane_elems(workloads)            # tuned (or cached) value
+    R, K = autotune.tune(workloads)               # tuned (or cached) pair
+    R = autotune.lane_elems(workloads)            # its elements per lane
     Solver(workloads, lane_elems="auto")           # same, through the solver
 """
 from __future__ import annotations
@@ -15,9 +20,10 @@ from __future__ import annotations
 import json
 import math
 import os
-from typing import Iterable, List
+from typing import List, Tuple
 
 CANDIDATES = (1, 2, 4)
+STEPS_PER_LAUNCH = (1, 2)
 
 
 def cache_path() -> str:
@@ -35,11 +41,18 @@ def _key(workloads, device_name: str) -> str:
 
 
 def admissible(workloads) -> List[int]:
+    """Elements per lane the library accepts for these problems (<= every
+    asynchronous problem's PE size)."""
     pes = min((w.pe_size for w in workloads if w.scheme != "dg" and w.n_elem // w.pe_size > 1), default=1 << 30)
     return [r for r in CANDIDATES if r <= pes]
 
 
-def lane_elems(workloads, steps: int = 24, use_cache: bool = True, verbose: bool = False) -> int:
+def configs(workloads) -> List[Tuple[int, int]]:
+    return [(r, k) for r in admissible(workloads) for k in STEPS_PER_LAUNCH]
+
+
+def tune(workloads, steps: int = 24, use_cache: bool = True, verbose: bool = False) -> Tuple[int, int]:
+    """(elements per lane, steps per launch) with the shortest time per step."""
     import torch
     from .solver import Solver
 
@@ -55,11 +68,11 @@ def lane_elems(workloads, steps: int = 24, use_cache: bool = True, verbose: bool
             cache = json.load(open(path))
         except (OSError, ValueError):
             cache = {}
-        if key in cache:
-            return int(cache[key]["lane_elems"])
+        if key in cache and "fused_steps" in cache[key]:
+            return int(cache[key]["lane_elems"]), int(cache[key]["fused_steps"])
     timings = {}
-    for r in admissible(workloads):
-        s = Solver(workloads, lane_elems=r)
+    for r, k in configs(workloads):
+        s = Solver(workloads, lane_elems=r, fused_steps=k)
         u = s.initial_state()
         s.run(u, 4, graph=False)
         torch.cuda.synchronize()
@@ -69,16 +82,22 @@ def lane_elems(workloads, steps: int = 24, use_cache: bool = True, verbose: bool
         s.run(u, steps, graph=True)
         ev1.record()
         torch.cuda.synchronize()
-        timings[r] = ev0.elapsed_time(ev1) / steps
+        timings[(r, k)] = ev0.elapsed_time(ev1) / steps
         s.close()
     best = min(timings, key=timings.get)
     if verbose:
-        print(f"autotune {key}: " + ", ".join(f"R={r}: {t * 1e3:.2f} us" for r, t in timings.items()), flush=True)
+        print(f"autotune {key}: " + ", ".join(f"R={r} K={k}: {t * 1e3:.2f} us" for (r, k), t in timings.items()),
+              flush=True)
     if use_cache:
-        cache[key] = {"lane_elems": best, "ms_per_step": timings}
+        cache[key] = {"lane_elems": best[0], "fused_steps": best[1],
+                      "ms_per_step": {f"R={r},K={k}": t for (r, k), t in timings.items()}}
         os.makedirs(os.path.dirname(path), exist_ok=True)
         tmp = path + ".tmp"
         with open(tmp, "w") as fh:
-            json.dump(cache, fh, indent=1, default=str)
+            json.dump(cache, fh, indent=1)
         os.replace(tmp, path)
     return best
+
+
+def lane_elems(workloads, steps: int = 24, use_cache: bool = True, verbose: bool = False) -> int:
+    return tune(workloads, steps, use_cache, verbose)[0]

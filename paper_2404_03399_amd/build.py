@@ -15,7 +15,10 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIBDIR = os.path.join(PKG, "_lib")
 LIB = os.path.join(LIBDIR, "libadg.so")
-SOURCES = ["adg_kernels.hip", "adg_api.hip"]
+# (source, extra defines): the fused step is compiled once per integrator so
+# that its many instantiations build in parallel
+UNITS = [("adg_fused.hip", ["-DADG_RK=0"]), ("adg_fused.hip", ["-DADG_RK=1"]), ("adg_fused.hip", ["-DADG_RK=2"]),
+         ("adg_adjoint.hip", []), ("adg_kernels.hip", []), ("adg_api.hip", [])]
 ARCH = "gfx950"
 
 
@@ -28,7 +31,7 @@ def hipcc() -> str:
 
 def flags() -> list:
     return [
-        f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
+        f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
         # packed FP32 instructions stay off (only FP64 math here; belt and braces)
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
         "-Wall", "-Wno-unused-function",
@@ -36,10 +39,7 @@ def flags() -> list:
     ]
 
 
-def build(verbose: bool = False) -> str:
-    os.makedirs(LIBDIR, exist_ok=True)
-    tmp = LIB + ".tmp"
-    cmd = [hipcc()] + flags() + [os.path.join(CSRC, s) for s in SOURCES] + ["-o", tmp]
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
@@ -47,6 +47,26 @@ def build(verbose: bool = False) -> str:
         raise RuntimeError(f"hipcc failed ({res.returncode}):\n{res.stdout}\n{res.stderr}")
     if verbose and res.stderr.strip():
         print(res.stderr, file=sys.stderr)
+
+
+def build(verbose: bool = False, jobs: int = 0) -> str:
+    """Compile every unit to an object (in parallel), then link libadg.so."""
+    from concurrent.futures import ThreadPoolExecutor
+    objdir = os.path.join(LIBDIR, "obj")
+    os.makedirs(objdir, exist_ok=True)
+    cc = hipcc()
+    objs, cmds = [], []
+    for src, defs in UNITS:
+        tag = "".join(d.split("=")[-1] for d in defs)
+        obj = os.path.join(objdir, os.path.splitext(src)[0] + (f"_{tag}" if tag else "") + ".o")
+        objs.append(obj)
+        cmds.append([cc] + flags() + defs + ["-c", os.path.join(CSRC, src), "-o", obj])
+    jobs = jobs or max(1, min(len(cmds), (os.cpu_count() or 2) - 1))
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        for f in [ex.submit(_run, c, verbose) for c in cmds]:
+            f.result()
+    tmp = LIB + ".tmp"
+    _run([cc, f"--offload-arch={ARCH}", "-shared", "-fPIC"] + objs + ["-o", tmp], verbose)
     os.replace(tmp, LIB)
     return LIB
 

@@ -217,17 +217,17 @@ int validate(const adg_problem* probs, int32_t n) {
 }
 
 struct Layout {
-  int64_t probs, work_f, work_s, first_s, ctr, ring, atsum, atk, state2, y0, y1, acc, part, stats_out;
+  int64_t probs, work_f, work_f2, work_s, first_s, ctr, ring, atsum, atk, state2, y0, y1, acc, part, stats_out;
   int64_t groups, gstats;  // ensemble statistics: group CSR (2n+1 int32) and 4 doubles per group
   // adjoint recording (-1 if not recording); ckrec holds the fused kernel's
   // PE-face records (AT sums, delays) at every checkpoint plus one spare slot
   int64_t ckpt, useg, ybuf, lam, q, adjring, cpart, ckrec, work_a;
   int64_t total;
-  int32_t n_work_f, n_work_s, n_work_a;
+  int32_t n_work_f, n_work_f2, n_work_s, n_work_a;
   int64_t rec_atsum_bytes, rec_atk_bytes, rec_bytes;
   int64_t total_doubles;
   int64_t ring_doubles;
-  int64_t at_entries;  // boundaries x 2 parities (x S for the sums)
+  int64_t at_entries;  // boundaries x kRecSlots (x S for the sums)
   int64_t n_rec, ckpt_every, n_ckpt;
 };
 
@@ -248,6 +248,13 @@ int lane_elems_of(const adg_problem* probs, int32_t n, const adg_options* opt) {
   return req <= min_pes ? req : 0;
 }
 
+// Time steps per fused launch (0 if the request is invalid).
+int fused_steps_of(const adg_options* opt) {
+  const int req = opt ? (int)opt->fused_steps : 0;
+  if (req == 0) return 2;
+  return (req == 1 || req == 2) ? req : 0;
+}
+
 int kernel_of(const adg_options* opt) {
   if (!opt || opt->kernel == ADG_KERNEL_AUTO) return ADG_KERNEL_FUSED;
   return opt->kernel;
@@ -256,22 +263,26 @@ int kernel_of(const adg_options* opt) {
 Layout make_layout(const adg_problem* probs, int32_t n, const adg_options* opt, int64_t n_rec) {
   Layout L{};
   const int S = rk_stages((int)probs[0].rk);
-  const int T = fused_tile((int)probs[0].rk, std::max(1, lane_elems_of(probs, n, opt)));
+  const int R = std::max(1, lane_elems_of(probs, n, opt));
+  const int T = fused_tile((int)probs[0].rk, R, 1);
+  const int T2 = fused_tile((int)probs[0].rk, R, 2);
   const int T1 = adj_tile_elems((int)probs[0].rk, probs[0].equation == ADG_EQ_BURGERS);
-  int64_t nwf = 0, nws = 0, nwa = 0, tot = 0, ring = 0, at = 0;
+  int64_t nwf = 0, nwf2 = 0, nws = 0, nwa = 0, tot = 0, ring = 0, at = 0;
   for (int32_t i = 0; i < n; ++i) {
     const adg_problem& p = probs[i];
     nwf += (p.n_elem + T - 1) / T;
+    nwf2 += (p.n_elem + T2 - 1) / T2;
     nwa += (p.n_elem + T1 - 1) / T1;
     nws += (p.n_elem + kBlock - 1) / kBlock;
     tot += ld_of(p) * (p.degree + 1);
     if (async_of(p)) {
       ring += (p.n_elem / p.pe_size) * S * depth_of(p, n_rec);
-      at += 2 * (p.n_elem / p.pe_size);
+      at += kRecSlots * (p.n_elem / p.pe_size);
     }
   }
   L.at_entries = at;
   L.n_work_f = (int32_t)nwf;
+  L.n_work_f2 = (int32_t)nwf2;
   L.n_work_s = (int32_t)nws;
   L.n_work_a = n_rec > 0 ? (int32_t)nwa : 0;
   L.total_doubles = tot;
@@ -281,6 +292,7 @@ Layout make_layout(const adg_problem* probs, int32_t n, const adg_options* opt, 
   auto take = [&](int64_t bytes) { const int64_t o = off; off = align_up(off + bytes, kAlign); return o; };
   L.probs = take((int64_t)sizeof(DevProblem) * n);
   L.work_f = take((int64_t)sizeof(WorkItem) * nwf);
+  L.work_f2 = take((int64_t)sizeof(WorkItem) * nwf2);
   L.work_s = take((int64_t)sizeof(WorkItem) * nws);
   L.first_s = take((int64_t)sizeof(int32_t) * (n + 1));
   L.ctr = take(8 * sizeof(int64_t));
@@ -304,9 +316,11 @@ Layout make_layout(const adg_problem* probs, int32_t n, const adg_options* opt, 
   L.rec_atk_bytes = 4 * std::max<int64_t>(at, 1);
   L.rec_bytes = align_up(L.rec_atsum_bytes, kAlign) + align_up(L.rec_atk_bytes, kAlign);
   if (rec) {
+    // stage kernels recompute a segment into seg slots; the fused adjoint
+    // reads the segment's first state from its checkpoint and needs seg - 1
     const int64_t seg = std::min<int64_t>(L.ckpt_every, n_rec);
     L.ckpt = take(8 * tot * L.n_ckpt);
-    L.useg = take(8 * tot * seg);
+    L.useg = take(8 * tot * (kern == ADG_KERNEL_STAGE ? seg : std::max<int64_t>(seg - 1, 1)));
     L.lam = take(8 * tot * 2);
     L.adjring = take(8 * std::max<int64_t>(ring, 1));
     if (kern == ADG_KERNEL_STAGE) {
@@ -343,15 +357,16 @@ struct adg_ctx {
   const double* graph_u = nullptr;
   int graph_steps = 0;
 
-  int32_t group[5] = {0, 0, 0, 0, 0};
-  int32_t grid[4] = {1, 1, 1, 1};
+  int32_t group[2][5] = {{0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}};  // fused work lists, 1 and 2 steps per launch
+  int32_t grid[2][4] = {{1, 1, 1, 1}, {1, 1, 1, 1}};
   int32_t lane_elems = 2;
+  int32_t fused_steps = 2;
   // fused adjoint work list (recording contexts of the fused kernel)
   std::vector<WorkItem> work_a;
   int32_t group_a[5] = {0, 0, 0, 0, 0};
   int32_t grid_a[4] = {1, 1, 1, 1};
 
-  StepArgs base_args(int64_t work_off, int32_t n_work) const {
+  StepArgs base_args(int64_t work_off, int32_t n_work, int K = 1) const {
     StepArgs a{};
     a.probs = (const DevProblem*)(ws + L.probs);
     a.work = (const WorkItem*)(ws + work_off);
@@ -360,12 +375,15 @@ struct adg_ctx {
     a.ctr = (int64_t*)(ws + L.ctr);
     a.atsum = (double*)(ws + L.atsum);
     a.atk = (int32_t*)(ws + L.atk);
-    for (int i = 0; i < 5; ++i) a.group[i] = group[i];
-    for (int i = 0; i < 4; ++i) a.grid[i] = grid[i];
+    for (int i = 0; i < 5; ++i) a.group[i] = group[K - 1][i];
+    for (int i = 0; i < 4; ++i) a.grid[i] = grid[K - 1][i];
     a.lane_elems = lane_elems;
+    a.steps = K;
     return a;
   }
-  StepArgs fused_args() const { return base_args(L.work_f, L.n_work_f); }
+  StepArgs fused_args(int K = 1) const {
+    return K == 2 ? base_args(L.work_f2, L.n_work_f2, 2) : base_args(L.work_f, L.n_work_f, 1);
+  }
   StepArgs stage_args() const { return base_args(L.work_s, L.n_work_s); }
   AdjArgs adj_args() const {
     AdjArgs a{};
@@ -393,11 +411,11 @@ struct adg_ctx {
 
 namespace {
 
-// Enqueue one step; for the fused kernel the result lands in *cur after a
-// swap with the internal buffer.
-int enqueue_step(adg_ctx* c, double** cur, double** other, int32_t step_offset, hipStream_t st) {
+// Enqueue K steps (K = 2 only for the fused kernel); for the fused kernel the
+// result lands in *cur after a swap with the internal buffer.
+int enqueue_steps(adg_ctx* c, double** cur, double** other, int32_t step_offset, int K, hipStream_t st) {
   if (c->kernel == ADG_KERNEL_FUSED) {
-    const StepArgs a = c->fused_args();
+    const StepArgs a = c->fused_args(K);
     ADG_HIP(launch_fused_step(c->rk, c->fused_phys, a, *cur, *other, step_offset, st));
     std::swap(*cur, *other);
     return ADG_OK;
@@ -407,10 +425,23 @@ int enqueue_step(adg_ctx* c, double** cur, double** other, int32_t step_offset, 
   double* Y0 = (double*)(c->ws + c->L.y0);
   double* Y1 = (double*)(c->ws + c->L.y1);
   double* A = (double*)(c->ws + c->L.acc);
-  for (int s = 0; s < c->S; ++s) {
-    const double* yin = s == 0 ? U : ((s & 1) ? Y0 : Y1);
-    double* yout = (s & 1) ? Y1 : Y0;
-    ADG_HIP(launch_stage(c->rk, c->phys, s, a, yin, yout, U, A, step_offset, st));
+  for (int k = 0; k < K; ++k)
+    for (int s = 0; s < c->S; ++s) {
+      const double* yin = s == 0 ? U : ((s & 1) ? Y0 : Y1);
+      double* yout = (s & 1) ? Y1 : Y0;
+      ADG_HIP(launch_stage(c->rk, c->phys, s, a, yin, yout, U, A, step_offset + k, st));
+    }
+  return ADG_OK;
+}
+
+// Steps [0, m) of a batch: two per launch where the kernel allows.
+int enqueue_batch(adg_ctx* c, double** cur, double** other, int32_t m, hipStream_t st) {
+  const int kmax = c->kernel == ADG_KERNEL_FUSED ? c->fused_steps : 1;
+  for (int32_t i = 0; i < m;) {
+    const int K = (kmax == 2 && i + 1 < m) ? 2 : 1;
+    const int rc = enqueue_steps(c, cur, other, i, K, st);
+    if (rc) return rc;
+    i += K;
   }
   return ADG_OK;
 }
@@ -446,7 +477,7 @@ int build_graph(adg_ctx* c, double* d_u) {
   }
   double* cur = d_u;
   double* other = c->state2();
-  for (int i = 0; i < kGraphSteps && rc == ADG_OK; ++i) rc = enqueue_step(c, &cur, &other, i, cap);
+  rc = enqueue_batch(c, &cur, &other, kGraphSteps, cap);
   if (rc == ADG_OK && launch_advance((int64_t*)(c->ws + c->L.ctr), kGraphSteps, cap) != hipSuccess)
     rc = fail(ADG_E_HIP, "capture of the step-counter advance failed");
   const hipError_t e1 = hipStreamEndCapture(cap, &g);
@@ -504,6 +535,7 @@ int adg_workspace_size(const adg_problem* probs, int32_t n_probs, const adg_opti
   if (k != ADG_KERNEL_FUSED && k != ADG_KERNEL_STAGE) return fail(ADG_E_INVALID, "unknown kernel family");
   if (lane_elems_of(probs, n_probs, opt) == 0)
     return fail(ADG_E_INVALID, "lane_elems must be 1, 2 or 4 and not exceed the PE size");
+  if (fused_steps_of(opt) == 0) return fail(ADG_E_INVALID, "fused_steps must be 0, 1 or 2");
   *bytes_out = make_layout(probs, n_probs, opt, n_steps_record).total;
   return ADG_OK;
 }
@@ -568,7 +600,7 @@ int adg_init(adg_ctx** out, const adg_problem* probs, int32_t n_probs, const adg
     d.atk_off = aoff;
     if (d.async_faces) {
       roff += d.n_pe * c->S * (int64_t)d.depth;
-      aoff += 2 * d.n_pe;
+      aoff += kRecSlots * d.n_pe;
     }
     d.seed = p.seed;
     for (int k = 0; k + 1 < d.n_delays; ++k) d.thr[k] = p.delay_threshold[k];
@@ -593,26 +625,35 @@ int adg_init(adg_ctx** out, const adg_problem* probs, int32_t n_probs, const adg
     for (int k = 0; k < d.n_delays; ++k)
       for (int j = 0; j < d.q; ++j) d.atc[k][j] = at_coefficient(d.q, k, j);
   }
+  if (roff != c->L.ring_doubles || aoff != c->L.at_entries) {
+    delete c;
+    return fail(ADG_E_INVALID, "internal: ring or record layout does not match the workspace layout");
+  }
   // work lists: heaviest (highest degree) problems first
   std::vector<int32_t> order(n_probs);
   for (int32_t i = 0; i < n_probs; ++i) order[i] = i;
   std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return probs[a].degree > probs[b].degree; });
   c->lane_elems = lane_elems_of(probs, n_probs, opt);
-  const int T = fused_tile(c->rk, c->lane_elems);
-  std::vector<WorkItem> wf, ws_;
+  c->fused_steps = fused_steps_of(opt);
+  std::vector<WorkItem> wfk[2], ws_;
   std::vector<int32_t> first(n_probs + 1, 0);
-  wf.reserve(c->L.n_work_f);
-  // ranges per degree, np = 5, 4, 3, 2 (order is sorted by degree, descending)
-  for (int np = 5, gi = 0; np >= 2; --np, ++gi) {
-    c->group[gi] = (int32_t)wf.size();
-    for (int32_t i : order) {
-      if ((int)probs[i].degree + 1 != np) continue;
-      const int64_t nt = (probs[i].n_elem + T - 1) / T;
-      for (int64_t t = 0; t < nt; ++t) wf.push_back(WorkItem{i, (int32_t)t});
+  for (int K = 1; K <= 2; ++K) {
+    const int T = fused_tile(c->rk, c->lane_elems, K);
+    std::vector<WorkItem>& wf = wfk[K - 1];
+    wf.reserve(K == 1 ? c->L.n_work_f : c->L.n_work_f2);
+    // ranges per degree, np = 5, 4, 3, 2 (order is sorted by degree, descending)
+    for (int np = 5, gi = 0; np >= 2; --np, ++gi) {
+      c->group[K - 1][gi] = (int32_t)wf.size();
+      for (int32_t i : order) {
+        if ((int)probs[i].degree + 1 != np) continue;
+        const int64_t nt = (probs[i].n_elem + T - 1) / T;
+        for (int64_t t = 0; t < nt; ++t) wf.push_back(WorkItem{i, (int32_t)t});
+      }
     }
+    c->group[K - 1][4] = (int32_t)wf.size();
+    for (int gi = 0; gi < 4; ++gi)
+      c->grid[K - 1][gi] = fused_grid(c->group[K - 1][gi + 1] - c->group[K - 1][gi]);
   }
-  c->group[4] = (int32_t)wf.size();
-  for (int gi = 0; gi < 4; ++gi) c->grid[gi] = fused_grid(c->group[gi + 1] - c->group[gi]);
   for (int32_t i = 0; i < n_probs; ++i) {  // stage/stats list in problem order (contiguous per problem)
     first[i] = (int32_t)ws_.size();
     const int64_t nt = (probs[i].n_elem + kBlock - 1) / kBlock;
@@ -639,7 +680,8 @@ int adg_init(adg_ctx** out, const adg_problem* probs, int32_t n_probs, const adg
     return ADG_OK;
   };
   if ((rc = up(c->L.probs, c->dev.data(), (int64_t)sizeof(DevProblem) * n_probs)) ||
-      (rc = up(c->L.work_f, wf.data(), (int64_t)sizeof(WorkItem) * wf.size())) ||
+      (rc = up(c->L.work_f, wfk[0].data(), (int64_t)sizeof(WorkItem) * wfk[0].size())) ||
+      (rc = up(c->L.work_f2, wfk[1].data(), (int64_t)sizeof(WorkItem) * wfk[1].size())) ||
       (rc = up(c->L.work_s, ws_.data(), (int64_t)sizeof(WorkItem) * ws_.size())) ||
       (rc = up(c->L.first_s, first.data(), (int64_t)sizeof(int32_t) * first.size())) ||
       (c->L.work_a >= 0 &&
@@ -680,6 +722,27 @@ int adg_run(adg_ctx* c, double* d_u, int64_t n_steps, uint32_t flags) {
     const int64_t C = c->L.ckpt_every, tot = c->L.total_doubles;
     int64_t done = 0;
     int rc;
+    if (C == 1 && c->kernel == ADG_KERNEL_FUSED) {
+      // every state is kept: each step writes its result straight into the
+      // next checkpoint slot (the last one into d_u), no copies
+      double* ck = (double*)(c->ws + c->L.ckpt);
+      ADG_HIP(hipMemcpyAsync(ck, d_u, 8 * tot, hipMemcpyDeviceToDevice, c->stream));
+      const StepArgs fa = c->fused_args();
+      while (done < n_steps) {
+        const int32_t m = (int32_t)std::min<int64_t>(n_steps - done, kGraphSteps);
+        for (int32_t i = 0; i < m; ++i) {
+          const int64_t n = done + i;
+          double* dst = n + 1 < n_steps ? ck + tot * (n + 1) : d_u;
+          ADG_HIP(launch_fused_step(c->rk, c->fused_phys, fa, ck + tot * n, dst, i, c->stream));
+        }
+        ADG_HIP(launch_advance((int64_t*)(c->ws + c->L.ctr), m, c->stream));
+        done += m;
+      }
+      c->steps += n_steps;
+      c->rec_steps = n_steps;
+      if (flags & ADG_RUN_CHECK_FINITE) return adg_run(c, d_u, 0, ADG_RUN_CHECK_FINITE);
+      return ADG_OK;
+    }
     for (int64_t k = 0; done < n_steps; ++k) {
       ADG_HIP(hipMemcpyAsync(c->ws + c->L.ckpt + 8 * tot * k, d_u, 8 * tot, hipMemcpyDeviceToDevice, c->stream));
       if ((rc = c->save_records(k, false))) return rc;
@@ -709,8 +772,7 @@ int adg_run(adg_ctx* c, double* d_u, int64_t n_steps, uint32_t flags) {
   // counter advance
   while (left > 0) {
     const int32_t m = (int32_t)std::min<int64_t>(left, kGraphSteps);
-    for (int32_t i = 0; i < m; ++i)
-      if ((rc = enqueue_step(c, &cur, &other, i, c->stream))) return rc;
+    if ((rc = enqueue_batch(c, &cur, &other, m, c->stream))) return rc;
     ADG_HIP(launch_advance((int64_t*)(c->ws + c->L.ctr), m, c->stream));
     left -= m;
   }
@@ -861,14 +923,15 @@ int adjoint_fused(adg_ctx* c, const double* d_cot_uT, double* d_grad_u0, double*
     const int64_t n0 = k * C;
     const int64_t len = std::min<int64_t>(C, N - n0);
     if (len <= 0) continue;
-    ADG_HIP(hipMemcpyAsync(useg, ws + L.ckpt + 8 * tot * k, bytes, hipMemcpyDeviceToDevice, st));
-    if ((rc = c->save_records(k, true))) return rc;
+    // u^{n0+i}: the checkpoint itself for i = 0, recomputed into useg[i-1] after
+    double* ck = (double*)(ws + L.ckpt) + tot * k;
+    auto state = [&](int64_t i) { return i == 0 ? ck : useg + tot * (i - 1); };
+    if (len > 1 && (rc = c->save_records(k, true))) return rc;
     for (int64_t i = 1; i < len; ++i)
-      ADG_HIP(launch_fused_step(c->rk, c->fused_phys, fa, useg + tot * (i - 1), useg + tot * i,
-                                (int32_t)(n0 + i - 1), st));
+      ADG_HIP(launch_fused_step(c->rk, c->fused_phys, fa, state(i - 1), state(i), (int32_t)(n0 + i - 1), st));
     for (int64_t i = len - 1; i >= 0; --i) {
-      ADG_HIP(launch_adj_fused(c->rk, c->phys, aa, useg + tot * i, lam, lamu, ring, adjring, cpart,
-                               (int32_t)(n0 + i), st));
+      ADG_HIP(launch_adj_fused(c->rk, c->phys, aa, state(i), lam, lamu, ring, adjring, cpart, (int32_t)(n0 + i),
+                               st));
       std::swap(lam, lamu);
     }
   }

@@ -10,6 +10,7 @@ constexpr int kMaxNp = 5;     // degree <= 4
 constexpr int kMaxL = 8;      // delays 0..7
 constexpr int kMaxQ = 5;      // AT levels
 constexpr int kBlock = 256;   // threads per workgroup (4 wave64)
+constexpr int kRecSlots = 3;  // fused kernel PE-face record slots, indexed by step mod 3
 
 // PHYS_ADV_UPWIND_POS: upwind advection with a > 0 in the fused kernel, which
 // folds the right-face flux a u_p into the volume operator.
@@ -54,8 +55,8 @@ struct DevProblem {
   int64_t ld;            // plane stride of the state
   int64_t u_off;         // offset of the problem in the state vector
   int64_t ring_off;      // offset of the problem's delay ring (doubles)
-  int64_t at_off;        // offset of the problem's AT sums ([2][P][S] doubles)
-  int64_t atk_off;       // offset of the problem's delays ([2][P] words, byte s = stage s)
+  int64_t at_off;        // offset of the problem's AT sums ([kRecSlots][P][S] doubles)
+  int64_t atk_off;       // offset of the problem's delays ([kRecSlots][P] words, byte s = stage s)
   int32_t np;            // degree + 1
   int32_t q;             // AT levels (1 for ADG)
   int32_t n_delays;      // L

@@ -1,0 +1,271 @@
+// Device helpers shared by the HIP kernels (gfx950, FP64) of the asynchronous
+// DG stepper with AT fluxes: physics, the PE-face ring, the element operator,
+// the RK updates, lane shifts and the Butcher tables of the adjoint.
+//
+// Element update of the reference-element weak form (paper Sec. 2):
+//   du^e/dt = (2/dx) ( D f(u^e) + l_l F_e - l_r F_{e+1} ),  D = M^-1 S,
+//   l_l = M^-1 phi(-1), l_r = M^-1 phi(1),
+// with one numerical flux per face shared by both neighbours (conservation,
+// Sec. 4.1).  At PE faces the flux is the AT combination of delayed levels
+// (Sec. 5): F = sum_{j<q} c_j(k) F^{n-k-j}, read from a per-(boundary, stage)
+// ring of past face fluxes.
+//
+// Layout: structure of arrays, u[off + j*ld + e]; lane = element, so every
+// node-plane load/store of a wave64 is one contiguous 512-byte segment.
+// Neighbour traces come through DPP lane shifts (fused kernels) or through the cache
+// from the neighbouring lanes' own loads (stage kernel).  No MFMA: the
+// per-element operators are at most 5x5.
+#pragma once
+
+#include "adg_launch.hpp"
+
+namespace adg {
+
+// ---------------------------------------------------------------- physics ---
+template <int PHYS>
+struct Physics;
+
+template <>
+struct Physics<PHYS_ADV_UPWIND> {
+  __device__ static double f(double u, double a) { return a * u; }
+  __device__ static double fhat(double um, double up, double a) { return a >= 0.0 ? a * um : a * up; }
+};
+
+template <>
+struct Physics<PHYS_ADV_UPWIND_POS> {
+  __device__ static double f(double u, double a) { return a * u; }
+  __device__ static double fhat(double um, double, double a) { return a * um; }
+};
+
+template <>
+struct Physics<PHYS_ADV_CENTRAL> {
+  __device__ static double f(double u, double a) { return a * u; }
+  __device__ static double fhat(double um, double up, double a) { return a * (0.5 * um + 0.5 * up); }
+};
+
+template <>
+struct Physics<PHYS_BURGERS_LLF> {
+  __device__ static double f(double u, double) { return 0.5 * u * u; }
+  __device__ static double fhat(double um, double up, double) {
+    const double lam = fmax(fabs(um), fabs(up));
+    return 0.5 * (0.5 * um * um + 0.5 * up * up) - 0.5 * lam * (up - um);
+  }
+};
+
+// ------------------------------------------------------- PE-face AT flux ---
+// Slot of level n - back (0 <= back < depth) given slot_n = n mod depth.
+__device__ __forceinline__ int ring_slot(int slot_n, int back, int depth) {
+  const int s = slot_n - back;
+  return s < 0 ? s + depth : s;
+}
+
+// Clamped delay of boundary b at (step n, stage s).
+__device__ __forceinline__ int pe_delay(const DevProblem& P, int64_t n, int s, uint32_t b) {
+  const int key = P.per_stage ? s : 0;
+  return clamp_delay(draw_delay(P.seed, n, key, (int64_t)b, P.thr, P.n_delays), n, P.q);
+}
+
+// sum_{j<q} c_j(k) F^{n-k-j} over the ring of (boundary, stage); k >= 1, so
+// every level is a past one.
+__device__ __forceinline__ double at_past_sum(const DevProblem& P, const double* __restrict__ r, int k,
+                                              int slot_n) {
+  double acc = 0.0;  // oldest level first, as in every other path
+  for (int j = P.q - 1; j >= 0; --j) acc += P.atc[k][j] * r[ring_slot(slot_n, k + j, P.depth)];
+  return acc;
+}
+
+// (2/dx) ( D f(y) + l_l fl - l_r fr ) with the operators held in registers.
+template <int NP, int PHYS>
+__device__ __forceinline__ void element_rhs(const double (&Dm)[NP][NP], const double (&ll)[NP],
+                                            const double (&lr)[NP], double two_dx, double a,
+                                            const double (&y)[NP], double fl, double fr, double (&k)[NP]) {
+  double fy[NP];
+#pragma unroll
+  for (int j = 0; j < NP; ++j) fy[j] = Physics<PHYS>::f(y[j], a);
+#pragma unroll
+  for (int i = 0; i < NP; ++i) {
+    double v = 0.0;
+#pragma unroll
+    for (int j = 0; j < NP; ++j) v += Dm[i][j] * fy[j];
+    k[i] = two_dx * (v + ll[i] * fl - lr[i] * fr);
+  }
+}
+
+template <int NP>
+__device__ __forceinline__ void load_operators(const DevProblem& P, double (&Dm)[NP][NP], double (&ll)[NP],
+                                               double (&lr)[NP]) {
+#pragma unroll
+  for (int i = 0; i < NP; ++i) {
+#pragma unroll
+    for (int j = 0; j < NP; ++j) Dm[i][j] = P.D[i * kMaxNp + j];
+    ll[i] = P.lift_l[i];
+    lr[i] = P.lift_r[i];
+  }
+}
+
+// RK update after the stage-s operator value k (oracle's algebraic forms).
+// u0: u^n; y: stage input (in) -> next stage input or u^{n+1} (out);
+// ks: RK4 running sum k1 + 2k2 + 2k3, Heun k1 = dt L(u^n).
+template <int NP, int RK>
+__device__ __forceinline__ void rk_update(int s, double dt, const double (&u0)[NP], double (&y)[NP],
+                                          double (&ks)[NP], const double (&k)[NP]) {
+  if constexpr (RK == RK_RK4) {
+    if (s == 0) {
+#pragma unroll
+      for (int j = 0; j < NP; ++j) { ks[j] = k[j]; y[j] = u0[j] + (0.5 * dt) * k[j]; }
+    } else if (s == 1) {
+#pragma unroll
+      for (int j = 0; j < NP; ++j) { ks[j] = ks[j] + 2.0 * k[j]; y[j] = u0[j] + (0.5 * dt) * k[j]; }
+    } else if (s == 2) {
+#pragma unroll
+      for (int j = 0; j < NP; ++j) { ks[j] = ks[j] + 2.0 * k[j]; y[j] = u0[j] + dt * k[j]; }
+    } else {
+#pragma unroll
+      for (int j = 0; j < NP; ++j) y[j] = u0[j] + (dt / 6.0) * (ks[j] + k[j]);
+    }
+  } else if constexpr (RK == RK_SSP3) {
+    if (s == 0) {
+#pragma unroll
+      for (int j = 0; j < NP; ++j) y[j] = u0[j] + dt * k[j];
+    } else if (s == 1) {
+#pragma unroll
+      for (int j = 0; j < NP; ++j) y[j] = 0.75 * u0[j] + 0.25 * (y[j] + dt * k[j]);
+    } else {
+#pragma unroll
+      for (int j = 0; j < NP; ++j) y[j] = u0[j] / 3.0 + (2.0 / 3.0) * (y[j] + dt * k[j]);
+    }
+  } else {  // Heun
+    if (s == 0) {
+#pragma unroll
+      for (int j = 0; j < NP; ++j) { ks[j] = dt * k[j]; y[j] = u0[j] + ks[j]; }
+    } else {
+#pragma unroll
+      for (int j = 0; j < NP; ++j) y[j] = u0[j] + 0.5 * (ks[j] + dt * k[j]);
+    }
+  }
+}
+
+// Element index of virtual position x on the periodic mesh of N elements.
+__device__ __forceinline__ int wrap_elem(int x, int N) {
+  while (x < 0) x += N;
+  while (x >= N) x -= N;
+  return x;
+}
+
+// Same for -N <= x < 2N (one correction at most).
+__device__ __forceinline__ int wrap_once(int x, int N) {
+  const int y = x < 0 ? x + N : x;
+  return y >= N ? y - N : y;
+}
+
+// ------------------------------------------------------ fused step kernel ---
+constexpr int kMaxStages = 4;
+
+// Workgroups are dispatched to the 8 XCDs round robin (workgroup i to XCD
+// i mod 8), and each XCD has its own L2.  Renumbering so that XCD x runs a
+// contiguous range of tiles makes the halo elements shared by neighbouring
+// workgroups hit in the same L2 instead of being fetched twice from HBM.
+// A bijection of [0, nb) whatever the dispatch order.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_block(int i, int nb) {
+  const int q = nb / kXcds, r = nb % kXcds;
+  const int x = i % kXcds, k = i / kXcds;
+  return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+}
+
+// Lane shifts across the whole wave64 (DPP wave_shr:1 / wave_shl:1): lane l
+// receives lane l-1 (resp. l+1); the lane without a source receives 0
+// (bound_ctrl).
+__device__ __forceinline__ double lane_from_left(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x138, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x138, 0xf, 0xf, true);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double lane_from_right(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x130, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x130, 0xf, 0xf, true);
+  return __hiloint2double(hi, lo);
+}
+
+// Per-lane PE-face values (written and read by the same lane only): the AT
+// flux of the current step per stage, and for a two-step launch the AT sums
+// of the second step.  With R <= PE size a lane's R left faces hold at most
+// one PE face.
+template <int K>
+struct WaveSmemK {
+  double at[K][kWavesPerBlock][kMaxStages][kWave];
+};
+
+template <int NP, int PHYS>
+__device__ __forceinline__ void folded_rhs(const DevProblem& P, const double (&y)[NP], double fl, double fr,
+                                           double (&k)[NP]) {
+  double g[NP];
+#pragma unroll
+  for (int j = 0; j < NP; ++j) g[j] = PHYS == PHYS_BURGERS_LLF ? y[j] * y[j] : y[j];
+#pragma unroll
+  for (int i = 0; i < NP; ++i) {
+    double v = P.Kl[i] * fl - P.Kr[i] * fr;
+#pragma unroll
+    for (int j = 0; j < NP; ++j) v += P.Kd[i * kMaxNp + j] * g[j];
+    k[i] = v;
+  }
+}
+
+struct FusedPtrs {
+  double* __restrict__ ring;
+  double* __restrict__ atsum;
+  int32_t* __restrict__ atk;
+};
+
+// Record slot of step m (steps below 2^31).
+__device__ __forceinline__ int64_t rec_slot(int64_t m) { return (int64_t)((uint32_t)m % (uint32_t)kRecSlots); }
+
+// Partial AT sum of step m over the levels m - kd - j, j = q-1 down to jmin,
+// oldest first (the order every path uses, so that a sum finished later with
+// its newest level is bitwise the one-pass sum).  slot_prev = slot of level
+// m - 1, all levels read here are at most m - 1.
+__device__ __forceinline__ double at_sum_from(const DevProblem& P, const double* __restrict__ rb, int kd, int jmin,
+                                              int slot_prev, int depth) {
+  double acc = 0.0;
+  for (int j = P.q - 1; j >= jmin; --j) acc += P.atc[kd][j] * rb[ring_slot(slot_prev, kd + j - 1, depth)];
+  return acc;
+}
+
+// --------------------------------------------------------------- adjoint ---
+// Butcher form of the three integrators (the same maps as the forward
+// algebraic forms): Y_i = U + dt sum_{j<i} a_ij K_j, U' = U + dt sum_i b_i K_i.
+template <int RK>
+__device__ constexpr double bt_a(int i, int j) {
+  if constexpr (RK == RK_RK4) return (j == i - 1) ? (i == 3 ? 1.0 : 0.5) : 0.0;
+  else if constexpr (RK == RK_SSP3) return i == 1 ? (j == 0 ? 1.0 : 0.0) : (i == 2 && j < 2 ? 0.25 : 0.0);
+  else return (i == 1 && j == 0) ? 1.0 : 0.0;
+}
+template <int RK>
+__device__ constexpr double bt_b(int i) {
+  if constexpr (RK == RK_RK4) return (i == 0 || i == 3) ? 1.0 / 6.0 : 1.0 / 3.0;
+  else if constexpr (RK == RK_SSP3) return i == 2 ? 2.0 / 3.0 : 1.0 / 6.0;
+  else return 0.5;
+}
+
+// (d fhat / d u-, d fhat / d u+); local Lax-Friedrichs on the branch taken
+// (ties pick u-), d|u|/du = sign(u) with sign(0) = +1.
+template <int PHYS>
+__device__ __forceinline__ void flux_partials(double um, double up, double a, double& dm, double& dp) {
+  if constexpr (PHYS == PHYS_ADV_UPWIND) {
+    dm = a >= 0.0 ? a : 0.0;
+    dp = a >= 0.0 ? 0.0 : a;
+  } else if constexpr (PHYS == PHYS_ADV_CENTRAL) {
+    dm = 0.5 * a;
+    dp = 0.5 * a;
+  } else {
+    const bool pick_m = fabs(um) >= fabs(up);
+    const double lam = pick_m ? fabs(um) : fabs(up);
+    const double dl_m = pick_m ? (um >= 0.0 ? 1.0 : -1.0) : 0.0;
+    const double dl_p = pick_m ? 0.0 : (up >= 0.0 ? 1.0 : -1.0);
+    const double jump = up - um;
+    dm = 0.5 * um - 0.5 * dl_m * jump + 0.5 * lam;
+    dp = 0.5 * up - 0.5 * dl_p * jump - 0.5 * lam;
+  }
+}
+
+}  // namespace adg

@@ -1,0 +1,310 @@
+// Fused step kernel: one wave64 per tile, all RK stages of one or two time
+// steps on chip.  Compiled once per integrator (-DADG_RK=0, 1, 2) so that the
+// instantiations build in parallel.
+#include "adg_device.hpp"
+
+#ifndef ADG_RK
+#error "compile once per integrator with -DADG_RK=0, 1 or 2"
+#endif
+
+namespace adg {
+
+// One wave64 = one tile of T owned elements plus HL halo lanes per side,
+// R consecutive elements per lane (16- or 32-byte accesses per plane), and
+// K time steps per launch.  Each stage shrinks the valid range by one element
+// per side, so after K*S stages the owned lanes are exact.  Halo elements are
+// recomputed with the same instructions as by their owners, so a face shared
+// by two waves gets a bitwise-identical flux on both sides.  Each lane
+// computes the fluxes of the left faces of its elements; the right face of
+// its last element is the next lane's first left face, received by a lane
+// shift.  No workgroup barrier: the waves of a workgroup are independent.
+//
+// PE faces (Secs. 3-5): at step m the lane owning the element right of PE
+// face b writes the level-m flux of every stage into the ring.  The AT fluxes
+// of the launch's first step n come from the records (delays and AT sums of
+// past levels) written by the previous launch into slot n mod 3.  For K = 2
+// every lane with a PE face forms the second step's AT sums itself: the levels
+// up to n - 1 are in the ring before the launch, and level n is the raw flux
+// the lane has just computed (the owner's ring write of level n is not read in
+// this launch, so halo copies in other waves never race with it).  At the end
+// the owner computes the records of step n + K into slot (n + K) mod 3, which
+// no wave of this launch reads.  A delay of 0 selects the synchronous flux.
+template <int NP, int RK, int PHYS, int R, int K>
+__device__ __forceinline__ void wave_tile(const DevProblem& P, const WorkItem wi, const FusedPtrs& A, int64_t n,
+                                          const double* __restrict__ uin, double* __restrict__ uout,
+                                          WaveSmemK<K>& sm, int wv, int lane) {
+  constexpr int S = rk_stages(RK);
+  constexpr int HL = fused_halo(RK, R, K);
+  constexpr int T = fused_tile(RK, R, K);
+  const int N = (int)P.n_elem;
+  const int e0 = wi.tile * T;
+  const int teff = (N - e0) < T ? (N - e0) : T;
+  const int xb = e0 - R * HL;  // element position of lane 0, element 0 (a multiple of R)
+  // With N a multiple of R a lane's R elements never straddle the periodic
+  // wrap, so one R*8-byte access per plane serves them all.
+  const bool grouped = R > 1 && (N % R) == 0;
+  const int64_t ld = P.ld;
+  const double* __restrict__ u = uin + P.u_off;
+  const bool lane_owned = lane >= HL && lane < kWave - HL;
+
+  const bool tiny = N < kWave * R;  // the wave's extent may wrap more than once
+  int e[R];
+  bool owned[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int x = xb + R * lane + r;
+    e[r] = tiny ? wrap_elem(x, N) : wrap_once(x, N);
+    owned[r] = lane_owned && (x - e0) < teff;
+  }
+  double u0[R][NP];
+  if (grouped) {
+    const double2* __restrict__ u2 = reinterpret_cast<const double2*>(__builtin_assume_aligned(u, 16));
+#pragma unroll
+    for (int j = 0; j < NP; ++j)
+#pragma unroll
+      for (int r = 0; r < R; r += 2) {
+        const double2 v = u2[(j * ld + e[0] + r) >> 1];
+        u0[r][j] = v.x;
+        u0[r + 1 < R ? r + 1 : r][j] = R > 1 ? v.y : v.x;
+      }
+  } else {
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int j = 0; j < NP; ++j) u0[r][j] = u[j * ld + e[r]];
+  }
+
+  // the PE face among this lane's left faces (if any) and its step-n record
+  bool pe[R];           // element r's left face is a PE face (at most one r)
+  bool pe_right = false;  // the right face of element R-1 is a PE face
+  bool any_pe = false;
+  uint32_t b = 0;       // its boundary index
+  int32_t kp[K];        // delays of step n + kk, byte s = stage s
+  int depth = 1, slot_n = 0;
+#pragma unroll
+  for (int kk = 0; kk < K; ++kk) kp[kk] = 0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) pe[r] = false;
+  if (P.async_faces) {
+    depth = P.depth;
+    const uint32_t n32 = (uint32_t)n;  // step indices stay below 2^31
+    slot_n = (int)(n32 - fast_div(n32, P.depth_div) * (uint32_t)depth);
+    const uint32_t pes = P.pe_div.d;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const uint32_t br = fast_div((uint32_t)e[r], P.pe_div);
+      pe[r] = (uint32_t)e[r] == br * pes;
+      if (pe[r]) b = br;
+      any_pe = any_pe || pe[r];
+    }
+    const uint32_t e1 = (e[R - 1] + 1 == N) ? 0u : (uint32_t)(e[R - 1] + 1);
+    pe_right = e1 == fast_div(e1, P.pe_div) * pes;
+    if (any_pe) {
+      const int64_t rs = rec_slot(n);
+      kp[0] = A.atk[P.atk_off + rs * P.n_pe + b];
+      const double* __restrict__ src = A.atsum + P.at_off + (rs * P.n_pe + b) * S;
+#pragma unroll
+      for (int s = 0; s < S; ++s) sm.at[0][wv][s][lane] = src[s];
+      if constexpr (K == 2) {
+        // step n + 1: delays, and the AT sums over the levels up to n - 1
+        const int64_t n1 = n + 1;
+        const double* __restrict__ rb0 = A.ring + P.ring_off + (int64_t)b * S * depth;
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+          const int kd = clamp_delay(delay_from_prefix(delay_prefix(P.seed, n1, P.per_stage ? s : 0), b, P.thr,
+                                                       P.n_delays), n1, P.q);
+          kp[1] |= kd << (8 * s);
+          // level n1 - kd - j <= n - 1 unless kd == 1 and j == 0 (level n, added in step n)
+          sm.at[1][wv][s][lane] = kd > 0 ? at_sum_from(P, rb0 + s * depth, kd, kd == 1 ? 1 : 0, slot_n, depth) : 0.0;
+        }
+      }
+    }
+  }
+
+  double y[R][NP], ks[R][NP], k[NP];
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int j = 0; j < NP; ++j) y[r][j] = u0[r][j];
+  const double a = P.speed;
+  const double dt = P.dt;
+
+  // upwind, a > 0: the interior right-face flux a u_p is part of Kdu; only a
+  // delayed PE face on the right adds -Kr (F_right - a u_p)
+  const bool wave_pe_right = PHYS == PHYS_ADV_UPWIND_POS && __ballot(pe_right) != 0;
+
+  int slot_m = slot_n;
+#pragma unroll
+  for (int kk = 0; kk < K; ++kk) {
+    if (kk > 0) {
+      slot_m = slot_m + 1 == depth ? 0 : slot_m + 1;
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int j = 0; j < NP; ++j) u0[r][j] = y[r][j];
+    }
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      double F[R];
+      const double um = lane_from_left(y[R - 1][NP - 1]);
+      F[0] = Physics<PHYS>::fhat(um, y[0][0], a);
+#pragma unroll
+      for (int r = 1; r < R; ++r) F[r] = Physics<PHYS>::fhat(y[r - 1][NP - 1], y[r][0], a);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        if (pe[r]) {
+          if (owned[r]) A.ring[P.ring_off + ((int64_t)b * S + s) * depth + slot_m] = F[r];
+          if constexpr (K == 2) {  // level n completes step n+1's sum when its delay is 1
+            if (kk == 0 && ((kp[1] >> (8 * s)) & 0xff) == 1) sm.at[1][wv][s][lane] += P.atc[1][0] * F[r];
+          }
+          if ((kp[kk] >> (8 * s)) & 0xff) F[r] = sm.at[kk][wv][s][lane];
+        }
+      }
+      if constexpr (PHYS == PHYS_ADV_UPWIND_POS) {
+        double f_last = 0.0;
+        if (wave_pe_right) f_last = lane_from_right(F[0]);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+#pragma unroll
+          for (int i = 0; i < NP; ++i) {
+            double v = P.Kl[i] * F[r];
+#pragma unroll
+            for (int j = 0; j < NP; ++j) v += P.Kdu[i * kMaxNp + j] * y[r][j];
+            k[i] = v;
+          }
+          const bool right_pe = r + 1 < R ? pe[r + 1] : pe_right;
+          if (right_pe) {
+            const double fr = r + 1 < R ? F[r + 1] : f_last;
+            const double corr = fr - a * y[r][NP - 1];  // exactly 0 unless the face is delayed
+#pragma unroll
+            for (int i = 0; i < NP; ++i) k[i] -= P.Kr[i] * corr;
+          }
+          rk_update<NP, RK>(s, dt, u0[r], y[r], ks[r], k);
+        }
+      } else {
+        const double f_last = lane_from_right(F[0]);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          folded_rhs<NP, PHYS>(P, y[r], F[r], r + 1 < R ? F[r + 1] : f_last, k);
+          rk_update<NP, RK>(s, dt, u0[r], y[r], ks[r], k);
+        }
+      }
+    }
+  }
+
+  double* __restrict__ uo = uout + P.u_off;
+  bool all_owned = true;
+#pragma unroll
+  for (int r = 0; r < R; ++r) all_owned = all_owned && owned[r];
+  if (grouped && all_owned) {
+    double2* __restrict__ uo2 = reinterpret_cast<double2*>(__builtin_assume_aligned(uo, 16));
+#pragma unroll
+    for (int j = 0; j < NP; ++j)
+#pragma unroll
+      for (int r = 0; r < R; r += 2) {
+        double2 v;
+        v.x = y[r][j];
+        v.y = y[r + 1 < R ? r + 1 : r][j];
+        uo2[(j * ld + e[0] + r) >> 1] = v;
+      }
+  } else {
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (owned[r])
+#pragma unroll
+        for (int j = 0; j < NP; ++j) uo[j * ld + e[r]] = y[r][j];
+  }
+
+  // owners of PE faces: records of step n+K, one lane per (face, stage).
+  // For each owned PE face of this wave (uniform loop over the owner mask),
+  // lanes 0..S-1 draw the stage's delay and sum the AT weights over the
+  // past levels (all written by the owner itself or by earlier launches).
+  bool own = false;
+#pragma unroll
+  for (int r = 0; r < R; ++r) own = own || (pe[r] && owned[r]);
+  uint64_t owners = __ballot(own);
+  while (owners) {
+    const int src = __builtin_ctzll(owners);
+    owners &= owners - 1;
+    const uint32_t bo = (uint32_t)__builtin_amdgcn_readlane((int)b, src);
+    if (lane < S) {
+      const int s = lane;
+      const int64_t nk = n + K;
+      const uint64_t pre = delay_prefix(P.seed, nk, P.per_stage ? s : 0);
+      const int kd = clamp_delay(delay_from_prefix(pre, bo, P.thr, P.n_delays), nk, P.q);
+      const double* __restrict__ rb = A.ring + P.ring_off + ((int64_t)bo * S + s) * depth;
+      const double acc = kd > 0 ? at_sum_from(P, rb, kd, 0, slot_m, depth) : 0.0;  // slot_m: level nk - 1
+      const int64_t rs = rec_slot(nk);
+      A.atsum[P.at_off + (rs * P.n_pe + bo) * S + s] = acc;
+      reinterpret_cast<uint8_t*>(A.atk + P.atk_off + rs * P.n_pe + bo)[s] = (uint8_t)kd;
+    }
+  }
+}
+
+template <int NP, int RK, int PHYS, int R, int K>
+__global__ __launch_bounds__(kBlock) void k_fused_step(const DevProblem* __restrict__ probs,
+                                                       const WorkItem* __restrict__ work,
+                                                       const int64_t* __restrict__ ctr, double* __restrict__ ring,
+                                                       double* __restrict__ atsum, int32_t* __restrict__ atk,
+                                                       int32_t w_begin, int32_t w_end, const double* __restrict__ uin,
+                                                       double* __restrict__ uout, int32_t step_offset) {
+  __shared__ WaveSmemK<K> sm;
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+  const int lane = (int)(threadIdx.x % kWave);
+  const int w = w_begin + xcd_block((int)blockIdx.x, (int)gridDim.x) * kWavesPerBlock + wv;
+  if (w >= w_end) return;  // whole wave
+  const int64_t n = ctr[0] + step_offset;
+  const WorkItem wi = work[w];
+  const FusedPtrs A{ring, atsum, atk};
+  wave_tile<NP, RK, PHYS, R, K>(probs[wi.prob], wi, A, n, uin, uout, sm, wv, lane);
+}
+
+template <int NP, int RK, int PHYS, int R>
+static void fused_go_r(const StepArgs& a, int gi, const double* uin, double* uout, int32_t off, hipStream_t st) {
+  const dim3 g(a.grid[gi]), b(kBlock);
+  if (a.steps == 2)
+    hipLaunchKernelGGL((k_fused_step<NP, RK, PHYS, R, 2>), g, b, 0, st, a.probs, a.work, a.ctr, a.ring, a.atsum, a.atk,
+                       a.group[gi], a.group[gi + 1], uin, uout, off);
+  else
+    hipLaunchKernelGGL((k_fused_step<NP, RK, PHYS, R, 1>), g, b, 0, st, a.probs, a.work, a.ctr, a.ring, a.atsum, a.atk,
+                       a.group[gi], a.group[gi + 1], uin, uout, off);
+}
+
+template <int NP, int RK, int PHYS>
+static void fused_go(const StepArgs& a, int gi, const double* uin, double* uout, int32_t off, hipStream_t st) {
+  switch (a.lane_elems) {
+    case 1: fused_go_r<NP, RK, PHYS, 1>(a, gi, uin, uout, off, st); break;
+    case 4: fused_go_r<NP, RK, PHYS, 4>(a, gi, uin, uout, off, st); break;
+    default: fused_go_r<NP, RK, PHYS, 2>(a, gi, uin, uout, off, st); break;
+  }
+}
+
+template <int RK, int PHYS>
+static void fused_np(const StepArgs& a, const double* uin, double* uout, int32_t off, hipStream_t st) {
+  // degree ranges np = 5, 4, 3, 2
+  if (a.group[1] > a.group[0]) fused_go<5, RK, PHYS>(a, 0, uin, uout, off, st);
+  if (a.group[2] > a.group[1]) fused_go<4, RK, PHYS>(a, 1, uin, uout, off, st);
+  if (a.group[3] > a.group[2]) fused_go<3, RK, PHYS>(a, 2, uin, uout, off, st);
+  if (a.group[4] > a.group[3]) fused_go<2, RK, PHYS>(a, 3, uin, uout, off, st);
+}
+
+template <int RK>
+static void fused_phys(int phys, const StepArgs& a, const double* uin, double* uout, int32_t off, hipStream_t st) {
+  switch (phys) {
+    case PHYS_ADV_UPWIND: fused_np<RK, PHYS_ADV_UPWIND>(a, uin, uout, off, st); break;
+    case PHYS_ADV_UPWIND_POS: fused_np<RK, PHYS_ADV_UPWIND_POS>(a, uin, uout, off, st); break;
+    case PHYS_ADV_CENTRAL: fused_np<RK, PHYS_ADV_CENTRAL>(a, uin, uout, off, st); break;
+    default: fused_np<RK, PHYS_BURGERS_LLF>(a, uin, uout, off, st); break;
+  }
+}
+
+template <int RK>
+hipError_t launch_fused_rk(int phys, const StepArgs& a, const double* uin, double* uout, int32_t step_offset,
+                           hipStream_t stream) {
+  fused_phys<RK>(phys, a, uin, uout, step_offset, stream);
+  return hipGetLastError();
+}
+
+template hipError_t launch_fused_rk<ADG_RK>(int, const StepArgs&, const double*, double*, int32_t, hipStream_t);
+
+}  // namespace adg

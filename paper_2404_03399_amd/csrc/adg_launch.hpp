@@ -16,6 +16,7 @@ struct StepArgs {
   int32_t group[5];          // fused kernel: work-item ranges per degree (below)
   int32_t grid[4];           // fused kernel: workgroups per degree range
   int32_t lane_elems;        // fused kernel: elements per lane (1, 2 or 4)
+  int32_t steps;             // fused kernel: time steps per launch (1 or 2)
 };
 
 // Work items of the fused kernel are sorted by descending np; items with
@@ -23,20 +24,24 @@ struct StepArgs {
 // [group[2], group[3]), [group[3], group[4]).
 
 // Fused step kernel geometry: one wave64 per work item, R in {1, 2, 4}
-// consecutive elements per lane, halo of ceil(S / R) lanes per side; owned
-// elements per work item:
+// consecutive elements per lane, K in {1, 2} time steps per launch, halo of
+// ceil(K S / R) lanes per side; owned elements per work item:
 constexpr int kWave = 64;
 constexpr int kWavesPerBlock = kBlock / kWave;
-__host__ __device__ constexpr int halo_lanes(int rk, int R) { return (rk_stages(rk) + R - 1) / R; }
-__host__ __device__ constexpr int fused_tile(int rk, int R) { return R * (kWave - 2 * halo_lanes(rk, R)); }
+__host__ __device__ constexpr int fused_halo(int rk, int R, int K) { return (K * rk_stages(rk) + R - 1) / R; }
+__host__ __device__ constexpr int fused_tile(int rk, int R, int K) { return R * (kWave - 2 * fused_halo(rk, R, K)); }
 
 // Workgroups of the fused kernel for n_work items (kWavesPerBlock per group).
 inline int fused_grid(int n_work) { return n_work < 1 ? 1 : (n_work + kWavesPerBlock - 1) / kWavesPerBlock; }
 
-// One full RK step, all stages on chip: state uin -> uout (distinct buffers).
-// The step index is ctr[0] + step_offset.
+// a.steps full RK steps (1 or 2), all stages on chip: state uin -> uout
+// (distinct buffers).  The first step's index is ctr[0] + step_offset.
 hipError_t launch_fused_step(int rk, int phys, const StepArgs& a, const double* uin, double* uout,
                              int32_t step_offset, hipStream_t stream);
+// Its per-integrator part (one translation unit per RK scheme).
+template <int RK>
+hipError_t launch_fused_rk(int phys, const StepArgs& a, const double* uin, double* uout, int32_t step_offset,
+                           hipStream_t stream);
 
 // One RK stage with the RK registers in HBM.  Stage 0 reads its input from U;
 // the last stage writes U in place.  yin/yout alternate between two buffers.

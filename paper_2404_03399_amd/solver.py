@@ -63,7 +63,7 @@ class Solver:
     """One context over one or more problems (batched when more than one)."""
 
     def __init__(self, workloads, kernel: str = "fused", n_steps_record: int = 0, ckpt_every: int = 0,
-                 device: str = "cuda", stream=None, lane_elems=0):
+                 device: str = "cuda", stream=None, lane_elems=0, fused_steps: int = 0):
         if not isinstance(workloads, (list, tuple)):
             workloads = [workloads]
         self.workloads = list(workloads)
@@ -73,9 +73,12 @@ class Solver:
         self.opt.kernel = adg.KERNEL[kernel]
         self.opt.ckpt_every = ckpt_every
         if lane_elems == "auto":
+            # elements per lane and (unless given) steps per launch, tuned together
             from . import autotune
-            lane_elems = autotune.lane_elems(self.workloads) if kernel == "fused" else 0
+            lane_elems, k = autotune.tune(self.workloads) if kernel == "fused" else (0, 0)
+            fused_steps = fused_steps or k
         self.opt.lane_elems = int(lane_elems)
+        self.opt.fused_steps = int(fused_steps)
         self.device = torch.device(device)
         self.ws_bytes = adg.adg_workspace_size(self.probs, self.opt, n_steps_record)
         self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)

@@ -31,9 +31,9 @@ def torch_cuda():
     return torch
 
 
-def gpu_run(torch, w, u0, n_steps, kernel="fused", graph=True, lane_elems=0):
+def gpu_run(torch, w, u0, n_steps, kernel="fused", graph=True, lane_elems=0, fused_steps=0):
     from paper_2404_03399_amd.solver import Solver
-    s = Solver(w, kernel=kernel, lane_elems=lane_elems)
+    s = Solver(w, kernel=kernel, lane_elems=lane_elems, fused_steps=fused_steps)
     u = s.pack(u0)
     s.run(u, n_steps, graph=graph)
     torch.cuda.synchronize()
@@ -152,6 +152,52 @@ def test_lane_elems_variants(torch_cuda, lane_elems, ne, pe, p, rk, phys):
                    probs=W.DELAYS_C2, seed=21, per_stage=(ne % 2 == 0), ic=ic,
                    dt=sig * W.TWO_PI / ne / (1.5 if eq == "burgers" else 1.0))
     _check(torch_cuda, w, 21, "fused", graph=True, lane_elems=lane_elems)
+
+
+TWO_STEP_CASES = [
+    # (ne, pe, p, rk, phys, scheme, per_stage, at_levels, lane_elems)
+    (1000, 40, 3, "rk4", "upwind", "adg_at", True, 0, 1),
+    (1000, 40, 3, "rk4", "upwind", "adg_at", True, 0, 2),
+    (1000, 40, 3, "rk4", "upwind", "adg_at", True, 0, 4),
+    (777, 7, 2, "ssprk3", "central", "adg_at", False, 0, 1),
+    (777, 7, 2, "ssprk3", "central", "adg", True, 0, 2),
+    (640, 5, 1, "heun", "llf", "adg_at", True, 0, 4),
+    (513, 9, 4, "rk4", "llf", "adg_at", False, 2, 1),
+    (96, 3, 2, "rk4", "upwind", "adg_at", True, 0, 2),
+    (40, 4, 3, "ssprk3", "upwind", "adg_at", True, 0, 1),
+    (7, 1, 2, "rk4", "upwind", "adg_at", True, 0, 1),
+    (300, 300, 2, "rk4", "central", "adg_at", True, 0, 4),
+    (1000, 40, 2, "rk4", "upwind", "dg", True, 0, 2),
+]
+
+
+@pytest.mark.parametrize("ne,pe,p,rk,phys,scheme,per_stage,q,lane_elems", TWO_STEP_CASES)
+def test_two_steps_per_launch_bitwise(torch_cuda, ne, pe, p, rk, phys, scheme, per_stage, q, lane_elems):
+    """Two time steps per fused launch (halo 2S, the second step's AT sums
+    formed in-kernel from the ring plus the lane's own level-n flux) give the
+    one-step-per-launch results: bitwise with one element per lane; with 2 or
+    4 the compiler contracts some multiply-adds differently in the two
+    kernels, so a few values differ in the last bit.  Both match the oracle."""
+    eq = "burgers" if phys == "llf" else "advection"
+    ic = W.MultiSine((1, 2), (1.0, 0.5), (0.3, 0.9), offset=0.5 if eq == "burgers" else 0.0)
+    sig = {1: 0.05, 2: 0.01, 3: 0.005, 4: 0.001}[p]
+    w = W.Workload(name=f"k2_{ne}_{pe}", equation=eq, flux=phys, rk=rk, scheme=scheme, degree=p, n_elem=ne,
+                   pe_size=pe, probs=W.DELAYS_C2, seed=5 + ne, per_stage=per_stage, at_levels=q, ic=ic,
+                   dt=sig * W.TWO_PI / ne / (1.5 if eq == "burgers" else 1.0))
+    u0 = stepper.initial_state(w)
+    n = 19
+    _say(f"two-step launches: N={ne} pe={pe} p={p} {rk} {phys} {scheme} per_stage={per_stage} q={q} "
+         f"R={lane_elems} steps={n}")
+    one = gpu_run(torch_cuda, w, u0, n, "fused", graph=False, lane_elems=lane_elems, fused_steps=1)
+    two = gpu_run(torch_cuda, w, u0, n, "fused", graph=False, lane_elems=lane_elems, fused_steps=2)
+    two_g = gpu_run(torch_cuda, w, u0, n + 13, "fused", graph=True, lane_elems=lane_elems, fused_steps=2)
+    one_g = gpu_run(torch_cuda, w, u0, n + 13, "fused", graph=True, lane_elems=lane_elems, fused_steps=1)
+    if lane_elems == 1:
+        assert np.array_equal(one, two)
+        assert np.array_equal(one_g, two_g)
+    else:
+        assert stats.rel_l2(two, one) <= 1e-14 and stats.rel_l2(two_g, one_g) <= 1e-14
+    assert stats.rel_l2(two, oracle_run(w, u0, n)) <= TOL
 
 
 def test_lane_elems_rejected_above_pe_size(torch_cuda):
