@@ -17,7 +17,11 @@ LIBDIR = os.path.join(PKG, "_lib")
 LIB = os.path.join(LIBDIR, "libadg.so")
 # (source, extra defines): the fused step is compiled once per integrator so
 # that its many instantiations build in parallel
-UNITS = [("adg_fused.hip", ["-DADG_RK=0"]), ("adg_fused.hip", ["-DADG_RK=1"]), ("adg_fused.hip", ["-DADG_RK=2"]),
+# kernel arguments preloaded into SGPRs (gfx950): the fused step reaches its
+# first HBM load one scalar load earlier
+PRELOAD = ["-mllvm", "-amdgpu-kernarg-preload-count=16"]
+UNITS = [("adg_fused.hip", ["-DADG_RK=0"] + PRELOAD), ("adg_fused.hip", ["-DADG_RK=1"] + PRELOAD),
+         ("adg_fused.hip", ["-DADG_RK=2"] + PRELOAD),
          ("adg_adjoint.hip", []), ("adg_kernels.hip", []), ("adg_api.hip", [])]
 ARCH = "gfx950"
 
@@ -57,7 +61,7 @@ def build(verbose: bool = False, jobs: int = 0) -> str:
     cc = hipcc()
     objs, cmds = [], []
     for src, defs in UNITS:
-        tag = "".join(d.split("=")[-1] for d in defs)
+        tag = "".join(d.split("=")[-1] for d in defs if d.startswith("-D"))
         obj = os.path.join(objdir, os.path.splitext(src)[0] + (f"_{tag}" if tag else "") + ".o")
         objs.append(obj)
         cmds.append([cc] + flags() + defs + ["-c", os.path.join(CSRC, src), "-o", obj])

@@ -359,6 +359,7 @@ struct adg_ctx {
 
   int32_t group[2][5] = {{0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}};  // fused work lists, 1 and 2 steps per launch
   int32_t grid[2][4] = {{1, 1, 1, 1}, {1, 1, 1, 1}};
+  int32_t single[2][4] = {{-1, -1, -1, -1}, {-1, -1, -1, -1}};
   int32_t lane_elems = 2;
   int32_t fused_steps = 2;
   // fused adjoint work list (recording contexts of the fused kernel)
@@ -377,6 +378,7 @@ struct adg_ctx {
     a.atk = (int32_t*)(ws + L.atk);
     for (int i = 0; i < 5; ++i) a.group[i] = group[K - 1][i];
     for (int i = 0; i < 4; ++i) a.grid[i] = grid[K - 1][i];
+    for (int i = 0; i < 4; ++i) a.single[i] = single[K - 1][i];
     a.lane_elems = lane_elems;
     a.steps = K;
     return a;
@@ -651,8 +653,13 @@ int adg_init(adg_ctx** out, const adg_problem* probs, int32_t n_probs, const adg
       }
     }
     c->group[K - 1][4] = (int32_t)wf.size();
-    for (int gi = 0; gi < 4; ++gi)
-      c->grid[K - 1][gi] = fused_grid(c->group[K - 1][gi + 1] - c->group[K - 1][gi]);
+    for (int gi = 0; gi < 4; ++gi) {
+      const int32_t b = c->group[K - 1][gi], e = c->group[K - 1][gi + 1];
+      c->grid[K - 1][gi] = fused_grid(e - b);
+      bool one = e > b;
+      for (int32_t w = b; w < e && one; ++w) one = wf[w].prob == wf[b].prob && wf[w].tile == w - b;
+      c->single[K - 1][gi] = one ? wf[b].prob : -1;
+    }
   }
   for (int32_t i = 0; i < n_probs; ++i) {  // stage/stats list in problem order (contiguous per problem)
     first[i] = (int32_t)ws_.size();

@@ -47,8 +47,10 @@ template <>
 struct Physics<PHYS_BURGERS_LLF> {
   __device__ static double f(double u, double) { return 0.5 * u * u; }
   __device__ static double fhat(double um, double up, double) {
+#pragma clang fp contract(off)
     const double lam = fmax(fabs(um), fabs(up));
-    return 0.5 * (0.5 * um * um + 0.5 * up * up) - 0.5 * lam * (up - um);
+    const double avg = 0.5 * (fma(0.5 * um, um, (0.5 * up) * up));
+    return fma(-0.5 * lam, up - um, avg);
   }
 };
 
@@ -70,7 +72,7 @@ __device__ __forceinline__ int pe_delay(const DevProblem& P, int64_t n, int s, u
 __device__ __forceinline__ double at_past_sum(const DevProblem& P, const double* __restrict__ r, int k,
                                               int slot_n) {
   double acc = 0.0;  // oldest level first, as in every other path
-  for (int j = P.q - 1; j >= 0; --j) acc += P.atc[k][j] * r[ring_slot(slot_n, k + j, P.depth)];
+  for (int j = P.q - 1; j >= 0; --j) acc = fma(P.atc[k][j], r[ring_slot(slot_n, k + j, P.depth)], acc);
   return acc;
 }
 
@@ -104,35 +106,39 @@ __device__ __forceinline__ void load_operators(const DevProblem& P, double (&Dm)
 }
 
 // RK update after the stage-s operator value k (oracle's algebraic forms).
+// Every multiply-add is an explicit FMA and nothing else is contracted, so
+// the rounding does not depend on how the compiler schedules the caller
+// (kernels of different launch shapes then agree bitwise).
 // u0: u^n; y: stage input (in) -> next stage input or u^{n+1} (out);
 // ks: RK4 running sum k1 + 2k2 + 2k3, Heun k1 = dt L(u^n).
 template <int NP, int RK>
 __device__ __forceinline__ void rk_update(int s, double dt, const double (&u0)[NP], double (&y)[NP],
                                           double (&ks)[NP], const double (&k)[NP]) {
+#pragma clang fp contract(off)
   if constexpr (RK == RK_RK4) {
     if (s == 0) {
 #pragma unroll
-      for (int j = 0; j < NP; ++j) { ks[j] = k[j]; y[j] = u0[j] + (0.5 * dt) * k[j]; }
+      for (int j = 0; j < NP; ++j) { ks[j] = k[j]; y[j] = fma(0.5 * dt, k[j], u0[j]); }
     } else if (s == 1) {
 #pragma unroll
-      for (int j = 0; j < NP; ++j) { ks[j] = ks[j] + 2.0 * k[j]; y[j] = u0[j] + (0.5 * dt) * k[j]; }
+      for (int j = 0; j < NP; ++j) { ks[j] = fma(2.0, k[j], ks[j]); y[j] = fma(0.5 * dt, k[j], u0[j]); }
     } else if (s == 2) {
 #pragma unroll
-      for (int j = 0; j < NP; ++j) { ks[j] = ks[j] + 2.0 * k[j]; y[j] = u0[j] + dt * k[j]; }
+      for (int j = 0; j < NP; ++j) { ks[j] = fma(2.0, k[j], ks[j]); y[j] = fma(dt, k[j], u0[j]); }
     } else {
 #pragma unroll
-      for (int j = 0; j < NP; ++j) y[j] = u0[j] + (dt / 6.0) * (ks[j] + k[j]);
+      for (int j = 0; j < NP; ++j) y[j] = fma(dt / 6.0, ks[j] + k[j], u0[j]);
     }
   } else if constexpr (RK == RK_SSP3) {
     if (s == 0) {
 #pragma unroll
-      for (int j = 0; j < NP; ++j) y[j] = u0[j] + dt * k[j];
+      for (int j = 0; j < NP; ++j) y[j] = fma(dt, k[j], u0[j]);
     } else if (s == 1) {
 #pragma unroll
-      for (int j = 0; j < NP; ++j) y[j] = 0.75 * u0[j] + 0.25 * (y[j] + dt * k[j]);
+      for (int j = 0; j < NP; ++j) y[j] = fma(0.25, fma(dt, k[j], y[j]), 0.75 * u0[j]);
     } else {
 #pragma unroll
-      for (int j = 0; j < NP; ++j) y[j] = u0[j] / 3.0 + (2.0 / 3.0) * (y[j] + dt * k[j]);
+      for (int j = 0; j < NP; ++j) y[j] = fma(2.0 / 3.0, fma(dt, k[j], y[j]), u0[j] / 3.0);
     }
   } else {  // Heun
     if (s == 0) {
@@ -140,7 +146,7 @@ __device__ __forceinline__ void rk_update(int s, double dt, const double (&u0)[N
       for (int j = 0; j < NP; ++j) { ks[j] = dt * k[j]; y[j] = u0[j] + ks[j]; }
     } else {
 #pragma unroll
-      for (int j = 0; j < NP; ++j) y[j] = u0[j] + 0.5 * (ks[j] + dt * k[j]);
+      for (int j = 0; j < NP; ++j) y[j] = fma(0.5, fma(dt, k[j], ks[j]), u0[j]);
     }
   }
 }
@@ -199,14 +205,15 @@ struct WaveSmemK {
 template <int NP, int PHYS>
 __device__ __forceinline__ void folded_rhs(const DevProblem& P, const double (&y)[NP], double fl, double fr,
                                            double (&k)[NP]) {
+#pragma clang fp contract(off)
   double g[NP];
 #pragma unroll
   for (int j = 0; j < NP; ++j) g[j] = PHYS == PHYS_BURGERS_LLF ? y[j] * y[j] : y[j];
 #pragma unroll
   for (int i = 0; i < NP; ++i) {
-    double v = P.Kl[i] * fl - P.Kr[i] * fr;
+    double v = fma(-P.Kr[i], fr, P.Kl[i] * fl);
 #pragma unroll
-    for (int j = 0; j < NP; ++j) v += P.Kd[i * kMaxNp + j] * g[j];
+    for (int j = 0; j < NP; ++j) v = fma(P.Kd[i * kMaxNp + j], g[j], v);
     k[i] = v;
   }
 }
@@ -221,13 +228,14 @@ struct FusedPtrs {
 __device__ __forceinline__ int64_t rec_slot(int64_t m) { return (int64_t)((uint32_t)m % (uint32_t)kRecSlots); }
 
 // Partial AT sum of step m over the levels m - kd - j, j = q-1 down to jmin,
-// oldest first (the order every path uses, so that a sum finished later with
-// its newest level is bitwise the one-pass sum).  slot_prev = slot of level
+// oldest first, one explicit FMA per level (the order and rounding every path
+// uses, so that a sum finished later with its newest level is bitwise the
+// one-pass sum whatever the compiler contracts elsewhere).  slot_prev = slot of level
 // m - 1, all levels read here are at most m - 1.
 __device__ __forceinline__ double at_sum_from(const DevProblem& P, const double* __restrict__ rb, int kd, int jmin,
                                               int slot_prev, int depth) {
   double acc = 0.0;
-  for (int j = P.q - 1; j >= jmin; --j) acc += P.atc[kd][j] * rb[ring_slot(slot_prev, kd + j - 1, depth)];
+  for (int j = P.q - 1; j >= jmin; --j) acc = fma(P.atc[kd][j], rb[ring_slot(slot_prev, kd + j - 1, depth)], acc);
   return acc;
 }
 

@@ -33,6 +33,7 @@ template <int NP, int RK, int PHYS, int R, int K>
 __device__ __forceinline__ void wave_tile(const DevProblem& P, const WorkItem wi, const FusedPtrs& A, int64_t n,
                                           const double* __restrict__ uin, double* __restrict__ uout,
                                           WaveSmemK<K>& sm, int wv, int lane) {
+#pragma clang fp contract(off)  // explicit FMAs only: rounding independent of the launch shape
   constexpr int S = rk_stages(RK);
   constexpr int HL = fused_halo(RK, R, K);
   constexpr int T = fused_tile(RK, R, K);
@@ -132,6 +133,9 @@ __device__ __forceinline__ void wave_tile(const DevProblem& P, const WorkItem wi
   // upwind, a > 0: the interior right-face flux a u_p is part of Kdu; only a
   // delayed PE face on the right adds -Kr (F_right - a u_p)
   const bool wave_pe_right = PHYS == PHYS_ADV_UPWIND_POS && __ballot(pe_right) != 0;
+  bool own_pe = false;  // this lane owns the element right of its PE face
+#pragma unroll
+  for (int r = 0; r < R; ++r) own_pe = own_pe || (pe[r] && owned[r]);
 
   int slot_m = slot_n;
 #pragma unroll
@@ -155,7 +159,8 @@ __device__ __forceinline__ void wave_tile(const DevProblem& P, const WorkItem wi
         if (pe[r]) {
           if (owned[r]) A.ring[P.ring_off + ((int64_t)b * S + s) * depth + slot_m] = F[r];
           if constexpr (K == 2) {  // level n completes step n+1's sum when its delay is 1
-            if (kk == 0 && ((kp[1] >> (8 * s)) & 0xff) == 1) sm.at[1][wv][s][lane] += P.atc[1][0] * F[r];
+            if (kk == 0 && ((kp[1] >> (8 * s)) & 0xff) == 1)
+              sm.at[1][wv][s][lane] = fma(P.atc[1][0], F[r], sm.at[1][wv][s][lane]);
           }
           if ((kp[kk] >> (8 * s)) & 0xff) F[r] = sm.at[kk][wv][s][lane];
         }
@@ -169,15 +174,16 @@ __device__ __forceinline__ void wave_tile(const DevProblem& P, const WorkItem wi
           for (int i = 0; i < NP; ++i) {
             double v = P.Kl[i] * F[r];
 #pragma unroll
-            for (int j = 0; j < NP; ++j) v += P.Kdu[i * kMaxNp + j] * y[r][j];
+            for (int j = 0; j < NP; ++j) v = fma(P.Kdu[i * kMaxNp + j], y[r][j], v);
             k[i] = v;
           }
-          const bool right_pe = r + 1 < R ? pe[r + 1] : pe_right;
-          if (right_pe) {
+          if (wave_pe_right) {
+            const bool right_pe = r + 1 < R ? pe[r + 1] : pe_right;
             const double fr = r + 1 < R ? F[r + 1] : f_last;
-            const double corr = fr - a * y[r][NP - 1];  // exactly 0 unless the face is delayed
+            // exactly 0 unless the right face is a delayed PE face
+            const double corr = right_pe ? fma(-a, y[r][NP - 1], fr) : 0.0;
 #pragma unroll
-            for (int i = 0; i < NP; ++i) k[i] -= P.Kr[i] * corr;
+            for (int i = 0; i < NP; ++i) k[i] = fma(-P.Kr[i], corr, k[i]);
           }
           rk_update<NP, RK>(s, dt, u0[r], y[r], ks[r], k);
         }
@@ -219,10 +225,7 @@ __device__ __forceinline__ void wave_tile(const DevProblem& P, const WorkItem wi
   // For each owned PE face of this wave (uniform loop over the owner mask),
   // lanes 0..S-1 draw the stage's delay and sum the AT weights over the
   // past levels (all written by the owner itself or by earlier launches).
-  bool own = false;
-#pragma unroll
-  for (int r = 0; r < R; ++r) own = own || (pe[r] && owned[r]);
-  uint64_t owners = __ballot(own);
+  uint64_t owners = __ballot(own_pe);
   while (owners) {
     const int src = __builtin_ctzll(owners);
     owners &= owners - 1;
@@ -247,14 +250,16 @@ __global__ __launch_bounds__(kBlock) void k_fused_step(const DevProblem* __restr
                                                        const int64_t* __restrict__ ctr, double* __restrict__ ring,
                                                        double* __restrict__ atsum, int32_t* __restrict__ atk,
                                                        int32_t w_begin, int32_t w_end, const double* __restrict__ uin,
-                                                       double* __restrict__ uout, int32_t step_offset) {
+                                                       double* __restrict__ uout, int32_t step_offset,
+                                                       int32_t single_prob) {
   __shared__ WaveSmemK<K> sm;
   const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
   const int lane = (int)(threadIdx.x % kWave);
   const int w = w_begin + xcd_block((int)blockIdx.x, (int)gridDim.x) * kWavesPerBlock + wv;
   if (w >= w_end) return;  // whole wave
   const int64_t n = ctr[0] + step_offset;
-  const WorkItem wi = work[w];
+  // a range holding one problem lists its tiles in order: no work-list load
+  const WorkItem wi = single_prob >= 0 ? WorkItem{single_prob, w - w_begin} : work[w];
   const FusedPtrs A{ring, atsum, atk};
   wave_tile<NP, RK, PHYS, R, K>(probs[wi.prob], wi, A, n, uin, uout, sm, wv, lane);
 }
@@ -264,10 +269,10 @@ static void fused_go_r(const StepArgs& a, int gi, const double* uin, double* uou
   const dim3 g(a.grid[gi]), b(kBlock);
   if (a.steps == 2)
     hipLaunchKernelGGL((k_fused_step<NP, RK, PHYS, R, 2>), g, b, 0, st, a.probs, a.work, a.ctr, a.ring, a.atsum, a.atk,
-                       a.group[gi], a.group[gi + 1], uin, uout, off);
+                       a.group[gi], a.group[gi + 1], uin, uout, off, a.single[gi]);
   else
     hipLaunchKernelGGL((k_fused_step<NP, RK, PHYS, R, 1>), g, b, 0, st, a.probs, a.work, a.ctr, a.ring, a.atsum, a.atk,
-                       a.group[gi], a.group[gi + 1], uin, uout, off);
+                       a.group[gi], a.group[gi + 1], uin, uout, off, a.single[gi]);
 }
 
 template <int NP, int RK, int PHYS>

@@ -15,6 +15,7 @@ struct StepArgs {
   int32_t* atk;              // fused kernel: clamped delays, [2][P][S] per problem
   int32_t group[5];          // fused kernel: work-item ranges per degree (below)
   int32_t grid[4];           // fused kernel: workgroups per degree range
+  int32_t single[4];         // fused kernel: the only problem of a degree range, or -1
   int32_t lane_elems;        // fused kernel: elements per lane (1, 2 or 4)
   int32_t steps;             // fused kernel: time steps per launch (1 or 2)
 };
