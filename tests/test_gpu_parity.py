@@ -262,6 +262,49 @@ def test_c2_full_size_window_other_schemes(torch_cuda, scheme):
     _check(torch_cuda, w, 4, "fused", graph=False)
 
 
+@pytest.mark.parametrize("lane_elems,fused_steps", [(1, 2), (2, 2), (1, 1)])
+def test_large_mesh_fourier_mode_closed_form(torch_cuda, lane_elems, fused_steps):
+    """2^28 elements (8.6 GB per state): synchronous DG of one Fourier mode
+    equals the per-element amplification closed form u_e^n = Im(G(theta)^n
+    w0 e^{i theta e}) (Sec. 4.2), checked on every element; ADG-AT on the same
+    mesh conserves the integral (one flux per face, Sec. 4.1)."""
+    torch = torch_cuda
+    from oracle import fourier
+    from paper_2404_03399_amd.solver import Solver
+    ne, p, m, n = 1 << 28, 3, 5, 6
+    dx = W.TWO_PI / ne
+    sigma = 0.05
+    w = W.Workload(name="big_dg", scheme="dg", rk="rk4", degree=p, n_elem=ne, pe_size=256,
+                   probs=W.DELAYS_C2, dt=sigma * dx, ic=W.MultiSine((m,), (1.0,), (0.0,)))
+    _say(f"2^28 elements, DG mode m={m}, {n} steps, R={lane_elems} K={fused_steps}")
+    s = Solver(w, lane_elems=lane_elems, fused_steps=fused_steps)
+    u = s.initial_state()
+    s.run(u, n, graph=False)
+    xi = s.nodes(0)[:, 0].cpu().numpy()  # node positions of element 0
+    theta = m * dx
+    g = np.linalg.matrix_power(fourier.amplification(p, "rk4", "upwind", sigma, theta), n)
+    wn = g @ np.exp(1j * m * xi)
+    e = torch.arange(ne, dtype=torch.float64, device="cuda") * theta
+    ref = (torch.tensor(wn.real, device="cuda")[:, None] * torch.sin(e)[None, :]
+           + torch.tensor(wn.imag, device="cuda")[:, None] * torch.cos(e)[None, :])
+    got = s.view(u)
+    err = float(torch.linalg.vector_norm(got - ref) / torch.linalg.vector_norm(ref))
+    del ref, got, e
+    s.close()
+    assert err <= 1e-12, err
+    if lane_elems == 1 and fused_steps == 2:
+        wa = replace(w, name="big_at", scheme="adg_at")
+        s = Solver(wa)
+        u = s.initial_state()
+        z = torch.zeros_like(u)
+        i0 = s.error_stats(u, z)[0][2]
+        s.run(u, n, graph=False, check_finite=True)
+        i1 = s.error_stats(u, z)[0][2]
+        s.close()
+        scale = float(W.TWO_PI / m)  # integral of |sin| over one period, order of the summands
+        assert abs(i1 - i0) <= 1e-12 * scale, (i0, i1)
+
+
 def test_c3_burgers_full_size_window(torch_cuda):
     w = W.c3_burgers()
     _check(torch_cuda, w, 4, "fused", graph=False)
