@@ -181,6 +181,27 @@ def bench_adjoint(torch, W, Solver, n_steps: int, n_elem: int, stage: bool):
     return out
 
 
+def bench_experiments():
+    """Sec. 6.2 scaling experiments on the batched engine (Figs. 9 and 10),
+    summarised: orders in N_E per P, the P-dependence of the asynchrony error,
+    and the fit of <E-bar> against the AT remainder's delay moment."""
+    from paper_2404_03399_amd import experiments as X
+    t0 = time.perf_counter()
+    f9a = X.error_vs_pe("at2", n_elems=(64, 128, 256, 512, 1024))
+    f9b = X.error_vs_pe("at4", n_elems=(64, 128, 256, 512))
+    f10a = X.error_vs_delay("at2", n_elem=512, delay_counts=(1, 2, 3, 4, 5))
+    f10b = X.error_vs_delay("at4", n_elem=128, delay_counts=(1, 2, 3, 4))
+    def slim(r):
+        return {k: r[k] for k in ("n_elem", "n_pe", "delay_counts", "mean", "delay_moment", "stable", "fit")}
+    return {"wall_s": time.perf_counter() - t0, "n_real": f9a["n_real"],
+            "fig9_at2": {"order_in_n_elem": f9a["order_in_n_elem"], "order_dg": f9a["order_in_n_elem_dg"],
+                         "inset_n_elem": f9a["inset"]["n_elem"], "inset_mean": f9a["inset"]["mean"],
+                         "slope_excess_vs_pe": f9a["inset"]["slope_excess_vs_pe"]},
+            "fig9_at4": {"order_in_n_elem": f9b["order_in_n_elem"], "order_dg": f9b["order_in_n_elem_dg"],
+                         "inset_n_elem": f9b["inset"]["n_elem"], "inset_excess_over_dg": f9b["inset"]["excess_over_dg"]},
+            "fig10_at2": slim(f10a), "fig10_at4": slim(f10b)}
+
+
 def bench_ensemble(torch, W, Solver, n_steps: int, n_real: int, plain: bool):
     """Batched ensemble (12 meshes x n_real delay realizations, one context,
     one launch per degree per step) against one context per problem."""
@@ -254,6 +275,7 @@ def main():
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the one-context-per-problem ensemble run")
     ap.add_argument("--no-adjoint-stage", action="store_true", help="skip the per-stage adjoint comparison")
+    ap.add_argument("--no-experiments", action="store_true", help="skip the Sec. 6.2 scaling experiments")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -365,6 +387,8 @@ def main():
     if not args.no_ensemble:
         out["ensemble"] = bench_ensemble(torch, W, Solver, args.ensemble_steps, args.ensemble_real,
                                          not args.no_plain)
+    if not args.no_experiments:
+        out["experiments"] = bench_experiments()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
         out["cpu_baseline"]["host"] = {"cpu_count": os.cpu_count()}

@@ -1,0 +1,159 @@
+"""Statistical scaling experiments of Section 6.2 on the batched engine.
+
+The ensemble-averaged overall error <E-bar> (Sec. 4.3: spatial mean of
+|u_h - u_exact| over all nodal values, averaged over delay realizations) of
+the two AT schemes of Figs. 9-10, ADG(1)-AT2-RK2 at sigma = 0.1 and
+ADG(3)-AT4-RK4 at sigma = 0.01, for linear advection with the Section 6
+initial data:
+
+* `error_vs_pe`: <E-bar> against the mesh for P = 2..32 PEs (Fig. 9): the AT
+  schemes keep their order (slopes -2 and -4 in N_E) and, where asynchrony
+  dominates, the error grows linearly with P (the Sec. 5 scaling
+  <E_f> ~ (P / N_E) dt^a sum_m gamma_m E[k^m]).
+* `error_vs_delay`: <E-bar> against the maximum delay L with p_k = 1/L
+  (Fig. 10), fitted against the delay moment of the AT remainder,
+  E[k (k+1) ... (k+q-1)] (E[k^2] + E[k] for q = 2; E[k^4] + 6E[k^3] +
+  11E[k^2] + 6E[k] for q = 4).
+
+Every realization of one mesh runs in one batched context (one launch per
+step for all of them); the statistics come from adg_ensemble_stats.  The
+paper uses 5 realizations per point; the defaults here use 32.
+
+    python -m paper_2404_03399_amd.experiments          # both figures, JSON
+"""
+from __future__ import annotations
+
+import json
+import math
+import sys
+import time
+from fractions import Fraction
+from typing import Dict, List, Sequence
+
+from . import workloads as W
+
+PE_COUNTS = (2, 4, 8, 16, 32)
+STABLE_ERROR = 0.1  # <E> of a run still inside the stability region (|u0| <= 3)
+
+
+# ---- analysis (host arithmetic on the measured errors) -----------------------
+def delay_moment(probs: Sequence, q: int) -> Fraction:
+    """E[k (k+1) ... (k+q-1)] for delays k = 0..L-1 with probabilities probs:
+    the delay dependence of the leading AT remainder (Sec. 5), exact."""
+    acc = Fraction(0)
+    for k, p in enumerate(probs):
+        term = Fraction(1)
+        for i in range(q):
+            term *= k + i
+        acc += Fraction(p) * term
+    return acc
+
+
+def mean_delay(probs: Sequence) -> Fraction:
+    return sum((Fraction(p) * k for k, p in enumerate(probs)), Fraction(0))
+
+
+def loglog_slope(xs: Sequence[float], ys: Sequence[float]) -> float:
+    """Least-squares slope of log y against log x."""
+    lx = [math.log(x) for x in xs]
+    ly = [math.log(y) for y in ys]
+    mx, my = sum(lx) / len(lx), sum(ly) / len(ly)
+    sxx = sum((a - mx) ** 2 for a in lx)
+    sxy = sum((a - mx) * (b - my) for a, b in zip(lx, ly))
+    return sxy / sxx
+
+
+def linear_fit(xs: Sequence[float], ys: Sequence[float]) -> Dict[str, float]:
+    """y = c0 + c1 x by least squares, with R^2."""
+    n = len(xs)
+    mx, my = sum(xs) / n, sum(ys) / n
+    sxx = sum((x - mx) ** 2 for x in xs)
+    sxy = sum((x - mx) * (y - my) for x, y in zip(xs, ys))
+    c1 = sxy / sxx
+    c0 = my - c1 * mx
+    ss_res = sum((y - c0 - c1 * x) ** 2 for x, y in zip(xs, ys))
+    ss_tot = sum((y - my) ** 2 for y in ys)
+    return {"c0": c0, "c1": c1, "r2": 1.0 - ss_res / ss_tot if ss_tot > 0 else 1.0}
+
+
+# ---- runs -----------------------------------------------------------------
+def run_groups(workloads, group_of, n_groups: int, t_final: float):
+    """Advance every problem to t_final in one batched context and return,
+    per group, (mean <E>, variance of <E>, mean max-error, its variance)
+    against the exact solution u0(x - a t_final)."""
+    from .solver import Solver
+
+    n_steps = {w.n_steps for w in workloads}
+    if len(n_steps) != 1:
+        raise ValueError("problems of one context must take the same number of steps")
+    s = Solver(workloads)
+    try:
+        u = s.initial_state()
+        s.run(u, n_steps.pop(), graph=True)
+        ref = s.exact_advection_state(t_final)
+        return s.ensemble_stats(u, ref, group_of, n_groups)
+    finally:
+        s.close()
+
+
+def sync_error(scheme_key: str, n_elem: int, t_final: float) -> float:
+    """<E> of the synchronous DG scheme on the same mesh (no delays)."""
+    w = W.scaling_workload(scheme_key, n_elem, 1, ("1",), 0, t_final, scheme="dg")
+    return run_groups([w], [0], 1, t_final)[0][0]
+
+
+def error_vs_pe(scheme_key: str = "at2", n_elems=(64, 128, 256, 512, 1024), pe_counts=PE_COUNTS,
+                n_real: int = 32, probs=W.DELAYS_FIG9, t_final: float = 1.0) -> dict:
+    """Fig. 9: <E-bar> for every (N_E, P) plus the synchronous DG error."""
+    table = []
+    for ne in n_elems:
+        ws, grp = W.error_vs_pe_workloads(scheme_key, ne, pe_counts, n_real, probs, t_final)
+        stats = run_groups(ws, grp, len(pe_counts), t_final)
+        table.append({"n_elem": ne, "dg": sync_error(scheme_key, ne, t_final),
+                      "mean": [st[0] for st in stats], "std": [math.sqrt(max(st[1], 0.0)) for st in stats]})
+    out = {"scheme": scheme_key, **W.SCALING_SCHEMES[scheme_key], "probs": list(probs), "t_final": t_final,
+           "n_real": n_real, "pe_counts": list(pe_counts), "table": table}
+    if len(n_elems) > 1:
+        out["order_in_n_elem"] = [loglog_slope(n_elems, [row["mean"][g] for row in table])
+                                  for g in range(len(pe_counts))]
+        out["order_in_n_elem_dg"] = loglog_slope(n_elems, [row["dg"] for row in table])
+    last = table[-1]
+    excess = [m - last["dg"] for m in last["mean"]]
+    out["inset"] = {"n_elem": last["n_elem"], "mean": last["mean"], "excess_over_dg": excess,
+                    "slope_excess_vs_pe": loglog_slope(pe_counts, excess) if min(excess) > 0 else None,
+                    "slope_mean_vs_pe": loglog_slope(pe_counts, last["mean"])}
+    return out
+
+
+def error_vs_delay(scheme_key: str = "at2", n_elem: int = 512, n_pe: int = 16, delay_counts=(1, 2, 3, 4, 5),
+                   n_real: int = 32, t_final: float = 1.0) -> dict:
+    """Fig. 10: <E-bar> against L (uniform p_k) and its fit against the delay
+    moment of the AT remainder."""
+    q = W.SCALING_SCHEMES[scheme_key]["degree"] + 1
+    ws, grp = W.error_vs_delay_workloads(scheme_key, n_elem, n_pe, delay_counts, n_real, t_final)
+    stats = run_groups(ws, grp, len(delay_counts), t_final)
+    means = [st[0] for st in stats]
+    moments = [float(delay_moment(W.uniform_probs(L), q)) for L in delay_counts]
+    # a run that left the scheme's stability region (Sec. 4.2.2: the region
+    # shrinks as L grows) has errors of the size of the solution or NaN
+    stable = [math.isfinite(m) and m < STABLE_ERROR for m in means]
+    idx = [i for i, ok in enumerate(stable) if ok]
+    fit = linear_fit([moments[i] for i in idx], [means[i] for i in idx]) if len(idx) > 2 else None
+    return {"scheme": scheme_key, **W.SCALING_SCHEMES[scheme_key], "n_elem": n_elem, "n_pe": n_pe,
+            "t_final": t_final, "n_real": n_real, "q": q, "delay_counts": list(delay_counts),
+            "mean": means, "std": [math.sqrt(max(st[1], 0.0)) if math.isfinite(st[1]) else None for st in stats],
+            "delay_moment": moments, "stable": stable, "fit": fit}
+
+
+def main(argv=None) -> int:
+    t0 = time.perf_counter()
+    out = {"error_vs_pe": [error_vs_pe("at2", n_elems=(64, 128, 256, 512, 1024)),
+                           error_vs_pe("at4", n_elems=(64, 128, 256, 512))],
+           "error_vs_delay": [error_vs_delay("at2", n_elem=512), error_vs_delay("at4", n_elem=128)]}
+    out["wall_s"] = time.perf_counter() - t0
+    print(json.dumps(out))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main(sys.argv[1:]))

@@ -159,6 +159,59 @@ def c5_adjoint_burgers(n_elem: int = 1 << 18, n_steps: int = 1000, sigma: float 
     return replace(w, name=f"c5_burgers_{n_elem}")
 
 
+# ---- statistical scaling experiments (Section 6.2, Figs. 9 and 10) ----------
+# Initial data of the Section 6 advection experiments: kappa = {2, 3},
+# A = {2, 1} (phases not printed: 0).
+SCALING_IC = MultiSine((2, 3), (2.0, 1.0), (0.0, 0.0))
+DELAYS_FIG9 = ("0.3", "0.4", "0.3")
+# The two AT schemes of Figs. 9-10: ADG(1)-AT2-RK2 at sigma = 0.1 and
+# ADG(3)-AT4-RK4 at sigma = 0.01.
+SCALING_SCHEMES = {"at2": {"degree": 1, "rk": "heun", "sigma": 0.1},
+                   "at4": {"degree": 3, "rk": "rk4", "sigma": 0.01}}
+
+
+def uniform_probs(n_delays: int) -> Tuple[str, ...]:
+    """p_k = 1/L for k = 0..L-1, as exact rationals."""
+    return tuple(f"1/{n_delays}" for _ in range(n_delays))
+
+
+def scaling_workload(scheme_key: str, n_elem: int, n_pe: int, probs, seed: int, t_final: float = 1.0,
+                     scheme: str = "adg_at", name: str = "") -> Workload:
+    """One problem of the scaling experiments: linear advection a = 1 on
+    [0, 2 pi), P = n_pe PEs, delays drawn once per step (Section 6.1)."""
+    cfg = SCALING_SCHEMES[scheme_key]
+    dt, n = time_step(TWO_PI, n_elem, cfg["sigma"], 1.0, t_final)
+    return Workload(name=name or f"{scheme_key}_{scheme}_N{n_elem}_P{n_pe}_s{seed}", scheme=scheme,
+                    rk=cfg["rk"], degree=cfg["degree"], n_elem=n_elem, pe_size=n_elem // n_pe,
+                    probs=tuple(probs), seed=seed, per_stage=False, dt=dt, n_steps=n, ic=SCALING_IC)
+
+
+def error_vs_pe_workloads(scheme_key: str, n_elem: int, pe_counts, n_real: int, probs=DELAYS_FIG9,
+                          t_final: float = 1.0, seed_base: int = 9):
+    """Fig. 9 at one mesh: n_real delay realizations for each P (group g =
+    index of P).  Seeds are distinct across meshes, P and realizations."""
+    out, group = [], []
+    for g, npe in enumerate(pe_counts):
+        for r in range(n_real):
+            seed = (seed_base << 48) | (n_elem << 24) | (npe << 16) | r
+            out.append(scaling_workload(scheme_key, n_elem, npe, probs, seed, t_final))
+            group.append(g)
+    return out, group
+
+
+def error_vs_delay_workloads(scheme_key: str, n_elem: int, n_pe: int, delay_counts, n_real: int,
+                             t_final: float = 1.0, seed_base: int = 10):
+    """Fig. 10: n_real realizations for each maximum delay L with uniform p_k
+    (group g = index of L)."""
+    out, group = [], []
+    for g, nd in enumerate(delay_counts):
+        for r in range(n_real):
+            seed = (seed_base << 48) | (nd << 24) | r
+            out.append(scaling_workload(scheme_key, n_elem, n_pe, uniform_probs(nd), seed, t_final))
+            group.append(g)
+    return out, group
+
+
 def random_coefficients(seed: int, shape) -> np.ndarray:
     """Generic N(0,1) FP64 array (cotangents, perturbation directions)."""
     return np.random.default_rng(seed).standard_normal(shape)

@@ -1,0 +1,78 @@
+"""Section 6.2 scaling experiments on the batched GPU engine: the driver's
+ensemble statistics against the oracle on a small case, then the paper's
+claims on the full experiments (Figs. 9 and 10): the AT schemes keep orders
+2 and 4 for every P, the asynchrony error of ADG(1)-AT2-RK2 grows linearly
+with P, and <E-bar> follows the delay moment of the AT remainder."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2404_03399_amd import experiments as X
+from paper_2404_03399_amd import workloads as W
+from oracle import basis, exact, stats, stepper
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.mark.parametrize("scheme_key,ne", [("at2", 64), ("at4", 32)])
+def test_ensemble_statistics_match_oracle(torch_cuda, scheme_key, ne):
+    ws, grp = W.error_vs_pe_workloads(scheme_key, ne, (2, 4), 3)
+    _say(f"experiment statistics vs oracle: {scheme_key} N_E={ne}, P=2,4, 3 realizations")
+    got = X.run_groups(ws, grp, 2, 1.0)
+    per = []
+    for w in ws:
+        u = stepper.Stepper(w).run(stepper.initial_state(w), w.n_steps)
+        x = basis.element_nodes(w.x_left, w.length, w.n_elem, w.degree)
+        per.append(stats.mean_abs(u, exact.advection(w, x, 1.0)))
+    for g in range(2):
+        mean, var = stats.ensemble_mean_var([e for e, gg in zip(per, grp) if gg == g])
+        # the states agree to ~1e-15 relative to |u| <= 3; the errors inherit that absolute size
+        assert abs(got[g][0] - mean) <= 1e-12, (g, got[g][0], mean)
+        assert abs(got[g][1] - var) <= 1e-12 * max(mean, 1e-300), (g, got[g][1], var)
+
+
+def test_error_vs_pe_at2(torch_cuda):
+    _say("Fig. 9(a): ADG(1)-AT2-RK2, N_E = 128..1024, P = 2..32, 32 realizations")
+    r = X.error_vs_pe("at2", n_elems=(128, 256, 512, 1024))
+    for slope in r["order_in_n_elem"]:
+        assert -2.05 <= slope <= -1.95, r["order_in_n_elem"]
+    inset = r["inset"]
+    assert all(b > a for a, b in zip(inset["mean"], inset["mean"][1:]))  # more PEs, more error
+    assert 0.85 <= inset["slope_excess_vs_pe"] <= 1.15, inset  # linear in P
+
+
+def test_error_vs_pe_at4(torch_cuda):
+    _say("Fig. 9(b): ADG(3)-AT4-RK4, N_E = 64..512, P = 2..32, 32 realizations")
+    r = X.error_vs_pe("at4", n_elems=(64, 128, 256, 512))
+    for slope in r["order_in_n_elem"]:
+        assert -4.1 <= slope <= -3.9, r["order_in_n_elem"]
+    # the AT4 flux keeps the synchronous accuracy: the asynchrony error
+    # (~ dt^4 P / N_E) is many orders below the spatial error here
+    for row in r["table"]:
+        for m in row["mean"]:
+            assert abs(m / row["dg"] - 1.0) <= 1e-4
+
+
+def test_error_vs_delay(torch_cuda):
+    _say("Fig. 10: <E-bar> against L with p_k = 1/L, AT2 (N_E=512) and AT4 (N_E=128), P = 16")
+    a = X.error_vs_delay("at2", n_elem=512, delay_counts=(1, 2, 3, 4))
+    assert all(a["stable"])
+    assert all(m2 > m1 for m1, m2 in zip(a["mean"], a["mean"][1:]))
+    assert a["fit"]["r2"] >= 0.99 and a["fit"]["c1"] > 0, a["fit"]
+    b = X.error_vs_delay("at4", n_elem=128, delay_counts=(1, 2, 3))
+    assert all(b["stable"])
+    assert all(m2 >= m1 for m1, m2 in zip(b["mean"], b["mean"][1:]))
