@@ -191,6 +191,7 @@ def bench_experiments():
     f9b = X.error_vs_pe("at4", n_elems=(64, 128, 256, 512))
     f10a = X.error_vs_delay("at2", n_elem=512, delay_counts=(1, 2, 3, 4, 5))
     f10b = X.error_vs_delay("at4", n_elem=128, delay_counts=(1, 2, 3, 4))
+    caa = X.error_caa("at2")
     def slim(r):
         return {k: r[k] for k in ("n_elem", "n_pe", "delay_counts", "mean", "delay_moment", "stable", "fit")}
     return {"wall_s": time.perf_counter() - t0, "n_real": f9a["n_real"],
@@ -199,7 +200,8 @@ def bench_experiments():
                          "slope_excess_vs_pe": f9a["inset"]["slope_excess_vs_pe"]},
             "fig9_at4": {"order_in_n_elem": f9b["order_in_n_elem"], "order_dg": f9b["order_in_n_elem_dg"],
                          "inset_n_elem": f9b["inset"]["n_elem"], "inset_excess_over_dg": f9b["inset"]["excess_over_dg"]},
-            "fig10_at2": slim(f10a), "fig10_at4": slim(f10b)}
+            "fig10_at2": slim(f10a), "fig10_at4": slim(f10b),
+            "caa_at2": {k: caa[k] for k in ("n_elems", "order_caa", "order_dg", "ratio_to_dg")}}
 
 
 def bench_ensemble(torch, W, Solver, n_steps: int, n_real: int, plain: bool):

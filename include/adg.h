@@ -70,7 +70,12 @@ enum adg_scheme { ADG_SCHEME_DG = 0, ADG_SCHEME_ADG = 1, ADG_SCHEME_ADG_AT = 2 }
 enum adg_flux { ADG_FLUX_UPWIND = 0, ADG_FLUX_CENTRAL = 1, ADG_FLUX_LLF = 2 };
 /* Heun RK2 as in Sec. 4.2.1; Shu-Osher SSP-RK3; classical RK4. */
 enum adg_rk { ADG_RK2_HEUN = 0, ADG_SSPRK3 = 1, ADG_RK4 = 2 };
-enum adg_delay_granularity { ADG_DELAY_PER_STEP = 0, ADG_DELAY_PER_STAGE = 1 };
+/* PER_STEP / PER_STAGE: random delays drawn per step or per (step, stage);
+ * CAA: the deterministic communication-avoiding cycle of Sec. 7 (of every five
+ * steps the first two synchronise, the next three do not): delays
+ * (0, 0, 0, 1, 2) by step mod 5 at every PE face, thresholds and seed ignored,
+ * n_delays must be 3. */
+enum adg_delay_granularity { ADG_DELAY_PER_STEP = 0, ADG_DELAY_PER_STAGE = 1, ADG_DELAY_CAA = 2 };
 /* Kernel family: one launch per RK stage with the RK registers in HBM, or one
  * launch per time step with all stages kept on chip (halo recompute). */
 enum adg_kernel { ADG_KERNEL_AUTO = 0, ADG_KERNEL_STAGE = 1, ADG_KERNEL_FUSED = 2 };

@@ -24,6 +24,17 @@ from typing import Sequence
 
 import numpy as np
 
+# Communication-avoiding schedule (Sec. 7, the two-dimensional runs): in
+# every cycle of five steps the first two communicate with synchronisation and
+# the remaining three do not, during which the PE-boundary data are 0, 1 and 2
+# levels old (L = 3).  Deterministic and equal at every PE boundary.
+CAA_CYCLE = (0, 0, 0, 1, 2)
+
+
+def caa_delay(step: int) -> int:
+    return CAA_CYCLE[step % len(CAA_CYCLE)]
+
+
 MASK64 = (1 << 64) - 1
 GAMMA = 0x9E3779B97F4A7C15
 
@@ -67,8 +78,9 @@ def clamp(k_drawn: int, step: int, q: int) -> int:
 
 
 def schedule(seed: int, probs: Sequence, n_steps: int, n_stages: int, n_bound: int,
-             per_stage: bool, q: int, step0: int = 0) -> np.ndarray:
-    """Clamped delays k[n - step0, s, b] for steps step0..step0+n_steps-1."""
+             per_stage: bool, q: int, step0: int = 0, caa: bool = False) -> np.ndarray:
+    """Clamped delays k[n - step0, s, b] for steps step0..step0+n_steps-1
+    (caa: the communication-avoiding cycle instead of random draws)."""
     edges = thresholds(probs)
     out = np.zeros((n_steps, n_stages, n_bound), dtype=np.int32)
     for i in range(n_steps):
@@ -76,5 +88,6 @@ def schedule(seed: int, probs: Sequence, n_steps: int, n_stages: int, n_bound: i
         for s in range(n_stages):
             key = s if per_stage else 0
             for b in range(n_bound):
-                out[i, s, b] = clamp(draw(seed, n, key, b, edges), n, q)
+                k = caa_delay(n) if caa else draw(seed, n, key, b, edges)
+                out[i, s, b] = clamp(k, n, q)
     return out

@@ -131,6 +131,8 @@ class Stepper:
     def delays_at(self, n: int, s: int, keys: np.ndarray) -> np.ndarray:
         if self.forced is not None:
             k = np.asarray(self.forced(n, s), dtype=np.int64)
+        elif getattr(self.w, "caa", False):
+            k = np.full(len(keys), delays.caa_delay(n), dtype=np.int64)
         else:
             key = s if self.w.per_stage else 0
             k = draw_vec(self.w.seed, n, key, keys, self.edges)

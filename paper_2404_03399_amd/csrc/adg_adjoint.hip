@@ -202,7 +202,7 @@ __device__ __forceinline__ void adj_tile(const DevProblem& P, const WorkItem wi,
 #pragma unroll
       for (int s = 0; s < S; ++s) {
         const uint64_t pre = P.per_stage ? delay_prefix(P.seed, n, s) : pre0;
-        kd[s] = clamp_delay(delay_from_prefix(pre, b, P.thr, P.n_delays), n, P.q);
+        kd[s] = clamp_delay(P.caa ? caa_delay(n) : delay_from_prefix(pre, b, P.thr, P.n_delays), n, P.q);
         const int64_t rb = P.ring_off + ((int64_t)b * S + s) * depth;
         adjn[s] = adjring[rb + slot_n];
         if (FWD && kd[s] > 0) atf[s] = at_past_sum(P, ring + rb, kd[s], slot_n);

@@ -185,7 +185,9 @@ int validate_one(const adg_problem& p, int idx) {
   if (p.scheme == ADG_SCHEME_ADG_AT && p.at_levels == 0 && p.degree + 1 > (uint32_t)kMaxQ)
     return fail(ADG_E_INVALID, at + "q = degree + 1 exceeds 5");
   if (p.n_delays < 1 || p.n_delays > (uint32_t)kMaxL) return fail(ADG_E_INVALID, at + "n_delays must be in 1..8");
-  if (p.delay_granularity > ADG_DELAY_PER_STAGE) return fail(ADG_E_INVALID, at + "bad delay_granularity");
+  if (p.delay_granularity > ADG_DELAY_CAA) return fail(ADG_E_INVALID, at + "bad delay_granularity");
+  if (p.delay_granularity == ADG_DELAY_CAA && p.n_delays != 3)
+    return fail(ADG_E_INVALID, at + "the communication-avoiding cycle needs n_delays = 3");
   if (p.reserved != 0) return fail(ADG_E_INVALID, at + "reserved must be 0");
   if (p.n_elem < 2 || p.n_elem > (int64_t)1 << 30) return fail(ADG_E_INVALID, at + "n_elem must be in 2..2^30");
   if (p.pe_size < 1 || p.n_elem % p.pe_size != 0) return fail(ADG_E_INVALID, at + "pe_size must divide n_elem");
@@ -587,6 +589,7 @@ int adg_init(adg_ctx** out, const adg_problem* probs, int32_t n_probs, const adg
     d.n_delays = (int)p.n_delays;
     d.depth = (int32_t)depth_of(p, n_steps_record);
     d.per_stage = p.delay_granularity == ADG_DELAY_PER_STAGE;
+    d.caa = p.delay_granularity == ADG_DELAY_CAA;
     d.scheme = (int)p.scheme;
     d.async_faces = async_of(p) ? 1 : 0;
     d.pe_div = make_fast_div((uint32_t)p.pe_size);
@@ -1018,7 +1021,9 @@ int adg_delay_schedule(const adg_problem* p, int64_t step0, int64_t n_steps, int
       for (int64_t b = 0; b < P; ++b) {
         int k = 0;
         if (p->scheme != ADG_SCHEME_DG) {
-          k = draw_delay(p->seed, n, key, b, p->delay_threshold, (int)p->n_delays);
+          k = p->delay_granularity == ADG_DELAY_CAA
+                  ? caa_delay(n)
+                  : draw_delay(p->seed, n, key, b, p->delay_threshold, (int)p->n_delays);
           k = clamp_delay(k, n, q);
         }
         h_k[(i * S + s) * P + b] = k;

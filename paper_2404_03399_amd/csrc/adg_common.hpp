@@ -64,7 +64,7 @@ struct DevProblem {
   int32_t per_stage;     // delay key includes the stage
   int32_t scheme;        // Scheme
   int32_t async_faces;   // 1 if PE faces use delayed data (scheme != DG and P > 1)
-  int32_t pad0;
+  int32_t caa;           // delays follow the communication-avoiding cycle
   FastDiv pe_div;        // division by pe_size
   uint64_t seed;
   uint64_t thr[kMaxL - 1];
@@ -126,6 +126,14 @@ __host__ __device__ inline int delay_from_prefix(uint64_t prefix, int64_t bounda
 __host__ __device__ inline int draw_delay(uint64_t seed, int64_t step, int32_t key, int64_t boundary,
                                           const uint64_t* thr, int n_delays) {
   return delay_from_prefix(delay_prefix(seed, step, key), boundary, thr, n_delays);
+}
+
+// Communication-avoiding schedule (Sec. 7): of every five steps the first two
+// communicate with synchronisation and the next three do not, so the PE-face
+// data are 0, 1 and 2 levels old: delays (0, 0, 0, 1, 2) at every face.
+__host__ __device__ inline int caa_delay(int64_t step) {
+  const int c = (int)(step % 5);
+  return c < 3 ? 0 : c - 2;
 }
 
 // Usable delay: every level n-k-j, j < q, must exist.

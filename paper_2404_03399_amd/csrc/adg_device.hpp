@@ -64,7 +64,8 @@ __device__ __forceinline__ int ring_slot(int slot_n, int back, int depth) {
 // Clamped delay of boundary b at (step n, stage s).
 __device__ __forceinline__ int pe_delay(const DevProblem& P, int64_t n, int s, uint32_t b) {
   const int key = P.per_stage ? s : 0;
-  return clamp_delay(draw_delay(P.seed, n, key, (int64_t)b, P.thr, P.n_delays), n, P.q);
+  const int k = P.caa ? caa_delay(n) : draw_delay(P.seed, n, key, (int64_t)b, P.thr, P.n_delays);
+  return clamp_delay(k, n, P.q);
 }
 
 // sum_{j<q} c_j(k) F^{n-k-j} over the ring of (boundary, stage); k >= 1, so

@@ -112,8 +112,10 @@ __device__ __forceinline__ void wave_tile(const DevProblem& P, const WorkItem wi
         const double* __restrict__ rb0 = A.ring + P.ring_off + (int64_t)b * S * depth;
 #pragma unroll
         for (int s = 0; s < S; ++s) {
-          const int kd = clamp_delay(delay_from_prefix(delay_prefix(P.seed, n1, P.per_stage ? s : 0), b, P.thr,
-                                                       P.n_delays), n1, P.q);
+          const int kraw = P.caa ? caa_delay(n1)
+                                 : delay_from_prefix(delay_prefix(P.seed, n1, P.per_stage ? s : 0), b, P.thr,
+                                                     P.n_delays);
+          const int kd = clamp_delay(kraw, n1, P.q);
           kp[1] |= kd << (8 * s);
           // level n1 - kd - j <= n - 1 unless kd == 1 and j == 0 (level n, added in step n)
           sm.at[1][wv][s][lane] = kd > 0 ? at_sum_from(P, rb0 + s * depth, kd, kd == 1 ? 1 : 0, slot_n, depth) : 0.0;
@@ -234,7 +236,7 @@ __device__ __forceinline__ void wave_tile(const DevProblem& P, const WorkItem wi
       const int s = lane;
       const int64_t nk = n + K;
       const uint64_t pre = delay_prefix(P.seed, nk, P.per_stage ? s : 0);
-      const int kd = clamp_delay(delay_from_prefix(pre, bo, P.thr, P.n_delays), nk, P.q);
+      const int kd = clamp_delay(P.caa ? caa_delay(nk) : delay_from_prefix(pre, bo, P.thr, P.n_delays), nk, P.q);
       const double* __restrict__ rb = A.ring + P.ring_off + ((int64_t)bo * S + s) * depth;
       const double acc = kd > 0 ? at_sum_from(P, rb, kd, 0, slot_m, depth) : 0.0;  // slot_m: level nk - 1
       const int64_t rs = rec_slot(nk);

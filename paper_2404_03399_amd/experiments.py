@@ -14,6 +14,8 @@ initial data:
   (Fig. 10), fitted against the delay moment of the AT remainder,
   E[k (k+1) ... (k+q-1)] (E[k^2] + E[k] for q = 2; E[k^4] + 6E[k^3] +
   11E[k^2] + 6E[k] for q = 4).
+* `error_caa`: the deterministic communication-avoiding cycle of Sec. 7
+  against synchronous DG over the mesh.
 
 Every realization of one mesh runs in one batched context (one launch per
 step for all of them); the statistics come from adg_ensemble_stats.  The
@@ -145,11 +147,28 @@ def error_vs_delay(scheme_key: str = "at2", n_elem: int = 512, n_pe: int = 16, d
             "delay_moment": moments, "stable": stable, "fit": fit}
 
 
+def error_caa(scheme_key: str = "at2", n_elems=(64, 128, 256, 512, 1024), n_pe: int = 8,
+              t_final: float = 1.0) -> dict:
+    """The communication-avoiding cycle of Sec. 7 (delays 0, 0, 0, 1, 2 by
+    step mod 5; deterministic, so one run per mesh) against synchronous DG:
+    the AT scheme keeps its order and DG-level errors."""
+    at, dg = [], []
+    for ne in n_elems:
+        w = W.scaling_workload(scheme_key, ne, n_pe, W.DELAYS_UNIFORM3, 0, t_final)
+        w = W.replace(w, caa=True, name=f"caa_{scheme_key}_{ne}")
+        at.append(run_groups([w], [0], 1, t_final)[0][0])
+        dg.append(sync_error(scheme_key, ne, t_final))
+    return {"scheme": scheme_key, **W.SCALING_SCHEMES[scheme_key], "n_pe": n_pe, "n_elems": list(n_elems),
+            "caa": at, "dg": dg, "order_caa": loglog_slope(n_elems, at), "order_dg": loglog_slope(n_elems, dg),
+            "ratio_to_dg": [a / d for a, d in zip(at, dg)]}
+
+
 def main(argv=None) -> int:
     t0 = time.perf_counter()
     out = {"error_vs_pe": [error_vs_pe("at2", n_elems=(64, 128, 256, 512, 1024)),
                            error_vs_pe("at4", n_elems=(64, 128, 256, 512))],
-           "error_vs_delay": [error_vs_delay("at2", n_elem=512), error_vs_delay("at4", n_elem=128)]}
+           "error_vs_delay": [error_vs_delay("at2", n_elem=512), error_vs_delay("at4", n_elem=128)],
+           "communication_avoiding": [error_caa("at2"), error_caa("at4", n_elems=(64, 128, 256, 512))]}
     out["wall_s"] = time.perf_counter() - t0
     print(json.dumps(out))
     return 0

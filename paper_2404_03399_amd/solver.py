@@ -39,7 +39,7 @@ def to_problem(w) -> adg.adg_problem:
     p.degree = w.degree
     p.at_levels = w.at_levels if w.scheme == "adg_at" else 0
     p.n_delays = len(w.probs)
-    p.delay_granularity = 1 if w.per_stage else 0
+    p.delay_granularity = 2 if getattr(w, "caa", False) else (1 if w.per_stage else 0)
     p.reserved = 0
     p.n_elem = w.n_elem
     p.pe_size = w.pe_size

@@ -48,6 +48,7 @@ class Workload:
     probs: Tuple[str, ...] = ("1",)  # decimal strings, exact
     seed: int = 0
     per_stage: bool = True           # delay key includes the RK stage
+    caa: bool = False                # delays follow the communication-avoiding cycle (L = 3)
     at_levels: int = 0               # q; 0 -> degree + 1
     x_left: float = 0.0
     length: float = TWO_PI

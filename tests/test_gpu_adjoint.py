@@ -165,6 +165,21 @@ def test_gradient_without_speed_is_identical(torch_cuda, kernel, equation):
     s.close()
 
 
+@pytest.mark.parametrize("kernel", ["fused", "stage"])
+def test_adjoint_with_communication_avoiding_cycle(torch_cuda, kernel):
+    w = W.Workload(name="adj_caa", scheme="adg_at", rk="rk4", degree=2, n_elem=120, pe_size=10,
+                   probs=W.DELAYS_UNIFORM3, caa=True, per_stage=False, dt=0.01 * W.TWO_PI / 120,
+                   speed=1.1, ic=W.PAPER_MULTISINE)
+    n = 21
+    u0 = stepper.initial_state(w)
+    ref = np.random.default_rng(8).standard_normal(u0.shape)
+    _say(f"adjoint with the communication-avoiding cycle, kernel={kernel}")
+    _, g_o, ga_o = oadj.gradient(w, u0, n, oadj.misfit_cotangent(ref))
+    g, ga, _ = _gpu_grad(torch_cuda, w, u0, n, lambda x: x - ref, kernel=kernel, ckpt=4)
+    assert stats.rel_l2(g, g_o) <= 1e-12
+    assert abs(ga - ga_o) <= 1e-12 * max(1.0, abs(ga_o))
+
+
 def test_stepping_after_adjoint_continues_the_run(torch_cuda):
     """adg_adjoint restores the PE-face records of the current step: stepping
     on afterwards gives bitwise the run that never called the adjoint."""

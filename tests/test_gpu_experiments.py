@@ -76,3 +76,11 @@ def test_error_vs_delay(torch_cuda):
     b = X.error_vs_delay("at4", n_elem=128, delay_counts=(1, 2, 3))
     assert all(b["stable"])
     assert all(m2 >= m1 for m1, m2 in zip(b["mean"], b["mean"][1:]))
+
+
+def test_communication_avoiding_keeps_order(torch_cuda):
+    _say("Sec. 7 communication-avoiding cycle: ADG(1)-AT2-RK2 and ADG(3)-AT4-RK4 vs DG")
+    a = X.error_caa("at2")
+    assert -2.05 <= a["order_caa"] <= -1.95 and max(a["ratio_to_dg"]) < 1.1, a
+    b = X.error_caa("at4", n_elems=(64, 128, 256, 512))
+    assert -4.1 <= b["order_caa"] <= -3.9 and max(b["ratio_to_dg"]) < 1.01, b

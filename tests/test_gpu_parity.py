@@ -197,6 +197,23 @@ def test_two_steps_per_launch_bitwise(torch_cuda, ne, pe, p, rk, phys, scheme, p
     assert stats.rel_l2(two, oracle_run(w, u0, n)) <= TOL
 
 
+@pytest.mark.parametrize("p,rk,scheme,lane_elems,fused_steps", [
+    (1, "heun", "adg_at", 1, 2), (3, "rk4", "adg_at", 2, 2), (2, "ssprk3", "adg", 1, 1), (4, "rk4", "adg_at", 4, 1)])
+def test_communication_avoiding_cycle(torch_cuda, p, rk, scheme, lane_elems, fused_steps):
+    """Deterministic communication-avoiding delays (0, 0, 0, 1, 2 by step mod 5)
+    through both kernel families against the oracle."""
+    ne = 600
+    sig = {1: 0.05, 2: 0.01, 3: 0.005, 4: 0.001}[p]
+    w = W.Workload(name=f"caa_{p}", scheme=scheme, rk=rk, degree=p, n_elem=ne, pe_size=25,
+                   probs=W.DELAYS_UNIFORM3, caa=True, per_stage=False, dt=sig * W.TWO_PI / ne,
+                   ic=W.PAPER_MULTISINE)
+    _check(torch_cuda, w, 17, "fused", graph=False, lane_elems=lane_elems)
+    u0 = stepper.initial_state(w)
+    a = gpu_run(torch_cuda, w, u0, 17, "fused", graph=False, lane_elems=lane_elems, fused_steps=fused_steps)
+    b = gpu_run(torch_cuda, w, u0, 17, "stage", graph=False)
+    assert stats.rel_l2(a, b) <= 1e-13
+
+
 def test_lane_elems_rejected_above_pe_size(torch_cuda):
     from paper_2404_03399_amd import adg
     from paper_2404_03399_amd.solver import Solver

@@ -82,6 +82,22 @@ def test_delay_schedule_bit_exact_vs_oracle(L, rk, per_stage, scheme):
     assert np.array_equal(got, ref)
 
 
+@pytest.mark.parametrize("rk,q", [("heun", 2), ("rk4", 4)])
+def test_caa_schedule_bit_exact_vs_oracle(L, rk, q):
+    w = replace(W.c2_advection_large("adg_at", n_elem=1024), rk=rk, caa=True, probs=W.DELAYS_UNIFORM3,
+                degree=q - 1)
+    S = adg.RK_STAGES[rk]
+    got = adg.adg_delay_schedule(solver.to_problem(w), 0, 23, S, w.n_pe)
+    ref = delays.schedule(w.seed, w.probs, 23, S, w.n_pe, w.per_stage, q, caa=True)
+    assert np.array_equal(got, ref)
+    # every face and stage of a step shares the cycle's delay
+    assert all(len(np.unique(got[i])) == 1 for i in range(23))
+    # communication-avoiding with L = 3 needs exactly three delay levels
+    p = solver.to_problem(replace(w, probs=W.DELAYS_C2))
+    with pytest.raises(adg.AdgError):
+        adg.adg_workspace_size([p], adg.adg_options())
+
+
 def _bad(**kw):
     return solver.to_problem(replace(W.c1_advection_small(), **kw))
 

@@ -129,6 +129,37 @@ def test_adg_loses_order_at_recovers_it(p, rk, sig):
     assert np.all(at[:, 0] < 1.5 * dg[:, 0])
 
 
+def _series_caa(p, rk, sig, scheme, sizes, t_final=0.5):
+    out = []
+    for ne in sizes:
+        dt, n = W.time_step(W.TWO_PI, ne, sig, 1.0, t_final)
+        w = _wl(scheme=scheme, rk=rk, degree=p, n_elem=ne, pe_size=ne // 8, probs=W.DELAYS_UNIFORM3,
+                caa=True, per_stage=False, dt=dt, n_steps=n)
+        out.append(_run_error(w))
+    return np.array(out)
+
+
+def test_communication_avoiding_cycle():
+    """Sec. 7's communication-avoiding runs (L = 3, delays 0, 1, 2 in the three
+    steps of every five without communication): ADG(1)-AT2-RK2 keeps second
+    order and DG-level errors, conservation holds, and the cycle's delays are
+    really applied (plain ADG with the same cycle is far less accurate)."""
+    sizes = [64, 128, 256]
+    dg = _series(1, "heun", 0.1, "dg", sizes)
+    at = _series_caa(1, "heun", 0.1, "adg_at", sizes)
+    plain = _series_caa(1, "heun", 0.1, "adg", sizes)
+    slopes = np.log2(at[:-1, 0] / at[1:, 0])
+    assert np.all(slopes > 1.85), slopes
+    assert np.all(at[:, 0] < 1.5 * dg[:, 0])
+    assert at[:, 2].max() < 1e-12 and plain[:, 2].max() < 1e-12
+    assert np.all(plain[:, 1] > 2 * dg[:, 1])
+    st = stepper.Stepper(_wl(scheme="adg_at", rk="heun", degree=1, n_elem=32, pe_size=4,
+                             probs=W.DELAYS_UNIFORM3, caa=True, dt=1e-3, n_steps=12), record_delays=True)
+    st.run(stepper.initial_state(st.w), 12)
+    ks = [int(st.delay_log[(n, 0)][0]) for n in range(12)]
+    assert ks == [0, 0, 0, 1, 2, 0, 0, 0, 1, 2, 0, 0]  # the cycle (0, 0, 0, 1, 2) by step mod 5
+
+
 def test_naive_adg_breaks_conservation():
     """Sec. 4.1: independent delays on the two sides make the flux two-valued."""
     e = _series(1, "heun", 0.1, "naive", [64])
