@@ -23,7 +23,33 @@ import numpy as np
 
 from . import stepper as stp
 
+def butcher_from_2n(A, B):
+    """Butcher form of a 2N-storage scheme, exact: with U_0 = U and K_s the
+    operator at U_{s-1}, U_s = U + dt sum_{j<=s} beta_{s,j} K_j where
+    beta_{s,j} = B_s alpha_{s,j} + beta_{s-1,j} and alpha_{s,j} (the weights
+    of dU_s) = A_s alpha_{s-1,j} for j < s, 1 for j = s.  Stage s+1 reads
+    U_s, so a_{s+1,j} = beta_{s,j} and b_j = beta_{S,j}."""
+    from fractions import Fraction
+    A = [Fraction(x) for x in A]
+    B = [Fraction(x) for x in B]
+    S = len(A)
+    alpha = [Fraction(0)] * S
+    beta = [Fraction(0)] * S
+    rows = [[]]
+    for s in range(S):
+        alpha = [A[s] * alpha[j] if j < s else (Fraction(1) if j == s else Fraction(0)) for j in range(S)]
+        beta = [beta[j] + B[s] * alpha[j] for j in range(S)]
+        if s + 1 < S:
+            rows.append(beta[:s + 1])
+    return rows, beta
+
+
+def _float_table(rows, b):
+    return [[float(x) for x in r] for r in rows], [float(x) for x in b]
+
+
 BUTCHER = {
+    "lsrk3": _float_table(*butcher_from_2n(stp.LSRK3_A, stp.LSRK3_B)),
     "heun": ([[], [1.0]], [0.5, 0.5]),
     "ssprk3": ([[], [1.0], [0.25, 0.25]], [1.0 / 6.0, 1.0 / 6.0, 2.0 / 3.0]),
     "rk4": ([[], [0.5], [0.0, 0.5], [0.0, 0.0, 1.0]], [1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0]),

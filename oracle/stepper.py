@@ -36,11 +36,19 @@ schemes are not printed).
 """
 from __future__ import annotations
 
+from fractions import Fraction
+
 import numpy as np
 
 from . import basis, atflux, delays
 
-N_STAGES = {"heun": 2, "ssprk3": 3, "rk4": 4}
+N_STAGES = {"heun": 2, "ssprk3": 3, "rk4": 4, "lsrk3": 3}
+
+# Williamson's third-order 2N-storage scheme (J. Comput. Phys. 35, 1980), of
+# the low-storage family the paper integrates with (Sec. 6.1):
+#   dU_s = A_s dU_{s-1} + dt L(U_{s-1}),  U_s = U_{s-1} + B_s dU_s,  s = 1..3.
+LSRK3_A = ("0", "-5/9", "-153/128")
+LSRK3_B = ("1/3", "15/16", "8/15")
 
 _M64 = np.uint64(0xFFFFFFFFFFFFFFFF)
 
@@ -190,6 +198,13 @@ class Stepper:
             u1 = u + dt * L(u, n, 0)
             u2 = 0.75 * u + 0.25 * (u1 + dt * L(u1, n, 1))
             return u / 3.0 + (2.0 / 3.0) * (u2 + dt * L(u2, n, 2))
+        if rk == "lsrk3":
+            du = np.zeros_like(u)
+            y = u
+            for s_, (a, b) in enumerate(zip(LSRK3_A, LSRK3_B)):
+                du = float(Fraction(a)) * du + dt * L(y, n, s_)
+                y = y + float(Fraction(b)) * du
+            return y
         if rk == "rk4":
             k1 = L(u, n, 0)
             k2 = L(u + 0.5 * dt * k1, n, 1)

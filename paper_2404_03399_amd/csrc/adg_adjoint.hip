@@ -358,6 +358,7 @@ hipError_t launch_adj_stage(int rk, int phys, int stage, const StepArgs& a, cons
   switch (rk) {
     case RK_HEUN: adj_phys<RK_HEUN>(phys, stage, a, p, n, stream); break;
     case RK_SSP3: adj_phys<RK_SSP3>(phys, stage, a, p, n, stream); break;
+    case RK_LS3: adj_phys<RK_LS3>(phys, stage, a, p, n, stream); break;
     default: adj_phys<RK_RK4>(phys, stage, a, p, n, stream); break;
   }
   return hipGetLastError();
@@ -407,6 +408,7 @@ hipError_t launch_adj_fused(int rk, int phys, const AdjArgs& a, const double* u,
   switch (rk) {
     case RK_HEUN: adj_fused_rk<RK_HEUN>(phys, a, u, lam, lamo, ring, adjring, cpart, n, stream); break;
     case RK_SSP3: adj_fused_rk<RK_SSP3>(phys, a, u, lam, lamo, ring, adjring, cpart, n, stream); break;
+    case RK_LS3: adj_fused_rk<RK_LS3>(phys, a, u, lam, lamo, ring, adjring, cpart, n, stream); break;
     default: adj_fused_rk<RK_RK4>(phys, a, u, lam, lamo, ring, adjring, cpart, n, stream); break;
   }
   return hipGetLastError();

@@ -173,7 +173,7 @@ int validate_one(const adg_problem& p, int idx) {
   if (p.equation > ADG_EQ_BURGERS) return fail(ADG_E_INVALID, at + "unknown equation");
   if (p.scheme > ADG_SCHEME_ADG_AT) return fail(ADG_E_INVALID, at + "unknown scheme");
   if (p.flux > ADG_FLUX_LLF) return fail(ADG_E_INVALID, at + "unknown flux");
-  if (p.rk > ADG_RK4) return fail(ADG_E_INVALID, at + "unknown rk");
+  if (p.rk > ADG_LSRK3) return fail(ADG_E_INVALID, at + "unknown rk");
   if (p.degree < 1 || p.degree > 4) return fail(ADG_E_INVALID, at + "degree must be in 1..4");
   if (p.equation == ADG_EQ_ADVECTION && p.flux == ADG_FLUX_LLF)
     return fail(ADG_E_INVALID, at + "llf flux is for Burgers");

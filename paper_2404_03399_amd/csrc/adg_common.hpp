@@ -15,10 +15,10 @@ constexpr int kRecSlots = 3;  // fused kernel PE-face record slots, indexed by s
 // PHYS_ADV_UPWIND_POS: upwind advection with a > 0 in the fused kernel, which
 // folds the right-face flux a u_p into the volume operator.
 enum Phys : int { PHYS_ADV_UPWIND = 0, PHYS_ADV_CENTRAL = 1, PHYS_BURGERS_LLF = 2, PHYS_ADV_UPWIND_POS = 3 };
-enum Rk : int { RK_HEUN = 0, RK_SSP3 = 1, RK_RK4 = 2 };
+enum Rk : int { RK_HEUN = 0, RK_SSP3 = 1, RK_RK4 = 2, RK_LS3 = 3 };
 enum Scheme : int { SCH_DG = 0, SCH_ADG = 1, SCH_AT = 2 };
 
-__host__ __device__ constexpr int rk_stages(int rk) { return rk == RK_HEUN ? 2 : (rk == RK_SSP3 ? 3 : 4); }
+__host__ __device__ constexpr int rk_stages(int rk) { return rk == RK_HEUN ? 2 : (rk == RK_RK4 ? 4 : 3); }
 
 // Division by a run-time invariant 0 < d < 2^31 for dividends n < 2^31 by
 // multiplication (Granlund & Montgomery, PLDI 1994): with l = ceil(log2 d),

@@ -141,6 +141,21 @@ __device__ __forceinline__ void rk_update(int s, double dt, const double (&u0)[N
 #pragma unroll
       for (int j = 0; j < NP; ++j) y[j] = fma(2.0 / 3.0, fma(dt, k[j], y[j]), u0[j] / 3.0);
     }
+  } else if constexpr (RK == RK_LS3) {
+    // Williamson's 2N-storage form, ks holding dU:
+    // dU = A_s dU + dt k, y = y + B_s dU, A = (0, -5/9, -153/128), B = (1/3, 15/16, 8/15)
+    constexpr double A1 = -5.0 / 9.0, A2 = -153.0 / 128.0;
+    constexpr double B0 = 1.0 / 3.0, B1 = 15.0 / 16.0, B2 = 8.0 / 15.0;
+    if (s == 0) {
+#pragma unroll
+      for (int j = 0; j < NP; ++j) { ks[j] = dt * k[j]; y[j] = fma(B0, ks[j], y[j]); }
+    } else if (s == 1) {
+#pragma unroll
+      for (int j = 0; j < NP; ++j) { ks[j] = fma(A1, ks[j], dt * k[j]); y[j] = fma(B1, ks[j], y[j]); }
+    } else {
+#pragma unroll
+      for (int j = 0; j < NP; ++j) { ks[j] = fma(A2, ks[j], dt * k[j]); y[j] = fma(B2, ks[j], y[j]); }
+    }
   } else {  // Heun
     if (s == 0) {
 #pragma unroll
@@ -245,12 +260,15 @@ __device__ __forceinline__ double at_sum_from(const DevProblem& P, const double*
 // algebraic forms): Y_i = U + dt sum_{j<i} a_ij K_j, U' = U + dt sum_i b_i K_i.
 template <int RK>
 __device__ constexpr double bt_a(int i, int j) {
+  if constexpr (RK == RK_LS3)  // Williamson's scheme in Butcher form: a21 = 1/3, a31 = -3/16, a32 = 15/16
+    return i == 1 ? (j == 0 ? 1.0 / 3.0 : 0.0) : (i == 2 && j < 2 ? (j == 0 ? -3.0 / 16.0 : 15.0 / 16.0) : 0.0);
   if constexpr (RK == RK_RK4) return (j == i - 1) ? (i == 3 ? 1.0 : 0.5) : 0.0;
   else if constexpr (RK == RK_SSP3) return i == 1 ? (j == 0 ? 1.0 : 0.0) : (i == 2 && j < 2 ? 0.25 : 0.0);
   else return (i == 1 && j == 0) ? 1.0 : 0.0;
 }
 template <int RK>
 __device__ constexpr double bt_b(int i) {
+  if constexpr (RK == RK_LS3) return i == 0 ? 1.0 / 6.0 : (i == 1 ? 3.0 / 10.0 : 8.0 / 15.0);
   if constexpr (RK == RK_RK4) return (i == 0 || i == 3) ? 1.0 / 6.0 : 1.0 / 3.0;
   else if constexpr (RK == RK_SSP3) return i == 2 ? 2.0 / 3.0 : 1.0 / 6.0;
   else return 0.5;

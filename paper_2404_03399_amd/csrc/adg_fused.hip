@@ -1,10 +1,10 @@
 // Fused step kernel: one wave64 per tile, all RK stages of one or two time
-// steps on chip.  Compiled once per integrator (-DADG_RK=0, 1, 2) so that the
-// instantiations build in parallel.
+// steps on chip.  Compiled once per integrator (-DADG_RK=0, 1, 2, 3) so that
+// the instantiations build in parallel.
 #include "adg_device.hpp"
 
 #ifndef ADG_RK
-#error "compile once per integrator with -DADG_RK=0, 1 or 2"
+#error "compile once per integrator with -DADG_RK=0, 1, 2 or 3"
 #endif
 
 namespace adg {

@@ -82,6 +82,21 @@ __device__ __forceinline__ void stage_elem(const DevProblem& P, int tile, const 
         Uo[i] = Uo[i] + (dt / 6.0) * (Ao[i] + k[j]);
       }
     }
+  } else if constexpr (RK == RK_LS3) {
+    // Williamson's 2N-storage scheme, A = dU: dU = A_s dU + dt k, next = y + B_s dU
+    constexpr double Acoef = SI == 1 ? -5.0 / 9.0 : -153.0 / 128.0;
+    constexpr double Bcoef = SI == 0 ? 1.0 / 3.0 : (SI == 1 ? 15.0 / 16.0 : 8.0 / 15.0);
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+      const int64_t i = j * ld + e;
+      const double du = SI == 0 ? dt * k[j] : fma(Acoef, Ao[i], dt * k[j]);
+      if constexpr (SI < 2) {
+        Ao[i] = du;
+        Yo[i] = fma(Bcoef, du, y[j]);
+      } else {
+        Uo[i] = fma(Bcoef, du, y[j]);
+      }
+    }
   } else if constexpr (RK == RK_SSP3) {
 #pragma unroll
     for (int j = 0; j < NP; ++j) {
@@ -277,6 +292,7 @@ hipError_t launch_fused_step(int rk, int phys, const StepArgs& a, const double* 
   switch (rk) {
     case RK_HEUN: return launch_fused_rk<RK_HEUN>(phys, a, uin, uout, step_offset, stream);
     case RK_SSP3: return launch_fused_rk<RK_SSP3>(phys, a, uin, uout, step_offset, stream);
+    case RK_LS3: return launch_fused_rk<RK_LS3>(phys, a, uin, uout, step_offset, stream);
     default: return launch_fused_rk<RK_RK4>(phys, a, uin, uout, step_offset, stream);
   }
 }
@@ -286,6 +302,7 @@ hipError_t launch_stage(int rk, int phys, int stage, const StepArgs& a, const do
   switch (rk) {
     case RK_HEUN: stage_phys<RK_HEUN>(phys, stage, a, yin, yout, U, A, step_offset, stream); break;
     case RK_SSP3: stage_phys<RK_SSP3>(phys, stage, a, yin, yout, U, A, step_offset, stream); break;
+    case RK_LS3: stage_phys<RK_LS3>(phys, stage, a, yin, yout, U, A, step_offset, stream); break;
     default: stage_phys<RK_RK4>(phys, stage, a, yin, yout, U, A, step_offset, stream); break;
   }
   return hipGetLastError();

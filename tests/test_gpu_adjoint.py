@@ -47,6 +47,7 @@ CASES = [
     ("adg", "heun", 1, "central", 64, 16),
     ("dg", "rk4", 4, "upwind", 70, 7),
     ("adg_at", "rk4", 3, "central", 300, 25),
+    ("adg_at", "lsrk3", 2, "upwind", 90, 9),
 ]
 
 
@@ -69,7 +70,7 @@ def test_adjoint_matches_oracle(torch_cuda, kernel, scheme, rk, p, flux, ne, pe)
 
 @pytest.mark.parametrize("kernel", ["fused", "stage"])
 @pytest.mark.parametrize("rk,p,per_stage", [("ssprk3", 2, True), ("ssprk3", 2, False), ("rk4", 3, True),
-                                            ("heun", 1, False)])
+                                            ("heun", 1, False), ("lsrk3", 2, True)])
 def test_burgers_adjoint_matches_oracle(torch_cuda, kernel, rk, p, per_stage):
     # N = 128 spans several fused-adjoint tiles (64 - 2(2S - 1) elements each)
     w = replace(W.c3_burgers(n_elem=128, n_steps=0, sigma=0.02), pe_size=16, per_stage=per_stage, rk=rk,

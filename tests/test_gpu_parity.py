@@ -113,7 +113,7 @@ def test_c1_adg_at_as_specified_until_growth(torch_cuda):
 # ---- operator / integrator / physics matrix on a ragged mesh ------------------
 MATRIX = []
 for p in (1, 2, 3, 4):
-    for rk in ("heun", "ssprk3", "rk4"):
+    for rk in ("heun", "ssprk3", "rk4", "lsrk3"):
         for phys in ("upwind", "central", "llf"):
             MATRIX.append((p, rk, phys))
 

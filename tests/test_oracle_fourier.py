@@ -22,7 +22,7 @@ def test_published_cfl_limits(p, rk, known):
 
 def test_rk_polynomials_are_truncated_exponentials():
     th = 0.7
-    for p, rk, nst in [(1, "heun", 2), (2, "ssprk3", 3), (3, "rk4", 4)]:
+    for p, rk, nst in [(1, "heun", 2), (2, "ssprk3", 3), (3, "rk4", 4), (2, "lsrk3", 3)]:
         z = fourier.stage_matrix(p, "upwind", 0.05, th)
         g = np.eye(p + 1, dtype=complex)
         term = np.eye(p + 1, dtype=complex)

@@ -139,6 +139,44 @@ def _series_caa(p, rk, sig, scheme, sizes, t_final=0.5):
     return np.array(out)
 
 
+def test_williamson_lsrk3_order_conditions():
+    """The 2N-storage coefficients (A, B) give, in Butcher form, c = (0, 1/3,
+    3/4), a21 = 1/3, a31 = -3/16, a32 = 15/16, b = (1/6, 3/10, 8/15), which
+    meets the four third-order conditions exactly and misses fourth order."""
+    from fractions import Fraction as Fr
+    from oracle import adjoint
+    rows, b = adjoint.butcher_from_2n(stepper.LSRK3_A, stepper.LSRK3_B)
+    assert rows == [[], [Fr(1, 3)], [Fr(-3, 16), Fr(15, 16)]] and b == [Fr(1, 6), Fr(3, 10), Fr(8, 15)]
+    c = [sum(r, Fr(0)) for r in rows]
+    assert sum(b) == 1
+    assert sum(bi * ci for bi, ci in zip(b, c)) == Fr(1, 2)
+    assert sum(bi * ci * ci for bi, ci in zip(b, c)) == Fr(1, 3)
+    assert b[2] * rows[2][1] * c[1] == Fr(1, 6)
+    assert sum(bi * ci ** 3 for bi, ci in zip(b, c)) != Fr(1, 4)
+
+
+def test_williamson_lsrk3_converges_at_third_order():
+    e = _series(2, "lsrk3", 0.02, "dg", [32, 64, 128])
+    slopes = np.log2(e[:-1, 0] / e[1:, 0])
+    assert np.all(slopes > 2.85), slopes
+    assert e[:, 2].max() < 1e-12
+    at = _series(2, "lsrk3", 0.02, "adg_at", [32, 64, 128])
+    slopes = np.log2(at[:-1, 0] / at[1:, 0])
+    assert np.all(slopes > 2.8), slopes
+    # the same map as its Butcher form (one step of the adjoint's table)
+    w = _wl(scheme="dg", rk="lsrk3", degree=2, n_elem=16, pe_size=4, dt=0.01, n_steps=1)
+    st = stepper.Stepper(w)
+    u = stepper.initial_state(w)
+    from oracle import adjoint
+    rows, b = adjoint.BUTCHER["lsrk3"]
+    ks = []
+    for i in range(3):
+        y = u + w.dt * sum((rows[i][j] * ks[j] for j in range(i)), np.zeros_like(u))
+        ks.append(st.operator(y, 0, i))
+    ref = u + w.dt * sum(bi * k for bi, k in zip(b, ks))
+    np.testing.assert_allclose(st.step(u, 0), ref, rtol=0, atol=1e-14)
+
+
 def test_communication_avoiding_cycle():
     """Sec. 7's communication-avoiding runs (L = 3, delays 0, 1, 2 in the three
     steps of every five without communication): ADG(1)-AT2-RK2 keeps second
