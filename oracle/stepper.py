@@ -107,6 +107,8 @@ class Stepper:
         self.coef = {k: np.array(atflux.at_coefficients(self.q, k)) for k in range(self.n_delays)}
         self.faces = np.arange(self.n_pe, dtype=np.int64) * w.pe_size
         self.hist = {}          # (level, stage) -> (u-, u+) at the PE faces
+        self.hist_u = {}        # local DG: (level, stage) -> u-hat at the PE faces
+        self.hist_g = {}        # local DG: (level, stage) -> total flux G at the PE faces
         self.record = record_delays
         self.delay_log = {}     # (step, stage) -> clamped delays per boundary
         self.forced = None      # optional fixed delays: callable (n, s) -> int array
@@ -115,7 +117,7 @@ class Stepper:
     def flux_fn(self, u):
         if self.w.equation == "advection":
             return self.a * u
-        return 0.5 * u * u
+        return 0.5 * u * u  # Burgers, inviscid or viscous
 
     def fhat(self, um, up):
         w = self.w
@@ -146,8 +148,53 @@ class Stepper:
             k = draw_vec(self.w.seed, n, key, keys, self.edges)
         return np.minimum(k, max(0, n - self.q + 1))
 
+    # ---- viscous Burgers, local DG (Sec. 6.1) ------------------------------
+    def _at_face_values(self, store: dict, raw: np.ndarray, n: int, s: int) -> np.ndarray:
+        """Face values at the PE faces after the delay rule: the raw level-n
+        values are stored per (level, stage); a delayed face takes the AT
+        combination sum_j c_j(k) of the stored levels n-k-j (Sec. 5)."""
+        store[(n, s)] = raw.copy()
+        store.pop((n - (self.n_delays + self.q), s), None)
+        k = self.delays_at(n, s, np.arange(self.n_pe))
+        out = raw.copy()
+        for b in range(self.n_pe):
+            kb = int(k[b])
+            if kb > 0:
+                c = self.coef[kb]
+                out[b] = sum(c[j] * store[(n - kb - j, s)][b] for j in range(self.q))
+        return out, k
+
+    def operator_ldg(self, y: np.ndarray, n: int, s: int) -> np.ndarray:
+        """u_t + (u^2/2 - nu q)_x = 0 with q = u_x, local DG with alternating
+        fluxes (u-hat = u from the left, q-hat = q from the right) and the LLF
+        flux for u^2/2.  Per element, with D = M^-1 S and the lifts l_l, l_r:
+          q = (2/dx) ( -D u + l_r u-hat_right - l_l u-hat_left ),
+          du/dt = (2/dx) ( D g + l_l G_left - l_r G_right ),  g = u^2/2 - nu q,
+          G = fhat_LLF(u-, u+) - nu q+.
+        At PE faces both face values (u-hat and G) use the delayed AT
+        combination, with one delay per face per (step[, stage])."""
+        nu = self.w.viscosity
+        uhat = np.roll(y[:, -1], 1)          # face e: the right trace of element e-1
+        asyn = self.scheme != "dg" and self.n_pe > 1
+        fb = self.faces
+        if asyn:
+            uhat[fb], k = self._at_face_values(self.hist_u, uhat[fb], n, s)
+            if self.record:
+                self.delay_log[(n, s)] = k.copy()
+        rq = -(y @ self.stiff.T) + np.outer(np.roll(uhat, -1), self.phi_p1) - np.outer(uhat, self.phi_m1)
+        q = (2.0 / self.dx) * np.linalg.solve(self.mass, rq.T).T
+        um = np.roll(y[:, -1], 1)
+        G = self.fhat(um, y[:, 0]) - nu * q[:, 0]
+        if asyn:
+            G[fb], _ = self._at_face_values(self.hist_g, G[fb], n, s)
+        g = 0.5 * y * y - nu * q
+        r = g @ self.stiff.T + np.outer(G, self.phi_m1) - np.outer(np.roll(G, -1), self.phi_p1)
+        return (2.0 / self.dx) * np.linalg.solve(self.mass, r.T).T
+
     # ---- one operator evaluation -------------------------------------------
     def operator(self, y: np.ndarray, n: int, s: int) -> np.ndarray:
+        if self.w.equation == "viscous_burgers":
+            return self.operator_ldg(y, n, s)
         um = np.roll(y[:, -1], 1)
         up = y[:, 0].copy()
         f = self.fhat(um, up)

@@ -38,7 +38,7 @@ class Workload:
     n_elem = N_E, degree = N_p, pe_size = N_E / P, probs = {p_k} (L = len),
     speed = a, dt = Delta t."""
     name: str
-    equation: str = "advection"      # "advection" | "burgers"
+    equation: str = "advection"      # "advection" | "burgers" | "viscous_burgers"
     scheme: str = "adg_at"           # "dg" | "adg" | "adg_at"
     flux: str = "upwind"             # "upwind" | "central" | "llf"
     rk: str = "rk4"                  # "heun" | "ssprk3" | "rk4"
@@ -53,6 +53,7 @@ class Workload:
     x_left: float = 0.0
     length: float = TWO_PI
     speed: float = 1.0
+    viscosity: float = 0.0           # nu of the viscous Burgers equation
     dt: float = 0.0
     n_steps: int = 0
     ic: MultiSine = field(default_factory=lambda: MultiSine((1,), (1.0,), (0.0,)))

@@ -260,3 +260,53 @@ def test_burgers_pre_shock_exact_solution():
     adg = _run_error(replace(w, scheme="adg"))
     assert at[2] < 1e-12 and adg[2] < 1e-12
     assert at[0] < 1.1 * dg[0] and adg[0] > 1.5 * dg[0]
+
+
+# ---- viscous Burgers, local DG (Sec. 6.1, Fig. 11) -------------------------
+def _ldg(**kw):
+    base = dict(name="ldg", equation="viscous_burgers", flux="llf", rk="heun", degree=2, n_elem=32, pe_size=8,
+                probs=("0.3", "0.4", "0.3"), scheme="dg", viscosity=0.1, dt=1e-3, n_steps=10,
+                ic=W.PAPER_MULTISINE)
+    base.update(kw)
+    return W.Workload(**base)
+
+
+def test_ldg_without_viscosity_is_the_dg_burgers_operator():
+    y = np.random.default_rng(2).standard_normal((32, 3))
+    for scheme in ("dg", "adg_at"):
+        a = stepper.Stepper(_ldg(viscosity=0.0, scheme=scheme, at_levels=2 if scheme == "adg_at" else 0))
+        b = stepper.Stepper(_ldg(equation="burgers", viscosity=0.0, scheme=scheme,
+                                 at_levels=2 if scheme == "adg_at" else 0))
+        for n in range(5):  # builds up delayed history on both
+            np.testing.assert_allclose(a.operator(y + 0.01 * n, n, 0), b.operator(y + 0.01 * n, n, 0),
+                                       rtol=0, atol=1e-12)
+
+
+def _heat_error(p, ne, scheme, eps=1e-6, nu=0.1, t_final=0.05):
+    """Small-amplitude data: the nonlinear term is O(eps^2), so the solution
+    is the heat equation's, each mode decaying as exp(-nu kappa^2 t)."""
+    ic = W.MultiSine((2, 3), (2.0 * eps, 1.0 * eps), (0.3, 1.1))
+    dx = W.TWO_PI / ne
+    # dt = 0.002 dx^2 / nu: the AT extrapolation of the stiff diffusive face
+    # values needs a smaller step than the synchronous scheme
+    dt, n = W.time_step(W.TWO_PI, ne, 0.002 * dx / nu, 1.0, t_final)
+    w = _ldg(degree=p, n_elem=ne, pe_size=ne // 4, scheme=scheme, at_levels=2 if scheme == "adg_at" else 0,
+             rk="rk4", viscosity=nu, dt=dt, n_steps=n, ic=ic)
+    st = stepper.Stepper(w)
+    u0 = stepper.initial_state(w)
+    i0 = st.integral(u0)
+    u = st.run(u0, n)
+    x = basis.element_nodes(w.x_left, w.length, ne, p)
+    ue = sum(a * np.exp(-nu * k * k * t_final) * np.sin(k * x + ph) for k, a, ph in zip(ic.kappa, ic.amp, ic.phase))
+    return stats.mean_abs(u, ue) / eps, abs(st.integral(u) - i0) / eps, u
+
+
+@pytest.mark.parametrize("p", [1, 2])
+def test_ldg_diffusion_converges_at_order_p_plus_1(p):
+    errs = [_heat_error(p, ne, "dg")[0] for ne in (16, 32, 64)]
+    slopes = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(slopes > p - 0.7) and slopes[-1] > p + 1 - 0.15, slopes  # alternating fluxes: optimal order
+    at = [_heat_error(p, ne, "adg_at") for ne in (16, 32, 64)]
+    slopes = np.log2(np.array([e[0] for e in at[:-1]]) / np.array([e[0] for e in at[1:]]))
+    assert np.all(slopes > p - 0.7) and slopes[-1] > p + 1 - 0.15, slopes  # AT2 at both face values
+    assert max(e[1] for e in at) < 1e-10            # one value per face: conservative
