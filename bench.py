@@ -192,6 +192,7 @@ def bench_experiments():
     f10a = X.error_vs_delay("at2", n_elem=512, delay_counts=(1, 2, 3, 4, 5))
     f10b = X.error_vs_delay("at4", n_elem=128, delay_counts=(1, 2, 3, 4))
     caa = X.error_caa("at2")
+    vb = X.viscous_burgers_convergence()
     def slim(r):
         return {k: r[k] for k in ("n_elem", "n_pe", "delay_counts", "mean", "delay_moment", "stable", "fit")}
     return {"wall_s": time.perf_counter() - t0, "n_real": f9a["n_real"],
@@ -201,7 +202,34 @@ def bench_experiments():
             "fig9_at4": {"order_in_n_elem": f9b["order_in_n_elem"], "order_dg": f9b["order_in_n_elem_dg"],
                          "inset_n_elem": f9b["inset"]["n_elem"], "inset_excess_over_dg": f9b["inset"]["excess_over_dg"]},
             "fig10_at2": slim(f10a), "fig10_at4": slim(f10b),
-            "caa_at2": {k: caa[k] for k in ("n_elems", "order_caa", "order_dg", "ratio_to_dg")}}
+            "caa_at2": {k: caa[k] for k in ("n_elems", "order_caa", "order_dg", "ratio_to_dg")},
+            "fig11_viscous_burgers": {k: vb[k] for k in ("n_elems", "n_ref", "t_final", "dg", "adg_at",
+                                                           "order_dg", "order_adg_at")}}
+
+
+# Local DG per-stage kernels, Heun: q pass reads Y and writes q (16 B/DOF);
+# the flux pass reads Y and q (16 B) and the Heun registers (stage 0 writes A
+# and Y, stage 1 reads U and A and writes U: 20 B on average).
+BYTES_PER_DOF_STAGE_LDG_HEUN = 52.0
+
+
+def bench_viscous_burgers(torch, W, Solver, n_elem: int = 1 << 20, steps: int = 200):
+    """Throughput of ALDG(2)-AT2-RK2 (viscous Burgers, P = n_elem / 256) on
+    the per-stage kernels."""
+    w = W.viscous_burgers_workload(n_elem, "adg_at", 2, t_final=1e-3)
+    from dataclasses import replace
+    w = replace(w, pe_size=256)
+    s = Solver(w)
+    u = s.initial_state()
+    g, _ = time_solver(torch, s, u, steps, 20)
+    dofs = w.n_elem * (w.degree + 1)
+    rate = dofs * 2 * steps / g
+    out = {"workload": f"viscous Burgers ALDG(2)-AT2-RK2, N_E={n_elem}, PE size 256, nu={w.viscosity}",
+           "dof_stage_per_s": rate, "us_per_step": g / steps * 1e6,
+           "hbm_frac_at_52B_per_dof_stage": rate * BYTES_PER_DOF_STAGE_LDG_HEUN / 1e9 / HBM_PEAK_GBS,
+           "state_finite": bool(torch.isfinite(u).all().item())}
+    s.close()
+    return out
 
 
 def bench_ensemble(torch, W, Solver, n_steps: int, n_real: int, plain: bool):
@@ -391,6 +419,7 @@ def main():
                                          not args.no_plain)
     if not args.no_experiments:
         out["experiments"] = bench_experiments()
+        out["viscous_burgers"] = bench_viscous_burgers(torch, W, Solver)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
         out["cpu_baseline"]["host"] = {"cpu_count": os.cpu_count()}

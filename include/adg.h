@@ -5,7 +5,10 @@
  * Method: Goswami & Aditya, "An asynchronous discontinuous Galerkin method
  * for massively parallel PDE solvers", arXiv 2404.03399.
  *   - u_t + f(u)_x = 0 on a periodic interval (Sec. 2, model problem);
- *     f = a u (linear advection) or f = u^2/2 (inviscid Burgers).
+ *     f = a u (linear advection) or f = u^2/2 (inviscid Burgers); and the
+ *     viscous Burgers equation u_t + (u^2/2)_x = nu u_xx of Sec. 6 in local
+ *     DG form (q = u_x; alternating fluxes: u-hat from the left element, q-hat
+ *     from the right; LLF for u^2/2; AT at PE faces on both face values).
  *   - N_E uniform elements, nodal Lagrange basis of degree N_p on
  *     Gauss-Lobatto-Legendre nodes, exact mass matrix (Sec. 2, element-wise
  *     weak form and reference matrices).
@@ -50,7 +53,7 @@
 extern "C" {
 #endif
 
-#define ADG_ABI_VERSION 1
+#define ADG_ABI_VERSION 2
 
 enum adg_status {
   ADG_OK = 0,
@@ -63,7 +66,9 @@ enum adg_status {
   ADG_E_UNSUPPORTED = -7   /* valid request not implemented by this build       */
 };
 
-enum adg_equation { ADG_EQ_ADVECTION = 0, ADG_EQ_BURGERS = 1 };
+/* VISCOUS_BURGERS runs on the per-stage kernels only (ADG_KERNEL_AUTO picks
+ * them; ADG_KERNEL_FUSED and adjoint recording return ADG_E_UNSUPPORTED). */
+enum adg_equation { ADG_EQ_ADVECTION = 0, ADG_EQ_BURGERS = 1, ADG_EQ_VISCOUS_BURGERS = 2 };
 enum adg_scheme { ADG_SCHEME_DG = 0, ADG_SCHEME_ADG = 1, ADG_SCHEME_ADG_AT = 2 };
 /* upwind / central: f^ = a (B+ u- + B- u+) (Sec. 2);  llf: local Lax-Friedrichs
  * 1/2 (f(u-) + f(u+)) - lambda/2 (u+ - u-), lambda = max(|u-|, |u+|) (Sec. 6.1). */
@@ -92,7 +97,7 @@ typedef struct adg_problem {
   uint32_t abi_version;        /* = ADG_ABI_VERSION */
   uint32_t equation;           /* adg_equation */
   uint32_t scheme;             /* adg_scheme */
-  uint32_t flux;               /* adg_flux: upwind/central need advection, llf needs Burgers */
+  uint32_t flux;               /* adg_flux: upwind/central need advection, llf needs (viscous) Burgers */
   uint32_t rk;                 /* adg_rk */
   uint32_t degree;             /* N_p in 1..4 */
   uint32_t at_levels;          /* q of the AT flux, 1..5; 0 -> degree + 1; must be 0 unless ADG-AT */
@@ -108,6 +113,7 @@ typedef struct adg_problem {
   double length;               /* interval length (> 0) */
   double speed;                /* advection speed a (advection only; != 0) */
   double dt;                   /* fixed time step (> 0) */
+  double viscosity;            /* nu >= 0 of the viscous Burgers equation; must be 0 otherwise */
 } adg_problem;
 
 typedef struct adg_options {

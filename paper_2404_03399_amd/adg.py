@@ -11,7 +11,7 @@ import os
 
 from . import build as _build
 
-ADG_ABI_VERSION = 1
+ADG_ABI_VERSION = 2
 
 ADG_OK = 0
 ADG_E_INVALID = -1
@@ -22,7 +22,7 @@ ADG_E_STATE = -5
 ADG_E_NONFINITE = -6
 ADG_E_UNSUPPORTED = -7
 
-EQUATION = {"advection": 0, "burgers": 1}
+EQUATION = {"advection": 0, "burgers": 1, "viscous_burgers": 2}
 SCHEME = {"dg": 0, "adg": 1, "adg_at": 2}
 FLUX = {"upwind": 0, "central": 1, "llf": 2}
 RK = {"heun": 0, "ssprk3": 1, "rk4": 2, "lsrk3": 3}
@@ -47,7 +47,7 @@ class adg_problem(C.Structure):
         ("at_levels", C.c_uint32), ("n_delays", C.c_uint32), ("delay_granularity", C.c_uint32),
         ("reserved", C.c_uint32), ("n_elem", C.c_int64), ("pe_size", C.c_int64),
         ("seed", C.c_uint64), ("delay_threshold", C.c_uint64 * 7), ("x_left", C.c_double),
-        ("length", C.c_double), ("speed", C.c_double), ("dt", C.c_double),
+        ("length", C.c_double), ("speed", C.c_double), ("dt", C.c_double), ("viscosity", C.c_double),
     ]
 
 

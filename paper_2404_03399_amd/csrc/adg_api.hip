@@ -155,6 +155,7 @@ double at_coefficient(int q, int k, int j) {
 
 int phys_of(const adg_problem& p) {
   if (p.equation == ADG_EQ_BURGERS) return PHYS_BURGERS_LLF;
+  if (p.equation == ADG_EQ_VISCOUS_BURGERS) return PHYS_BURGERS_LDG;
   return p.flux == ADG_FLUX_CENTRAL ? PHYS_ADV_CENTRAL : PHYS_ADV_UPWIND;
 }
 
@@ -170,7 +171,12 @@ bool async_of(const adg_problem& p) { return p.scheme != ADG_SCHEME_DG && p.n_el
 int validate_one(const adg_problem& p, int idx) {
   const std::string at = "problem " + std::to_string(idx) + ": ";
   if (p.abi_version != ADG_ABI_VERSION) return fail(ADG_E_ABI, at + "abi_version mismatch");
-  if (p.equation > ADG_EQ_BURGERS) return fail(ADG_E_INVALID, at + "unknown equation");
+  if (p.equation > ADG_EQ_VISCOUS_BURGERS) return fail(ADG_E_INVALID, at + "unknown equation");
+  if (p.equation == ADG_EQ_VISCOUS_BURGERS && (p.flux != ADG_FLUX_LLF || !(p.viscosity >= 0.0) ||
+                                               !std::isfinite(p.viscosity)))
+    return fail(ADG_E_INVALID, at + "viscous Burgers needs the llf flux and a finite viscosity >= 0");
+  if (p.equation != ADG_EQ_VISCOUS_BURGERS && p.viscosity != 0.0)
+    return fail(ADG_E_INVALID, at + "viscosity is only for viscous Burgers");
   if (p.scheme > ADG_SCHEME_ADG_AT) return fail(ADG_E_INVALID, at + "unknown scheme");
   if (p.flux > ADG_FLUX_LLF) return fail(ADG_E_INVALID, at + "unknown flux");
   if (p.rk > ADG_LSRK3) return fail(ADG_E_INVALID, at + "unknown rk");
@@ -219,7 +225,7 @@ int validate(const adg_problem* probs, int32_t n) {
 }
 
 struct Layout {
-  int64_t probs, work_f, work_f2, work_s, first_s, ctr, ring, atsum, atk, state2, y0, y1, acc, part, stats_out;
+  int64_t probs, work_f, work_f2, work_s, first_s, ctr, ring, atsum, atk, state2, y0, y1, acc, qbuf, part, stats_out;
   int64_t groups, gstats;  // ensemble statistics: group CSR (2n+1 int32) and 4 doubles per group
   // adjoint recording (-1 if not recording); ckrec holds the fused kernel's
   // PE-face records (AT sums, delays) at every checkpoint plus one spare slot
@@ -257,10 +263,15 @@ int fused_steps_of(const adg_options* opt) {
   return (req == 1 || req == 2) ? req : 0;
 }
 
-int kernel_of(const adg_options* opt) {
-  if (!opt || opt->kernel == ADG_KERNEL_AUTO) return ADG_KERNEL_FUSED;
+// Kernel family: AUTO picks the fused kernel, or the per-stage kernels for
+// viscous Burgers (local DG runs on those only).
+int kernel_of(const adg_problem* probs, const adg_options* opt) {
+  const bool ldg = probs[0].equation == ADG_EQ_VISCOUS_BURGERS;
+  if (!opt || opt->kernel == ADG_KERNEL_AUTO) return ldg ? ADG_KERNEL_STAGE : ADG_KERNEL_FUSED;
   return opt->kernel;
 }
+
+bool is_ldg(const adg_problem* probs) { return probs[0].equation == ADG_EQ_VISCOUS_BURGERS; }
 
 Layout make_layout(const adg_problem* probs, int32_t n, const adg_options* opt, int64_t n_rec) {
   Layout L{};
@@ -278,7 +289,8 @@ Layout make_layout(const adg_problem* probs, int32_t n, const adg_options* opt, 
     nws += (p.n_elem + kBlock - 1) / kBlock;
     tot += ld_of(p) * (p.degree + 1);
     if (async_of(p)) {
-      ring += (p.n_elem / p.pe_size) * S * depth_of(p, n_rec);
+      // local DG keeps a second ring of the same shape for u-hat
+      ring += (is_ldg(probs) ? 2 : 1) * (p.n_elem / p.pe_size) * S * depth_of(p, n_rec);
       at += kRecSlots * (p.n_elem / p.pe_size);
     }
   }
@@ -289,7 +301,7 @@ Layout make_layout(const adg_problem* probs, int32_t n, const adg_options* opt, 
   L.n_work_a = n_rec > 0 ? (int32_t)nwa : 0;
   L.total_doubles = tot;
   L.ring_doubles = ring;
-  const int kern = kernel_of(opt);
+  const int kern = kernel_of(probs, opt);
   int64_t off = 0;
   auto take = [&](int64_t bytes) { const int64_t o = off; off = align_up(off + bytes, kAlign); return o; };
   L.probs = take((int64_t)sizeof(DevProblem) * n);
@@ -306,6 +318,7 @@ Layout make_layout(const adg_problem* probs, int32_t n, const adg_options* opt, 
   L.y0 = kern == ADG_KERNEL_STAGE ? take(8 * tot) : -1;
   L.y1 = kern == ADG_KERNEL_STAGE ? take(8 * tot) : -1;
   L.acc = kern == ADG_KERNEL_STAGE ? take(8 * tot) : -1;
+  L.qbuf = is_ldg(probs) ? take(8 * tot) : -1;
   L.part = take(3 * 8 * nws);
   L.stats_out = take(3 * 8 * (int64_t)n);
   L.groups = take(4 * (2 * (int64_t)n + 1));
@@ -383,6 +396,7 @@ struct adg_ctx {
     for (int i = 0; i < 4; ++i) a.single[i] = single[K - 1][i];
     a.lane_elems = lane_elems;
     a.steps = K;
+    a.qbuf = L.qbuf >= 0 ? (double*)(ws + L.qbuf) : nullptr;
     return a;
   }
   StepArgs fused_args(int K = 1) const {
@@ -433,6 +447,7 @@ int enqueue_steps(adg_ctx* c, double** cur, double** other, int32_t step_offset,
     for (int s = 0; s < c->S; ++s) {
       const double* yin = s == 0 ? U : ((s & 1) ? Y0 : Y1);
       double* yout = (s & 1) ? Y1 : Y0;
+      if (c->phys == PHYS_BURGERS_LDG) ADG_HIP(launch_ldg_q(c->rk, s, a, yin, step_offset + k, st));
       ADG_HIP(launch_stage(c->rk, c->phys, s, a, yin, yout, U, A, step_offset + k, st));
     }
   return ADG_OK;
@@ -535,11 +550,15 @@ int adg_workspace_size(const adg_problem* probs, int32_t n_probs, const adg_opti
   if (!bytes_out) return fail(ADG_E_INVALID, "bytes_out is null");
   if (n_steps_record < 0 || n_steps_record > (1 << 28)) return fail(ADG_E_INVALID, "n_steps_record out of range");
   if (opt && opt->ckpt_every < 0) return fail(ADG_E_INVALID, "ckpt_every < 0");
-  const int k = kernel_of(opt);
+  const int k = kernel_of(probs, opt);
   if (k != ADG_KERNEL_FUSED && k != ADG_KERNEL_STAGE) return fail(ADG_E_INVALID, "unknown kernel family");
   if (lane_elems_of(probs, n_probs, opt) == 0)
     return fail(ADG_E_INVALID, "lane_elems must be 1, 2 or 4 and not exceed the PE size");
   if (fused_steps_of(opt) == 0) return fail(ADG_E_INVALID, "fused_steps must be 0, 1 or 2");
+  if (is_ldg(probs) && k == ADG_KERNEL_FUSED)
+    return fail(ADG_E_UNSUPPORTED, "viscous Burgers runs on the per-stage kernels only");
+  if (is_ldg(probs) && n_steps_record > 0)
+    return fail(ADG_E_UNSUPPORTED, "no adjoint for viscous Burgers (local DG)");
   *bytes_out = make_layout(probs, n_probs, opt, n_steps_record).total;
   return ADG_OK;
 }
@@ -557,7 +576,7 @@ int adg_init(adg_ctx** out, const adg_problem* probs, int32_t n_probs, const adg
   adg_ctx* c = new adg_ctx();
   c->probs.assign(probs, probs + n_probs);
   if (opt) c->opt = *opt;
-  c->kernel = kernel_of(opt);
+  c->kernel = kernel_of(probs, opt);
   c->rk = (int)probs[0].rk;
   c->phys = phys_of(probs[0]);
   c->fused_phys = c->phys;
@@ -604,7 +623,9 @@ int adg_init(adg_ctx** out, const adg_problem* probs, int32_t n_probs, const adg
     d.at_off = aoff * c->S;
     d.atk_off = aoff;
     if (d.async_faces) {
-      roff += d.n_pe * c->S * (int64_t)d.depth;
+      const int64_t one_ring = d.n_pe * c->S * (int64_t)d.depth;
+      d.ring2_off = roff + one_ring;
+      roff += (is_ldg(probs) ? 2 : 1) * one_ring;
       aoff += kRecSlots * d.n_pe;
     }
     d.seed = p.seed;
@@ -613,10 +634,14 @@ int adg_init(adg_ctx** out, const adg_problem* probs, int32_t n_probs, const adg
     d.two_over_dx = 2.0 / dx;
     d.half_dx = 0.5 * dx;
     d.speed = p.equation == ADG_EQ_ADVECTION ? p.speed : 1.0;
+    d.nu = p.viscosity;
     d.dt = p.dt;
     element_operators((int)p.degree, &d);
     {
-      const double fac = p.equation == ADG_EQ_ADVECTION ? p.speed : 0.5;
+      // Kd folds the flux constant: a (advection), 1/2 (Burgers: g = u^2), 1
+      // (local DG: g = u^2/2 - nu q is formed in the kernel)
+      const double fac = p.equation == ADG_EQ_ADVECTION ? p.speed
+                         : (p.equation == ADG_EQ_BURGERS ? 0.5 : 1.0);
       for (int i = 0; i < kMaxNp * kMaxNp; ++i) d.Kd[i] = d.two_over_dx * fac * d.D[i];
       for (int i = 0; i < kMaxNp; ++i) {
         d.Kl[i] = d.two_over_dx * d.lift_l[i];

@@ -14,7 +14,9 @@ constexpr int kRecSlots = 3;  // fused kernel PE-face record slots, indexed by s
 
 // PHYS_ADV_UPWIND_POS: upwind advection with a > 0 in the fused kernel, which
 // folds the right-face flux a u_p into the volume operator.
-enum Phys : int { PHYS_ADV_UPWIND = 0, PHYS_ADV_CENTRAL = 1, PHYS_BURGERS_LLF = 2, PHYS_ADV_UPWIND_POS = 3 };
+enum Phys : int {
+  PHYS_ADV_UPWIND = 0, PHYS_ADV_CENTRAL = 1, PHYS_BURGERS_LLF = 2, PHYS_ADV_UPWIND_POS = 3, PHYS_BURGERS_LDG = 4
+};
 enum Rk : int { RK_HEUN = 0, RK_SSP3 = 1, RK_RK4 = 2, RK_LS3 = 3 };
 enum Scheme : int { SCH_DG = 0, SCH_ADG = 1, SCH_AT = 2 };
 
@@ -55,6 +57,7 @@ struct DevProblem {
   int64_t ld;            // plane stride of the state
   int64_t u_off;         // offset of the problem in the state vector
   int64_t ring_off;      // offset of the problem's delay ring (doubles)
+  int64_t ring2_off;     // local DG: offset of the u-hat ring (same shape as the flux ring)
   int64_t at_off;        // offset of the problem's AT sums ([kRecSlots][P][S] doubles)
   int64_t atk_off;       // offset of the problem's delays ([kRecSlots][P] words, byte s = stage s)
   int32_t np;            // degree + 1
@@ -72,6 +75,7 @@ struct DevProblem {
   double speed;
   double dt;
   double half_dx;
+  double nu;             // viscosity (local DG)
   double D[kMaxNp * kMaxNp];   // M^-1 S, row major
   double lift_l[kMaxNp];       // M^-1 phi(-1)
   double lift_r[kMaxNp];       // M^-1 phi(+1)

@@ -44,6 +44,9 @@ struct Physics<PHYS_ADV_CENTRAL> {
 };
 
 template <>
+struct Physics<PHYS_BURGERS_LDG>;  // viscous Burgers: the inviscid part is Physics<PHYS_BURGERS_LLF>
+
+template <>
 struct Physics<PHYS_BURGERS_LLF> {
   __device__ static double f(double u, double) { return 0.5 * u * u; }
   __device__ static double fhat(double um, double up, double) {

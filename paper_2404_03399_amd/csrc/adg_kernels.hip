@@ -23,7 +23,8 @@ __global__ void k_advance(int64_t* __restrict__ ctr, int64_t n_steps) {
 template <int NP, int RK, int PHYS, int SI>
 __device__ __forceinline__ void stage_elem(const DevProblem& P, int tile, const double* __restrict__ yin,
                                            double* __restrict__ yout, double* __restrict__ U,
-                                           double* __restrict__ A, double* __restrict__ ring, int64_t n) {
+                                           double* __restrict__ A, double* __restrict__ ring, int64_t n,
+                                           const double* __restrict__ qb) {
   constexpr int S = rk_stages(RK);
   const int N = (int)P.n_elem;
   const int e = tile * kBlock + (int)threadIdx.x;
@@ -41,8 +42,20 @@ __device__ __forceinline__ void stage_elem(const DevProblem& P, int tile, const 
   for (int j = 0; j < NP; ++j) y[j] = yin[off + j * ld + e];
   const double um = yin[off + (NP - 1) * ld + em];
   const double upr = yin[off + e1];
-  double fl = Physics<PHYS>::fhat(um, y[0], a);
-  double fr = Physics<PHYS>::fhat(y[NP - 1], upr, a);
+  constexpr bool ldg = PHYS == PHYS_BURGERS_LDG;
+  constexpr int PF = ldg ? PHYS_BURGERS_LLF : PHYS;  // the inviscid face flux
+  double qv[NP];
+  double fl, fr;
+  if constexpr (ldg) {
+    // total flux G = fhat_LLF(u-, u+) - nu q+ (q-hat from the right element)
+#pragma unroll
+    for (int j = 0; j < NP; ++j) qv[j] = qb[off + j * ld + e];
+    fl = Physics<PF>::fhat(um, y[0], a) - P.nu * qv[0];
+    fr = Physics<PF>::fhat(y[NP - 1], upr, a) - P.nu * qb[off + e1];
+  } else {
+    fl = Physics<PF>::fhat(um, y[0], a);
+    fr = Physics<PF>::fhat(y[NP - 1], upr, a);
+  }
   if (P.async_faces) {
     const uint32_t pes = P.pe_div.d;
     const int slot_n = (int)(n % (int64_t)P.depth);
@@ -60,7 +73,21 @@ __device__ __forceinline__ void stage_elem(const DevProblem& P, int tile, const 
       if (kd > 0) fr = at_past_sum(P, r, kd, slot_n);
     }
   }
-  element_rhs<NP, PHYS>(Dm, ll, lr, P.two_over_dx, a, y, fl, fr, k);
+  if constexpr (ldg) {
+    // (2/dx)(D g + l_l G_left - l_r G_right), g = u^2/2 - nu q (Kd = (2/dx) D)
+    double g[NP];
+#pragma unroll
+    for (int j = 0; j < NP; ++j) g[j] = 0.5 * y[j] * y[j] - P.nu * qv[j];
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+      double v = P.Kl[i] * fl - P.Kr[i] * fr;
+#pragma unroll
+      for (int j = 0; j < NP; ++j) v += P.Kd[i * kMaxNp + j] * g[j];
+      k[i] = v;
+    }
+  } else {
+    element_rhs<NP, PF>(Dm, ll, lr, P.two_over_dx, a, y, fl, fr, k);
+  }
 
   double* __restrict__ Uo = U + off;
   double* __restrict__ Ao = A + off;
@@ -128,15 +155,76 @@ template <int RK, int PHYS, int SI>
 __global__ __launch_bounds__(kBlock) void k_stage(const DevProblem* __restrict__ probs,
                                                   const WorkItem* __restrict__ work, const double* yin,
                                                   double* yout, double* U, double* A, double* __restrict__ ring,
+                                                  const int64_t* __restrict__ ctr, int32_t step_offset,
+                                                  const double* __restrict__ qb) {
+  const WorkItem wi = work[blockIdx.x];
+  const DevProblem& P = probs[wi.prob];
+  const int64_t n = ctr[0] + step_offset;
+  switch (P.np) {
+    case 2: stage_elem<2, RK, PHYS, SI>(P, wi.tile, yin, yout, U, A, ring, n, qb); break;
+    case 3: stage_elem<3, RK, PHYS, SI>(P, wi.tile, yin, yout, U, A, ring, n, qb); break;
+    case 4: stage_elem<4, RK, PHYS, SI>(P, wi.tile, yin, yout, U, A, ring, n, qb); break;
+    default: stage_elem<5, RK, PHYS, SI>(P, wi.tile, yin, yout, U, A, ring, n, qb); break;
+  }
+}
+
+// Local DG, first pass: q = (2/dx)(-D u + l_r u-hat_right - l_l u-hat_left)
+// with u-hat from the left element (alternating flux).  At a PE face the
+// element right of it writes the raw level-n u-hat to the u-hat ring and
+// both neighbours take the AT combination of past levels when delayed.
+template <int NP, int RK, int SI>
+__device__ __forceinline__ void ldg_q_elem(const DevProblem& P, int tile, const double* __restrict__ yin,
+                                           double* __restrict__ qout, double* __restrict__ ring, int64_t n) {
+  constexpr int S = rk_stages(RK);
+  const int N = (int)P.n_elem;
+  const int e = tile * kBlock + (int)threadIdx.x;
+  if (e >= N) return;
+  const int64_t ld = P.ld, off = P.u_off;
+  const int em = e == 0 ? N - 1 : e - 1;
+  const int e1 = e + 1 == N ? 0 : e + 1;
+  double y[NP];
+#pragma unroll
+  for (int j = 0; j < NP; ++j) y[j] = yin[off + j * ld + e];
+  double hl = yin[off + (NP - 1) * ld + em];
+  double hr = y[NP - 1];
+  if (P.async_faces) {
+    const uint32_t pes = P.pe_div.d;
+    const int slot_n = (int)(n % (int64_t)P.depth);
+    const uint32_t bl = fast_div((uint32_t)e, P.pe_div);
+    if ((uint32_t)e == bl * pes) {
+      const int64_t rb = P.ring2_off + ((int64_t)bl * S + SI) * P.depth;
+      const int kd = pe_delay(P, n, SI, bl);
+      ring[rb + slot_n] = hl;
+      if (kd > 0) hl = at_past_sum(P, ring + rb, kd, slot_n);
+    }
+    const uint32_t br = fast_div((uint32_t)e1, P.pe_div);
+    if ((uint32_t)e1 == br * pes) {
+      const int kd = pe_delay(P, n, SI, br);
+      if (kd > 0) hr = at_past_sum(P, ring + P.ring2_off + ((int64_t)br * S + SI) * P.depth, kd, slot_n);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < NP; ++i) {
+    double v = P.Kr[i] * hr - P.Kl[i] * hl;
+#pragma unroll
+    for (int j = 0; j < NP; ++j) v -= P.Kd[i * kMaxNp + j] * y[j];
+    qout[off + i * ld + e] = v;
+  }
+}
+
+template <int RK, int SI>
+__global__ __launch_bounds__(kBlock) void k_ldg_q(const DevProblem* __restrict__ probs,
+                                                  const WorkItem* __restrict__ work, const double* __restrict__ yin,
+                                                  double* __restrict__ qout, double* __restrict__ ring,
                                                   const int64_t* __restrict__ ctr, int32_t step_offset) {
   const WorkItem wi = work[blockIdx.x];
   const DevProblem& P = probs[wi.prob];
   const int64_t n = ctr[0] + step_offset;
   switch (P.np) {
-    case 2: stage_elem<2, RK, PHYS, SI>(P, wi.tile, yin, yout, U, A, ring, n); break;
-    case 3: stage_elem<3, RK, PHYS, SI>(P, wi.tile, yin, yout, U, A, ring, n); break;
-    case 4: stage_elem<4, RK, PHYS, SI>(P, wi.tile, yin, yout, U, A, ring, n); break;
-    default: stage_elem<5, RK, PHYS, SI>(P, wi.tile, yin, yout, U, A, ring, n); break;
+    case 2: ldg_q_elem<2, RK, SI>(P, wi.tile, yin, qout, ring, n); break;
+    case 3: ldg_q_elem<3, RK, SI>(P, wi.tile, yin, qout, ring, n); break;
+    case 4: ldg_q_elem<4, RK, SI>(P, wi.tile, yin, qout, ring, n); break;
+    default: ldg_q_elem<5, RK, SI>(P, wi.tile, yin, qout, ring, n); break;
   }
 }
 
@@ -263,7 +351,35 @@ template <int RK, int PHYS, int SI>
 static void stage_go(const StepArgs& a, const double* yin, double* yout, double* U, double* A, int32_t off,
                      hipStream_t st) {
   hipLaunchKernelGGL((k_stage<RK, PHYS, SI>), dim3(a.n_work), dim3(kBlock), 0, st, a.probs, a.work, yin, yout, U, A,
-                     a.ring, a.ctr, off);
+                     a.ring, a.ctr, off, a.qbuf);
+}
+
+template <int RK>
+static void ldg_q_si(int si, const StepArgs& a, const double* yin, int32_t off, hipStream_t st) {
+  const dim3 g(a.n_work), b(kBlock);
+  switch (si) {
+    case 0: hipLaunchKernelGGL((k_ldg_q<RK, 0>), g, b, 0, st, a.probs, a.work, yin, a.qbuf, a.ring, a.ctr, off); break;
+    case 1: hipLaunchKernelGGL((k_ldg_q<RK, 1>), g, b, 0, st, a.probs, a.work, yin, a.qbuf, a.ring, a.ctr, off); break;
+    case 2:
+      if constexpr (rk_stages(RK) > 2)
+        hipLaunchKernelGGL((k_ldg_q<RK, 2>), g, b, 0, st, a.probs, a.work, yin, a.qbuf, a.ring, a.ctr, off);
+      break;
+    default:
+      if constexpr (rk_stages(RK) > 3)
+        hipLaunchKernelGGL((k_ldg_q<RK, 3>), g, b, 0, st, a.probs, a.work, yin, a.qbuf, a.ring, a.ctr, off);
+      break;
+  }
+}
+
+hipError_t launch_ldg_q(int rk, int stage, const StepArgs& a, const double* yin, int32_t step_offset,
+                        hipStream_t stream) {
+  switch (rk) {
+    case RK_HEUN: ldg_q_si<RK_HEUN>(stage, a, yin, step_offset, stream); break;
+    case RK_SSP3: ldg_q_si<RK_SSP3>(stage, a, yin, step_offset, stream); break;
+    case RK_LS3: ldg_q_si<RK_LS3>(stage, a, yin, step_offset, stream); break;
+    default: ldg_q_si<RK_RK4>(stage, a, yin, step_offset, stream); break;
+  }
+  return hipGetLastError();
 }
 
 template <int RK, int PHYS>
@@ -283,6 +399,7 @@ static void stage_phys(int phys, int si, const StepArgs& a, const double* yin, d
   switch (phys) {
     case PHYS_ADV_UPWIND: stage_si<RK, PHYS_ADV_UPWIND>(si, a, yin, yout, U, A, off, st); break;
     case PHYS_ADV_CENTRAL: stage_si<RK, PHYS_ADV_CENTRAL>(si, a, yin, yout, U, A, off, st); break;
+    case PHYS_BURGERS_LDG: stage_si<RK, PHYS_BURGERS_LDG>(si, a, yin, yout, U, A, off, st); break;
     default: stage_si<RK, PHYS_BURGERS_LLF>(si, a, yin, yout, U, A, off, st); break;
   }
 }

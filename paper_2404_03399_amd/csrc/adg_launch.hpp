@@ -18,6 +18,7 @@ struct StepArgs {
   int32_t single[4];         // fused kernel: the only problem of a degree range, or -1
   int32_t lane_elems;        // fused kernel: elements per lane (1, 2 or 4)
   int32_t steps;             // fused kernel: time steps per launch (1 or 2)
+  double* qbuf;              // local DG: q = u_x of the current stage input (state layout)
 };
 
 // Work items of the fused kernel are sorted by descending np; items with
@@ -48,6 +49,12 @@ hipError_t launch_fused_rk(int phys, const StepArgs& a, const double* uin, doubl
 // the last stage writes U in place.  yin/yout alternate between two buffers.
 hipError_t launch_stage(int rk, int phys, int stage, const StepArgs& a, const double* yin, double* yout,
                         double* U, double* A, int32_t step_offset, hipStream_t stream);
+
+// Local DG, first pass of stage `stage`: q = u_x of the stage input yin into
+// a.qbuf, with the u-hat face values (AT-combined at PE faces, level-n raw
+// values written to the u-hat ring).
+hipError_t launch_ldg_q(int rk, int stage, const StepArgs& a, const double* yin, int32_t step_offset,
+                        hipStream_t stream);
 
 // Reverse of RK stage `stage` of step n (absolute index) for all problems:
 // lamu += mu, Q_i += a_{stage,i} mu, adjoint-ring deposits for delayed AT

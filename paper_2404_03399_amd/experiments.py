@@ -16,6 +16,8 @@ initial data:
   11E[k^2] + 6E[k] for q = 4).
 * `error_caa`: the deterministic communication-avoiding cycle of Sec. 7
   against synchronous DG over the mesh.
+* `viscous_burgers_convergence`: LDG(2)-RK2 and ALDG(2)-AT2-RK2 for the
+  viscous Burgers equation (Fig. 11) against a finer synchronous run.
 
 Every realization of one mesh runs in one batched context (one launch per
 step for all of them); the statistics come from adg_ensemble_stats.  The
@@ -163,12 +165,73 @@ def error_caa(scheme_key: str = "at2", n_elems=(64, 128, 256, 512, 1024), n_pe: 
             "ratio_to_dg": [a / d for a, d in zip(at, dg)]}
 
 
+def _eval_on(nodes_ref: "np.ndarray", u_ref, n_ref: int, x, length: float = W.TWO_PI):
+    """Evaluate the reference DG solution (n_ref elements, Lagrange basis on
+    the nodes nodes_ref in [-1, 1]) at the points x (barycentric form)."""
+    import numpy as np
+    dxr = length / n_ref
+    e = np.minimum((x // dxr).astype(np.int64), n_ref - 1)
+    xi = 2.0 * (x - e * dxr) / dxr - 1.0
+    m = len(nodes_ref)
+    w = np.array([1.0 / np.prod([nodes_ref[j] - nodes_ref[k] for k in range(m) if k != j]) for j in range(m)])
+    diff = xi[..., None] - nodes_ref
+    exact = np.isclose(diff, 0.0, atol=1e-15)
+    diff = np.where(exact, 1.0, diff)
+    terms = w / diff
+    vals = u_ref[e]                      # (..., m) nodal values of the containing element
+    out = (terms * vals).sum(-1) / terms.sum(-1)
+    hit = exact.any(-1)
+    if hit.any():
+        out[hit] = (vals * exact)[hit].sum(-1)
+    return out
+
+
+def viscous_burgers_convergence(n_elems=(16, 32, 64), ref_factor: int = 8, t_final: float = 0.1,
+                                degree: int = 2) -> dict:
+    """Fig. 11(b): <E> of LDG(2)-RK2 and ALDG(2)-AT2-RK2 against a synchronous
+    LDG run on a mesh ref_factor times finer than the finest (same scheme and
+    Courant number), evaluated at the coarse nodes."""
+    import numpy as np
+    from . import adg
+    from .solver import Solver
+
+    def run(w):
+        s = Solver(w)
+        try:
+            u = s.initial_state()
+            s.run(u, w.n_steps, graph=True)
+            return s.unpack(u)[0]
+        finally:
+            s.close()
+
+    n_ref = ref_factor * max(n_elems)
+    wr = W.viscous_burgers_workload(n_ref, "dg", degree, t_final=t_final)
+    u_ref = run(wr)
+    xi = np.array(adg.adg_nodes(degree))
+    out = {"n_elems": list(n_elems), "n_ref": n_ref, "t_final": t_final, "degree": degree,
+           "nu": wr.viscosity, "sigma": 0.0005}
+    for scheme in ("dg", "adg_at"):
+        errs = []
+        for ne in n_elems:
+            w = W.viscous_burgers_workload(ne, scheme, degree, t_final=t_final)
+            if abs(w.dt * w.n_steps - wr.dt * wr.n_steps) > 1e-12:
+                raise ValueError("reference and run end at different times")
+            u = run(w)
+            dx = W.TWO_PI / ne
+            x = np.arange(ne)[:, None] * dx + (xi[None, :] + 1.0) * dx / 2.0
+            errs.append(float(np.mean(np.abs(u - _eval_on(xi, u_ref, n_ref, x)))))
+        out[scheme] = errs
+        out["order_" + scheme] = loglog_slope(n_elems, errs)
+    return out
+
+
 def main(argv=None) -> int:
     t0 = time.perf_counter()
     out = {"error_vs_pe": [error_vs_pe("at2", n_elems=(64, 128, 256, 512, 1024)),
                            error_vs_pe("at4", n_elems=(64, 128, 256, 512))],
            "error_vs_delay": [error_vs_delay("at2", n_elem=512), error_vs_delay("at4", n_elem=128)],
-           "communication_avoiding": [error_caa("at2"), error_caa("at4", n_elems=(64, 128, 256, 512))]}
+           "communication_avoiding": [error_caa("at2"), error_caa("at4", n_elems=(64, 128, 256, 512))],
+           "viscous_burgers": viscous_burgers_convergence()}
     out["wall_s"] = time.perf_counter() - t0
     print(json.dumps(out))
     return 0

@@ -51,6 +51,7 @@ def to_problem(w) -> adg.adg_problem:
     p.length = w.length
     p.speed = w.speed
     p.dt = w.dt
+    p.viscosity = getattr(w, "viscosity", 0.0)
     return p
 
 
@@ -62,7 +63,7 @@ def _stream_handle(stream) -> int:
 class Solver:
     """One context over one or more problems (batched when more than one)."""
 
-    def __init__(self, workloads, kernel: str = "fused", n_steps_record: int = 0, ckpt_every: int = 0,
+    def __init__(self, workloads, kernel: str = "auto", n_steps_record: int = 0, ckpt_every: int = 0,
                  device: str = "cuda", stream=None, lane_elems=0, fused_steps: int = 0):
         if not isinstance(workloads, (list, tuple)):
             workloads = [workloads]
@@ -75,7 +76,8 @@ class Solver:
         if lane_elems == "auto":
             # elements per lane and (unless given) steps per launch, tuned together
             from . import autotune
-            lane_elems, k = autotune.tune(self.workloads) if kernel == "fused" else (0, 0)
+            fused = kernel == "fused" or (kernel == "auto" and self.workloads[0].equation != "viscous_burgers")
+            lane_elems, k = autotune.tune(self.workloads) if fused else (0, 0)
             fused_steps = fused_steps or k
         self.opt.lane_elems = int(lane_elems)
         self.opt.fused_steps = int(fused_steps)

@@ -214,6 +214,22 @@ def error_vs_delay_workloads(scheme_key: str, n_elem: int, n_pe: int, delay_coun
     return out, group
 
 
+# Viscous Burgers runs (Fig. 11): kappa = {2,3,5}, A = {3,2,1}, nu = 0.1,
+# sigma = 0.0005, P = 4, L = 3 with p = (0.3, 0.4, 0.3), LDG(2) with RK2 and
+# AT2 at the PE faces.  dt = sigma dx / a_max with a_max = sum |A| = 6.
+VISCOUS_IC = MultiSine((2, 3, 5), (3.0, 2.0, 1.0), (0.3, 1.1, 2.0))
+
+
+def viscous_burgers_workload(n_elem: int, scheme: str = "adg_at", degree: int = 2, nu: float = 0.1,
+                             sigma: float = 0.0005, n_pe: int = 4, t_final: float = 0.1, seed: int = 0,
+                             rk: str = "heun") -> Workload:
+    dt, n = time_step(TWO_PI, n_elem, sigma, float(sum(abs(a) for a in VISCOUS_IC.amp)), t_final)
+    return Workload(name=f"vburgers_{scheme}_{n_elem}", equation="viscous_burgers", flux="llf", rk=rk,
+                    scheme=scheme, degree=degree, n_elem=n_elem, pe_size=n_elem // n_pe, probs=DELAYS_FIG9,
+                    seed=seed, per_stage=False, at_levels=2 if scheme == "adg_at" else 0, viscosity=nu,
+                    dt=dt, n_steps=n, ic=VISCOUS_IC)
+
+
 def random_coefficients(seed: int, shape) -> np.ndarray:
     """Generic N(0,1) FP64 array (cotangents, perturbation directions)."""
     return np.random.default_rng(seed).standard_normal(shape)

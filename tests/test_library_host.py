@@ -37,7 +37,7 @@ def test_exports_every_declared_symbol(L):
 
 
 def test_abi_version(L):
-    assert adg.adg_abi_version() == 1
+    assert adg.adg_abi_version() == 2
 
 
 @pytest.mark.parametrize("p", [1, 2, 3, 4])
@@ -46,7 +46,7 @@ def test_nodes_match_oracle(L, p):
 
 
 def test_struct_sizes(L):
-    assert ctypes.sizeof(adg.adg_problem) == 40 + 16 + 8 + 56 + 32
+    assert ctypes.sizeof(adg.adg_problem) == 40 + 16 + 8 + 56 + 40
     assert ctypes.sizeof(adg.adg_options) == 24
 
 
@@ -96,6 +96,27 @@ def test_caa_schedule_bit_exact_vs_oracle(L, rk, q):
     p = solver.to_problem(replace(w, probs=W.DELAYS_C2))
     with pytest.raises(adg.AdgError):
         adg.adg_workspace_size([p], adg.adg_options())
+
+
+def test_viscous_burgers_options(L):
+    w = W.Workload(name="ldg", equation="viscous_burgers", flux="llf", rk="heun", degree=2, n_elem=64,
+                   pe_size=16, probs=("0.3", "0.4", "0.3"), viscosity=0.1, dt=1e-4)
+    p = solver.to_problem(w)
+    assert adg.adg_workspace_size([p], adg.adg_options()) > 0          # AUTO -> per-stage kernels
+    opt = adg.adg_options()
+    opt.kernel = adg.KERNEL["fused"]
+    with pytest.raises(adg.AdgError) as ei:
+        adg.adg_workspace_size([p], opt)
+    assert ei.value.code == adg.ADG_E_UNSUPPORTED
+    with pytest.raises(adg.AdgError) as ei:
+        adg.adg_workspace_size([p], adg.adg_options(), 10)             # no adjoint for local DG
+    assert ei.value.code == adg.ADG_E_UNSUPPORTED
+    for bad in (dict(flux="central"), dict(viscosity=-1.0), dict(viscosity=float("nan"))):
+        with pytest.raises(adg.AdgError):
+            adg.adg_workspace_size([solver.to_problem(replace(w, **bad))], adg.adg_options())
+    with pytest.raises(adg.AdgError):   # viscosity only for viscous Burgers
+        adg.adg_workspace_size([solver.to_problem(replace(W.c1_advection_small(), viscosity=0.1))],
+                               adg.adg_options())
 
 
 def _bad(**kw):
