@@ -186,7 +186,7 @@ def _eval_on(nodes_ref: "np.ndarray", u_ref, n_ref: int, x, length: float = W.TW
     return out
 
 
-def viscous_burgers_convergence(n_elems=(16, 32, 64), ref_factor: int = 8, t_final: float = 0.1,
+def viscous_burgers_convergence(n_elems=(32, 64, 128), ref_factor: int = 8, t_final: float = 0.1,
                                 degree: int = 2) -> dict:
     """Fig. 11(b): <E> of LDG(2)-RK2 and ALDG(2)-AT2-RK2 against a synchronous
     LDG run on a mesh ref_factor times finer than the finest (same scheme and

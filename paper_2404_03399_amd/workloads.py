@@ -223,7 +223,12 @@ VISCOUS_IC = MultiSine((2, 3, 5), (3.0, 2.0, 1.0), (0.3, 1.1, 2.0))
 def viscous_burgers_workload(n_elem: int, scheme: str = "adg_at", degree: int = 2, nu: float = 0.1,
                              sigma: float = 0.0005, n_pe: int = 4, t_final: float = 0.1, seed: int = 0,
                              rk: str = "heun") -> Workload:
-    dt, n = time_step(TWO_PI, n_elem, sigma, float(sum(abs(a) for a in VISCOUS_IC.amp)), t_final)
+    """dt = sigma dx / a_max, capped by the explicit diffusive limit
+    0.002 dx^2 / nu on fine meshes (it binds only above ~1500 elements)."""
+    a_max = float(sum(abs(a) for a in VISCOUS_IC.amp))
+    dx = TWO_PI / n_elem
+    sig_eff = min(sigma, 0.002 * dx * a_max / nu) if nu > 0 else sigma
+    dt, n = time_step(TWO_PI, n_elem, sig_eff, a_max, t_final)
     return Workload(name=f"vburgers_{scheme}_{n_elem}", equation="viscous_burgers", flux="llf", rk=rk,
                     scheme=scheme, degree=degree, n_elem=n_elem, pe_size=n_elem // n_pe, probs=DELAYS_FIG9,
                     seed=seed, per_stage=False, at_levels=2 if scheme == "adg_at" else 0, viscosity=nu,

@@ -81,7 +81,7 @@ def test_viscous_burgers_convergence(torch_cuda):
     """Fig. 11(b): LDG(2)-RK2 and ALDG(2)-AT2-RK2 converge at third order
     (against a synchronous run on an 8x finer mesh) with nearly equal errors."""
     from paper_2404_03399_amd import experiments as X
-    _say("viscous Burgers convergence, N_E = 16, 32, 64, reference 512, T = 0.1")
+    _say("viscous Burgers convergence, N_E = 32, 64, 128, reference 1024, T = 0.1")
     r = X.viscous_burgers_convergence()
-    assert r["order_dg"] <= -2.6 and r["order_adg_at"] <= -2.6, r
+    assert r["order_dg"] <= -2.8 and r["order_adg_at"] <= -2.8, r
     assert all(a < 1.5 * d for a, d in zip(r["adg_at"], r["dg"])), r
