@@ -10,7 +10,7 @@ constexpr int kMaxNp = 5;     // degree <= 4
 constexpr int kMaxL = 8;      // delays 0..7
 constexpr int kMaxQ = 5;      // AT levels
 constexpr int kBlock = 256;   // threads per workgroup (4 wave64)
-constexpr int kRecSlots = 3;  // fused kernel PE-face record slots, indexed by step mod 3
+constexpr int kRecSlots = 4;  // fused kernel PE-face record slots, indexed by step mod 4
 
 // PHYS_ADV_UPWIND_POS: upwind advection with a > 0 in the fused kernel, which
 // folds the right-face flux a u_p into the volume operator.

@@ -64,10 +64,18 @@ __device__ __forceinline__ int ring_slot(int slot_n, int back, int depth) {
   return s < 0 ? s + depth : s;
 }
 
-// Clamped delay of boundary b at (step n, stage s).
+// Clamped delay of boundary b at (step n, stage s): the hash of
+// draw_delay with the threshold count unrolled over kMaxL - 1 (the threshold
+// loads issue together instead of one per loop trip).
 __device__ __forceinline__ int pe_delay(const DevProblem& P, int64_t n, int s, uint32_t b) {
-  const int key = P.per_stage ? s : 0;
-  const int k = P.caa ? caa_delay(n) : draw_delay(P.seed, n, key, (int64_t)b, P.thr, P.n_delays);
+  int k = 0;
+  if (P.caa) {
+    k = caa_delay(n);
+  } else {
+    const uint64_t u = splitmix64(delay_prefix(P.seed, n, P.per_stage ? s : 0) ^ (uint64_t)b) >> 11;
+#pragma unroll
+    for (int i = 0; i < kMaxL - 1; ++i) k += (i < P.n_delays - 1 && u >= P.thr[i]) ? 1 : 0;
+  }
   return clamp_delay(k, n, P.q);
 }
 
@@ -212,13 +220,17 @@ __device__ __forceinline__ double lane_from_right(double v) {
   return __hiloint2double(hi, lo);
 }
 
-// Per-lane PE-face values (written and read by the same lane only): the AT
-// flux of the current step per stage, and for a two-step launch the AT sums
-// of the second step.  With R <= PE size a lane's R left faces hold at most
-// one PE face.
+// Per-lane PE-face values.  at[kk][s][lane]: the AT sum of step n + kk
+// (read by the lane itself), then the raw level-(n + kk) flux of an owner
+// lane (read at the end by the lanes that form the next records).  With
+// R <= PE size a lane's R left faces hold at most one PE face.  part / kdj:
+// per record job (a lane of an owner wave), the sum over the levels before
+// the launch and the delay, formed at the start of the launch.
 template <int K>
 struct WaveSmemK {
   double at[K][kWavesPerBlock][kMaxStages][kWave];
+  double part[kWavesPerBlock][kWave];
+  int32_t kdj[kWavesPerBlock][kWave];
 };
 
 template <int NP, int PHYS>
@@ -243,20 +255,47 @@ struct FusedPtrs {
   int32_t* __restrict__ atk;
 };
 
+// Lane of the i-th set bit (from 0) of a wave-uniform mask, 0 if there is none.
+__device__ __forceinline__ int nth_set_lane(uint64_t mask, int i) {
+  int lane = 0;
+  for (int c = 0; mask != 0; ++c) {
+    const int bit = __builtin_ctzll(mask);
+    mask &= mask - 1;
+    if (c == i) lane = bit;
+  }
+  return lane;
+}
+
 // Record slot of step m (steps below 2^31).
 __device__ __forceinline__ int64_t rec_slot(int64_t m) { return (int64_t)((uint32_t)m % (uint32_t)kRecSlots); }
 
-// Partial AT sum of step m over the levels m - kd - j, j = q-1 down to jmin,
-// oldest first, one explicit FMA per level (the order and rounding every path
-// uses, so that a sum finished later with its newest level is bitwise the
-// one-pass sum whatever the compiler contracts elsewhere).  slot_prev = slot of level
-// m - 1, all levels read here are at most m - 1.
-__device__ __forceinline__ double at_sum_from(const DevProblem& P, const double* __restrict__ rb, int kd, int jmin,
-                                              int slot_prev, int depth) {
+// Part of the AT sum of step m (delay kd >= 1) over the levels m - kd - j
+// that precede step n, j = q-1 down to 0, oldest first, one explicit FMA per
+// level; rb is the ring of one (boundary, stage), slot_n = n mod depth.  The
+// loads are unrolled over kMaxQ and issue together.
+__device__ __forceinline__ double at_old_levels(const DevProblem& P, const double* __restrict__ rb, int64_t m,
+                                                int kd, int64_t n, int slot_n, int depth) {
+#pragma clang fp contract(off)
+  double c[kMaxQ], v[kMaxQ];
+  bool use[kMaxQ];
+#pragma unroll
+  for (int j = 0; j < kMaxQ; ++j) {
+    const int64_t back = n - (m - kd - j);  // level n - back
+    use[j] = kd > 0 && j < P.q && back >= 1;
+    c[j] = 0.0;
+    v[j] = 0.0;
+    if (use[j]) {
+      c[j] = P.atc[kd][j];
+      v[j] = rb[ring_slot(slot_n, (int)back, depth)];
+    }
+  }
   double acc = 0.0;
-  for (int j = P.q - 1; j >= jmin; --j) acc = fma(P.atc[kd][j], rb[ring_slot(slot_prev, kd + j - 1, depth)], acc);
+#pragma unroll
+  for (int j = kMaxQ - 1; j >= 0; --j)
+    if (use[j]) acc = fma(c[j], v[j], acc);
   return acc;
 }
+
 
 // --------------------------------------------------------------- adjoint ---
 // Butcher form of the three integrators (the same maps as the forward

@@ -20,15 +20,20 @@ namespace adg {
 // shift.  No workgroup barrier: the waves of a workgroup are independent.
 //
 // PE faces (Secs. 3-5): at step m the lane owning the element right of PE
-// face b writes the level-m flux of every stage into the ring.  The AT fluxes
-// of the launch's first step n come from the records (delays and AT sums of
-// past levels) written by the previous launch into slot n mod 3.  For K = 2
-// every lane with a PE face forms the second step's AT sums itself: the levels
-// up to n - 1 are in the ring before the launch, and level n is the raw flux
-// the lane has just computed (the owner's ring write of level n is not read in
-// this launch, so halo copies in other waves never race with it).  At the end
-// the owner computes the records of step n + K into slot (n + K) mod 3, which
-// no wave of this launch reads.  A delay of 0 selects the synchronous flux.
+// face b writes the level-m flux of every stage into the ring.  Before a
+// launch at step n the records hold, per face and stage, the delay and AT sum
+// of step n over its past levels and, for step n + 1, the delay and the part
+// of its AT sum over the levels up to n - 1; a two-step launch adds the
+// level-n term of step n + 1 itself (delay 1), from the raw flux the lane has
+// just computed.  So the PE faces of a launch read two records and nothing
+// else; no lane reads what another wave writes in the same launch.  The owner
+// wave writes the records of steps n + K and n + K + 1 (levels up to
+// n + K - 1) into slots that no wave of the launch reads (slot = step mod 4),
+// one lane per (face, step, stage): the delays and the sums over the levels
+// before n are formed at the start of the launch, where their ring loads
+// overlap the state loads, and the levels of the launch are added at the end
+// from the owner's raw fluxes kept on chip.  A delay of 0 selects the
+// synchronous flux.  AT sums add the oldest level first in every path.
 template <int NP, int RK, int PHYS, int R, int K>
 __device__ __forceinline__ void wave_tile(const DevProblem& P, const WorkItem wi, const FusedPtrs& A, int64_t n,
                                           const double* __restrict__ uin, double* __restrict__ uout,
@@ -75,7 +80,7 @@ __device__ __forceinline__ void wave_tile(const DevProblem& P, const WorkItem wi
       for (int j = 0; j < NP; ++j) u0[r][j] = u[j * ld + e[r]];
   }
 
-  // the PE face among this lane's left faces (if any) and its step-n record
+  // the PE face among this lane's left faces (if any) and its records
   bool pe[R];           // element r's left face is a PE face (at most one r)
   bool pe_right = false;  // the right face of element R-1 is a PE face
   bool any_pe = false;
@@ -101,26 +106,45 @@ __device__ __forceinline__ void wave_tile(const DevProblem& P, const WorkItem wi
     const uint32_t e1 = (e[R - 1] + 1 == N) ? 0u : (uint32_t)(e[R - 1] + 1);
     pe_right = e1 == fast_div(e1, P.pe_div) * pes;
     if (any_pe) {
-      const int64_t rs = rec_slot(n);
-      kp[0] = A.atk[P.atk_off + rs * P.n_pe + b];
-      const double* __restrict__ src = A.atsum + P.at_off + (rs * P.n_pe + b) * S;
 #pragma unroll
-      for (int s = 0; s < S; ++s) sm.at[0][wv][s][lane] = src[s];
+      for (int kk = 0; kk < K; ++kk) {
+        const int64_t rs = rec_slot(n + kk);
+        kp[kk] = A.atk[P.atk_off + rs * P.n_pe + b];
+        const double* __restrict__ src = A.atsum + P.at_off + (rs * P.n_pe + b) * S;
+#pragma unroll
+        for (int s = 0; s < S; ++s) sm.at[kk][wv][s][lane] = src[s];
+      }
       if constexpr (K == 2) {
-        // step n + 1: delays, and the AT sums over the levels up to n - 1
-        const int64_t n1 = n + 1;
-        const double* __restrict__ rb0 = A.ring + P.ring_off + (int64_t)b * S * depth;
+        if (n == 0) {  // no launch has written the records of step 1: its delays, no past levels
+          kp[1] = 0;
 #pragma unroll
-        for (int s = 0; s < S; ++s) {
-          const int kraw = P.caa ? caa_delay(n1)
-                                 : delay_from_prefix(delay_prefix(P.seed, n1, P.per_stage ? s : 0), b, P.thr,
-                                                     P.n_delays);
-          const int kd = clamp_delay(kraw, n1, P.q);
-          kp[1] |= kd << (8 * s);
-          // level n1 - kd - j <= n - 1 unless kd == 1 and j == 0 (level n, added in step n)
-          sm.at[1][wv][s][lane] = kd > 0 ? at_sum_from(P, rb0 + s * depth, kd, kd == 1 ? 1 : 0, slot_n, depth) : 0.0;
+          for (int s = 0; s < S; ++s) {
+            kp[1] |= pe_delay(P, 1, s, b) << (8 * s);
+            sm.at[1][wv][s][lane] = 0.0;
+          }
         }
       }
+    }
+  }
+
+  bool own_pe = false;  // this lane owns the element right of its PE face
+#pragma unroll
+  for (int r = 0; r < R; ++r) own_pe = own_pe || (pe[r] && owned[r]);
+  // record jobs of the owner wave: g = face * 2S + t * S + s for the t-th
+  // next record step n + K + t; one pass when they fit the wave
+  constexpr int NJ = 2 * S;
+  const uint64_t owners = __ballot(own_pe);
+  const int n_jobs = NJ * __builtin_popcountll(owners);
+  const bool one_pass = n_jobs <= kWave;
+  if (owners != 0 && one_pass) {  // uniform: every lane takes part in the lane shuffle
+    const int fi = lane / NJ, jj = lane - fi * NJ, t = jj / S, s = jj - t * S;
+    const uint32_t bo = (uint32_t)__shfl((int)b, nth_set_lane(owners, fi));
+    if (lane < n_jobs) {
+      const int64_t m = n + K + t;
+      const int kd = pe_delay(P, m, s, bo);
+      sm.kdj[wv][lane] = kd;
+      sm.part[wv][lane] =
+          at_old_levels(P, A.ring + P.ring_off + ((int64_t)bo * S + s) * depth, m, kd, n, slot_n, depth);
     }
   }
 
@@ -135,9 +159,6 @@ __device__ __forceinline__ void wave_tile(const DevProblem& P, const WorkItem wi
   // upwind, a > 0: the interior right-face flux a u_p is part of Kdu; only a
   // delayed PE face on the right adds -Kr (F_right - a u_p)
   const bool wave_pe_right = PHYS == PHYS_ADV_UPWIND_POS && __ballot(pe_right) != 0;
-  bool own_pe = false;  // this lane owns the element right of its PE face
-#pragma unroll
-  for (int r = 0; r < R; ++r) own_pe = own_pe || (pe[r] && owned[r]);
 
   int slot_m = slot_n;
 #pragma unroll
@@ -159,12 +180,14 @@ __device__ __forceinline__ void wave_tile(const DevProblem& P, const WorkItem wi
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         if (pe[r]) {
-          if (owned[r]) A.ring[P.ring_off + ((int64_t)b * S + s) * depth + slot_m] = F[r];
+          const double raw = F[r];
+          if (owned[r]) A.ring[P.ring_off + ((int64_t)b * S + s) * depth + slot_m] = raw;
           if constexpr (K == 2) {  // level n completes step n+1's sum when its delay is 1
             if (kk == 0 && ((kp[1] >> (8 * s)) & 0xff) == 1)
-              sm.at[1][wv][s][lane] = fma(P.atc[1][0], F[r], sm.at[1][wv][s][lane]);
+              sm.at[1][wv][s][lane] = fma(P.atc[1][0], raw, sm.at[1][wv][s][lane]);
           }
           if ((kp[kk] >> (8 * s)) & 0xff) F[r] = sm.at[kk][wv][s][lane];
+          sm.at[kk][wv][s][lane] = raw;  // level n + kk, for the records formed at the end
         }
       }
       if constexpr (PHYS == PHYS_ADV_UPWIND_POS) {
@@ -223,23 +246,32 @@ __device__ __forceinline__ void wave_tile(const DevProblem& P, const WorkItem wi
         for (int j = 0; j < NP; ++j) uo[j * ld + e[r]] = y[r][j];
   }
 
-  // owners of PE faces: records of step n+K, one lane per (face, stage).
-  // For each owned PE face of this wave (uniform loop over the owner mask),
-  // lanes 0..S-1 draw the stage's delay and sum the AT weights over the
-  // past levels (all written by the owner itself or by earlier launches).
-  uint64_t owners = __ballot(own_pe);
-  while (owners) {
-    const int src = __builtin_ctzll(owners);
-    owners &= owners - 1;
-    const uint32_t bo = (uint32_t)__builtin_amdgcn_readlane((int)b, src);
-    if (lane < S) {
-      const int s = lane;
-      const int64_t nk = n + K;
-      const uint64_t pre = delay_prefix(P.seed, nk, P.per_stage ? s : 0);
-      const int kd = clamp_delay(P.caa ? caa_delay(nk) : delay_from_prefix(pre, bo, P.thr, P.n_delays), nk, P.q);
-      const double* __restrict__ rb = A.ring + P.ring_off + ((int64_t)bo * S + s) * depth;
-      const double acc = kd > 0 ? at_sum_from(P, rb, kd, 0, slot_m, depth) : 0.0;  // slot_m: level nk - 1
-      const int64_t rs = rec_slot(nk);
+  // records of steps n + K and n + K + 1 over the levels up to n + K - 1:
+  // the part before n and the delay from the start of the launch (formed here
+  // when the jobs need more than one pass), the levels of the launch from the
+  // owners' raw fluxes
+  for (int g0 = 0; g0 < n_jobs; g0 += kWave) {
+    const int g = g0 + lane;
+    const int fi = g / NJ, jj = g - fi * NJ, t = jj / S, s = jj - t * S;
+    const int src = nth_set_lane(owners, fi);
+    const uint32_t bo = (uint32_t)__shfl((int)b, src);  // outside the branch: every lane active
+    if (g < n_jobs) {
+      const int64_t m = n + K + t;
+      int kd;
+      double acc;
+      if (one_pass) {
+        kd = sm.kdj[wv][lane];
+        acc = sm.part[wv][lane];
+      } else {
+        kd = pe_delay(P, m, s, bo);
+        acc = at_old_levels(P, A.ring + P.ring_off + ((int64_t)bo * S + s) * depth, m, kd, n, slot_n, depth);
+      }
+#pragma unroll
+      for (int j = kMaxQ - 1; j >= 0; --j) {
+        const int64_t rel = m - kd - j - n;  // level n + rel of this launch
+        if (kd > 0 && j < P.q && rel >= 0 && rel < K) acc = fma(P.atc[kd][j], sm.at[rel][wv][s][src], acc);
+      }
+      const int64_t rs = rec_slot(m);
       A.atsum[P.at_off + (rs * P.n_pe + bo) * S + s] = acc;
       reinterpret_cast<uint8_t*>(A.atk + P.atk_off + rs * P.n_pe + bo)[s] = (uint8_t)kd;
     }

@@ -11,8 +11,8 @@ struct StepArgs {
   int32_t n_work;
   double* ring;              // delay ring (fluxes), may be null when no PE faces
   int64_t* ctr;              // ctr[0] = steps completed by earlier batches, ctr[2] = non-finite flag
-  double* atsum;             // fused kernel: AT sums of past levels, [2][P][S] per problem
-  int32_t* atk;              // fused kernel: clamped delays, [2][P][S] per problem
+  double* atsum;             // fused kernel: AT sums of past levels, [kRecSlots][P][S] per problem
+  int32_t* atk;              // fused kernel: clamped delays, [kRecSlots][P] words per problem (byte s = stage s)
   int32_t group[5];          // fused kernel: work-item ranges per degree (below)
   int32_t grid[4];           // fused kernel: workgroups per degree range
   int32_t single[4];         // fused kernel: the only problem of a degree range, or -1
