@@ -57,7 +57,7 @@ def ring_bytes_per_step(w) -> float:
     if w.scheme == "dg" or w.n_pe <= 1:
         return 0.0
     q = (w.at_levels or w.degree + 1) if w.scheme == "adg_at" else 1
-    stages = {"rk4": 4, "ssprk3": 3, "heun": 2}[w.rk]
+    stages = {"rk4": 4, "ssprk3": 3, "heun": 2, "lsrk3": 3}[w.rk]
     return w.n_pe * stages * 8.0 * (1 + q)
 
 
@@ -215,20 +215,31 @@ BYTES_PER_DOF_STAGE_LDG_HEUN = 52.0
 
 def bench_viscous_burgers(torch, W, Solver, n_elem: int = 1 << 20, steps: int = 200):
     """Throughput of ALDG(2)-AT2-RK2 (viscous Burgers, P = n_elem / 256) on
-    the per-stage kernels."""
+    the fused local DG kernel (one step per launch: 16 B per DOF and step
+    plus the two PE-face rings) and on the per-stage kernels."""
     w = W.viscous_burgers_workload(n_elem, "adg_at", 2, t_final=1e-3)
     from dataclasses import replace
     w = replace(w, pe_size=256)
-    s = Solver(w)
-    u = s.initial_state()
-    g, _ = time_solver(torch, s, u, steps, 20)
     dofs = w.n_elem * (w.degree + 1)
-    rate = dofs * 2 * steps / g
-    out = {"workload": f"viscous Burgers ALDG(2)-AT2-RK2, N_E={n_elem}, PE size 256, nu={w.viscosity}",
-           "dof_stage_per_s": rate, "us_per_step": g / steps * 1e6,
-           "hbm_frac_at_52B_per_dof_stage": rate * BYTES_PER_DOF_STAGE_LDG_HEUN / 1e9 / HBM_PEAK_GBS,
-           "state_finite": bool(torch.isfinite(u).all().item())}
-    s.close()
+    out = {"workload": f"viscous Burgers ALDG(2)-AT2-RK2, N_E={n_elem}, PE size 256, nu={w.viscosity}"}
+    finite = True
+    for kernel in ("fused", "stage"):
+        s = Solver(w, kernel=kernel)
+        u = s.initial_state()
+        g, _ = time_solver(torch, s, u, steps, 20)
+        finite = finite and bool(torch.isfinite(u).all().item())
+        s.close()
+        rate = dofs * 2 * steps / g
+        if kernel == "fused":
+            step_bytes = BYTES_PER_DOF_STEP_FUSED * dofs + 2 * ring_bytes_per_step(w)
+            out.update({"dof_stage_per_s": rate, "us_per_step": g / steps * 1e6,
+                        "hbm_frac": step_bytes / (g / steps) / 1e9 / HBM_PEAK_GBS})
+        else:
+            out["stage_kernels"] = {"dof_stage_per_s": rate, "us_per_step": g / steps * 1e6,
+                                    "hbm_frac_at_52B_per_dof_stage":
+                                        rate * BYTES_PER_DOF_STAGE_LDG_HEUN / 1e9 / HBM_PEAK_GBS}
+    out["fused_over_stage"] = out["dof_stage_per_s"] / out["stage_kernels"]["dof_stage_per_s"]
+    out["state_finite"] = finite
     return out
 
 

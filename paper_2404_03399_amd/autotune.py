@@ -48,6 +48,8 @@ def admissible(workloads) -> List[int]:
 
 
 def configs(workloads) -> List[Tuple[int, int]]:
+    if workloads[0].equation == "viscous_burgers":  # the local DG kernel has one shape
+        return [(1, 1)]
     return [(r, k) for r in admissible(workloads) for k in STEPS_PER_LAUNCH]
 
 

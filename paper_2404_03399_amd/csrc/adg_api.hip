@@ -263,11 +263,9 @@ int fused_steps_of(const adg_options* opt) {
   return (req == 1 || req == 2) ? req : 0;
 }
 
-// Kernel family: AUTO picks the fused kernel, or the per-stage kernels for
-// viscous Burgers (local DG runs on those only).
-int kernel_of(const adg_problem* probs, const adg_options* opt) {
-  const bool ldg = probs[0].equation == ADG_EQ_VISCOUS_BURGERS;
-  if (!opt || opt->kernel == ADG_KERNEL_AUTO) return ldg ? ADG_KERNEL_STAGE : ADG_KERNEL_FUSED;
+// Kernel family: AUTO picks the fused kernel.
+int kernel_of(const adg_problem*, const adg_options* opt) {
+  if (!opt || opt->kernel == ADG_KERNEL_AUTO) return ADG_KERNEL_FUSED;
   return opt->kernel;
 }
 
@@ -318,7 +316,7 @@ Layout make_layout(const adg_problem* probs, int32_t n, const adg_options* opt, 
   L.y0 = kern == ADG_KERNEL_STAGE ? take(8 * tot) : -1;
   L.y1 = kern == ADG_KERNEL_STAGE ? take(8 * tot) : -1;
   L.acc = kern == ADG_KERNEL_STAGE ? take(8 * tot) : -1;
-  L.qbuf = is_ldg(probs) ? take(8 * tot) : -1;
+  L.qbuf = (is_ldg(probs) && kern == ADG_KERNEL_STAGE) ? take(8 * tot) : -1;  // the fused kernel keeps q on chip
   L.part = take(3 * 8 * nws);
   L.stats_out = take(3 * 8 * (int64_t)n);
   L.groups = take(4 * (2 * (int64_t)n + 1));
@@ -555,8 +553,8 @@ int adg_workspace_size(const adg_problem* probs, int32_t n_probs, const adg_opti
   if (lane_elems_of(probs, n_probs, opt) == 0)
     return fail(ADG_E_INVALID, "lane_elems must be 1, 2 or 4 and not exceed the PE size");
   if (fused_steps_of(opt) == 0) return fail(ADG_E_INVALID, "fused_steps must be 0, 1 or 2");
-  if (is_ldg(probs) && k == ADG_KERNEL_FUSED)
-    return fail(ADG_E_UNSUPPORTED, "viscous Burgers runs on the per-stage kernels only");
+  if (is_ldg(probs) && k == ADG_KERNEL_FUSED && opt && (opt->lane_elems > 1 || opt->fused_steps > 1))
+    return fail(ADG_E_UNSUPPORTED, "the fused local DG kernel runs one element per lane and one step per launch");
   if (is_ldg(probs) && n_steps_record > 0)
     return fail(ADG_E_UNSUPPORTED, "no adjoint for viscous Burgers (local DG)");
   *bytes_out = make_layout(probs, n_probs, opt, n_steps_record).total;
@@ -664,7 +662,7 @@ int adg_init(adg_ctx** out, const adg_problem* probs, int32_t n_probs, const adg
   for (int32_t i = 0; i < n_probs; ++i) order[i] = i;
   std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return probs[a].degree > probs[b].degree; });
   c->lane_elems = lane_elems_of(probs, n_probs, opt);
-  c->fused_steps = fused_steps_of(opt);
+  c->fused_steps = is_ldg(probs) ? 1 : fused_steps_of(opt);
   std::vector<WorkItem> wfk[2], ws_;
   std::vector<int32_t> first(n_probs + 1, 0);
   for (int K = 1; K <= 2; ++K) {

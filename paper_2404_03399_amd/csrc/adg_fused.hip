@@ -298,6 +298,179 @@ __global__ __launch_bounds__(kBlock) void k_fused_step(const DevProblem* __restr
   wave_tile<NP, RK, PHYS, R, K>(probs[wi.prob], wi, A, n, uin, uout, sm, wv, lane);
 }
 
+// Viscous Burgers in local DG form (Sec. 7), one time step per launch, one
+// element per lane, halo S lanes per side.  Per stage: u-hat at a face is the
+// trace of the element on its left (alternating flux); q = Kr u-hat_right -
+// Kl u-hat_left - Kd u; the total flux at a face is G = LLF(u-, u+) - nu q+
+// with q+ from the element on its right; the element update is
+// Kl G_left - Kr G_right + Kd (u^2/2 - nu q).  u-hat_left comes from the left
+// lane by a lane shift and u-hat_right is the lane's own trace, so q needs no
+// data from the right; G_right comes from the right lane.  Each stage then
+// depends on one lane to either side, as the inviscid update does.  At a PE
+// face the element right of it writes the raw level-n u-hat and G to their
+// rings; every lane holding the face as its left face takes the AT
+// combinations of past levels of both, and every lane holding it as its right
+// face the u-hat combination (all those levels were written by earlier
+// launches, so the combinations are formed at the start of the launch).
+template <int S>
+struct LdgSmem {
+  double atu[kWavesPerBlock][S][kWave];   // left face: u-hat
+  double atg[kWavesPerBlock][S][kWave];   // left face: G
+  double atur[kWavesPerBlock][S][kWave];  // right face: u-hat
+  uint8_t kl[kWavesPerBlock][S][kWave];   // delays of the left face
+  uint8_t kr[kWavesPerBlock][S][kWave];   // delays of the right face
+};
+
+template <int NP, int RK>
+__device__ __forceinline__ void wave_tile_ldg(const DevProblem& P, const WorkItem wi, double* __restrict__ ring,
+                                              int64_t n, const double* __restrict__ uin, double* __restrict__ uout,
+                                              LdgSmem<rk_stages(RK)>& sm, int wv, int lane) {
+#pragma clang fp contract(off)  // explicit FMAs only
+  constexpr int S = rk_stages(RK);
+  constexpr int HL = fused_halo(RK, 1, 1);
+  constexpr int T = fused_tile(RK, 1, 1);
+  const int N = (int)P.n_elem;
+  const int e0 = wi.tile * T;
+  const int teff = (N - e0) < T ? (N - e0) : T;
+  const int x = e0 - HL + lane;
+  const int e = N < kWave ? wrap_elem(x, N) : wrap_once(x, N);
+  const bool owned = lane >= HL && lane < kWave - HL && (x - e0) < teff;
+  const int64_t ld = P.ld;
+  const double* __restrict__ u = uin + P.u_off;
+  double u0[NP];
+#pragma unroll
+  for (int j = 0; j < NP; ++j) u0[j] = u[j * ld + e];
+
+  bool pe = false;    // the left face of this lane's element is a PE face
+  bool pe_r = false;  // the right face is a PE face
+  uint32_t b = 0, br = 0;
+  int depth = 1, slot_n = 0;
+  if (P.async_faces) {
+    depth = P.depth;
+    const uint32_t n32 = (uint32_t)n;  // step indices stay below 2^31
+    slot_n = (int)(n32 - fast_div(n32, P.depth_div) * (uint32_t)depth);
+    const uint32_t pes = P.pe_div.d;
+    b = fast_div((uint32_t)e, P.pe_div);
+    pe = (uint32_t)e == b * pes;
+    const uint32_t e1 = (e + 1 == N) ? 0u : (uint32_t)(e + 1);
+    br = fast_div(e1, P.pe_div);
+    pe_r = e1 == br * pes;
+  }
+  // The delays and AT sums of the launch, one job lane per (PE lane, stage,
+  // value): the left-face u-hat and G of each lane with a PE left face, the
+  // right-face u-hat of each lane with a PE right face.  Each job draws its
+  // delay and sums its past levels; the target lane reads both from LDS.
+  const uint64_t m_l = __ballot(pe), m_r = __ballot(pe_r);
+  const int n_l = 2 * S * __builtin_popcountll(m_l);
+  const int n_jobs = n_l + S * __builtin_popcountll(m_r);
+  for (int g0 = 0; g0 < n_jobs; g0 += kWave) {  // uniform
+    const int g = g0 + lane;
+    const bool left = g < n_l;
+    const int h = left ? g : g - n_l;
+    const int per = left ? 2 * S : S;
+    const int i = h / per, r = h - i * per;
+    const int v = left ? r / S : 2;  // 0: u-hat, 1: G (left face); 2: u-hat (right face)
+    const int s = r - (left ? v * S : 0);
+    const int tl = nth_set_lane(m_l, i), tr = nth_set_lane(m_r, i);
+    const uint32_t fl = (uint32_t)__shfl((int)b, tl), fr = (uint32_t)__shfl((int)br, tr);  // every lane active
+    if (g < n_jobs) {
+      const int tgt = left ? tl : tr;
+      const uint32_t face = left ? fl : fr;
+      const int kd = pe_delay(P, n, s, face);
+      const double* __restrict__ rb = ring + (v == 1 ? P.ring_off : P.ring2_off) + ((int64_t)face * S + s) * depth;
+      const double val = at_old_levels(P, rb, n, kd, n, slot_n, depth);
+      if (v == 0) {
+        sm.atu[wv][s][tgt] = val;
+        sm.kl[wv][s][tgt] = (uint8_t)kd;
+      } else if (v == 1) {
+        sm.atg[wv][s][tgt] = val;
+      } else {
+        sm.atur[wv][s][tgt] = val;
+        sm.kr[wv][s][tgt] = (uint8_t)kd;
+      }
+    }
+  }
+
+  double y[NP], ks[NP], k[NP], q[NP];
+#pragma unroll
+  for (int j = 0; j < NP; ++j) y[j] = u0[j];
+  const double nu = P.nu;
+  const double dt = P.dt;
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const bool delayed = pe && sm.kl[wv][s][lane] != 0;
+    const int64_t rs = ((int64_t)b * S + s) * depth + slot_n;
+    const double um = lane_from_left(y[NP - 1]);  // u- at the left face, and its u-hat
+    double hl = um;
+    if (pe) {
+      if (owned) ring[P.ring2_off + rs] = um;
+      if (delayed) hl = sm.atu[wv][s][lane];
+    }
+    double hr = y[NP - 1];  // u-hat at the right face: this element's own trace
+    if (pe_r && sm.kr[wv][s][lane] != 0) hr = sm.atur[wv][s][lane];
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+      double v = fma(-P.Kl[i], hl, P.Kr[i] * hr);
+#pragma unroll
+      for (int j = 0; j < NP; ++j) v = fma(-P.Kd[i * kMaxNp + j], y[j], v);
+      q[i] = v;
+    }
+    double G = fma(-nu, q[0], Physics<PHYS_BURGERS_LLF>::fhat(um, y[0], 1.0));
+    if (pe) {
+      if (owned) ring[P.ring_off + rs] = G;
+      if (delayed) G = sm.atg[wv][s][lane];
+    }
+    const double Gr = lane_from_right(G);
+    double g[NP];
+#pragma unroll
+    for (int j = 0; j < NP; ++j) g[j] = fma(0.5 * y[j], y[j], -nu * q[j]);
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+      double v = fma(-P.Kr[i], Gr, P.Kl[i] * G);
+#pragma unroll
+      for (int j = 0; j < NP; ++j) v = fma(P.Kd[i * kMaxNp + j], g[j], v);
+      k[i] = v;
+    }
+    rk_update<NP, RK>(s, dt, u0, y, ks, k);
+  }
+  if (owned) {
+    double* __restrict__ uo = uout + P.u_off;
+#pragma unroll
+    for (int j = 0; j < NP; ++j) uo[j * ld + e] = y[j];
+  }
+}
+
+template <int NP, int RK>
+__global__ __launch_bounds__(kBlock) void k_fused_ldg(const DevProblem* __restrict__ probs,
+                                                      const WorkItem* __restrict__ work,
+                                                      const int64_t* __restrict__ ctr, double* __restrict__ ring,
+                                                      int32_t w_begin, int32_t w_end, const double* __restrict__ uin,
+                                                      double* __restrict__ uout, int32_t step_offset,
+                                                      int32_t single_prob) {
+  __shared__ LdgSmem<rk_stages(RK)> sm;
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+  const int lane = (int)(threadIdx.x % kWave);
+  const int w = w_begin + xcd_block((int)blockIdx.x, (int)gridDim.x) * kWavesPerBlock + wv;
+  if (w >= w_end) return;  // whole wave
+  const int64_t n = ctr[0] + step_offset;
+  const WorkItem wi = single_prob >= 0 ? WorkItem{single_prob, w - w_begin} : work[w];
+  wave_tile_ldg<NP, RK>(probs[wi.prob], wi, ring, n, uin, uout, sm, wv, lane);
+}
+
+template <int NP, int RK>
+static void fused_ldg_go(const StepArgs& a, int gi, const double* uin, double* uout, int32_t off, hipStream_t st) {
+  hipLaunchKernelGGL((k_fused_ldg<NP, RK>), dim3(a.grid[gi]), dim3(kBlock), 0, st, a.probs, a.work, a.ctr, a.ring,
+                     a.group[gi], a.group[gi + 1], uin, uout, off, a.single[gi]);
+}
+
+template <int RK>
+static void fused_ldg_np(const StepArgs& a, const double* uin, double* uout, int32_t off, hipStream_t st) {
+  if (a.group[1] > a.group[0]) fused_ldg_go<5, RK>(a, 0, uin, uout, off, st);
+  if (a.group[2] > a.group[1]) fused_ldg_go<4, RK>(a, 1, uin, uout, off, st);
+  if (a.group[3] > a.group[2]) fused_ldg_go<3, RK>(a, 2, uin, uout, off, st);
+  if (a.group[4] > a.group[3]) fused_ldg_go<2, RK>(a, 3, uin, uout, off, st);
+}
+
 template <int NP, int RK, int PHYS, int R>
 static void fused_go_r(const StepArgs& a, int gi, const double* uin, double* uout, int32_t off, hipStream_t st) {
   const dim3 g(a.grid[gi]), b(kBlock);
@@ -333,6 +506,7 @@ static void fused_phys(int phys, const StepArgs& a, const double* uin, double* u
     case PHYS_ADV_UPWIND: fused_np<RK, PHYS_ADV_UPWIND>(a, uin, uout, off, st); break;
     case PHYS_ADV_UPWIND_POS: fused_np<RK, PHYS_ADV_UPWIND_POS>(a, uin, uout, off, st); break;
     case PHYS_ADV_CENTRAL: fused_np<RK, PHYS_ADV_CENTRAL>(a, uin, uout, off, st); break;
+    case PHYS_BURGERS_LDG: fused_ldg_np<RK>(a, uin, uout, off, st); break;  // one step, one element per lane
     default: fused_np<RK, PHYS_BURGERS_LLF>(a, uin, uout, off, st); break;
   }
 }

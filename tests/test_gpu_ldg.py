@@ -1,7 +1,8 @@
-"""Viscous Burgers in local DG form (per-stage kernels, q pass + flux pass)
-against the FP64 oracle: synchronous LDG, ALDG with AT2 and AT(p+1) on both
-PE-face values, plain ALDG, per-step and per-stage delays, every
-integrator, ragged and tiny meshes, and a batch with different viscosities."""
+"""Viscous Burgers in local DG form against the FP64 oracle, on the fused
+kernel (q on chip, one launch per step) and on the per-stage kernels (q pass
++ flux pass): synchronous LDG, ALDG with AT2 and AT(p+1) on both PE-face
+values, plain ALDG, per-step and per-stage delays, every integrator, ragged
+and tiny meshes, and a batch with different viscosities."""
 import sys
 from dataclasses import replace
 
@@ -40,16 +41,17 @@ CASES = [(2, "heun", "adg_at", 2, False), (2, "heun", "dg", 0, False), (1, "rk4"
          (3, "ssprk3", "adg", 0, True), (2, "lsrk3", "adg_at", 3, False), (4, "rk4", "adg_at", 2, True)]
 
 
+@pytest.mark.parametrize("kernel", ["fused", "stage"])
 @pytest.mark.parametrize("p,rk,scheme,q,per_stage", CASES)
-def test_ldg_matches_oracle(torch_cuda, p, rk, scheme, q, per_stage):
+def test_ldg_matches_oracle(torch_cuda, p, rk, scheme, q, per_stage, kernel):
     from paper_2404_03399_amd.solver import Solver
     w = _w(p, rk, scheme, q, per_stage)
     n = 17
-    _say(f"viscous Burgers LDG p={p} {rk} {scheme} q={q} per_stage={per_stage} N=300 steps={n}")
+    _say(f"viscous Burgers LDG {kernel} p={p} {rk} {scheme} q={q} per_stage={per_stage} N=300 steps={n}")
     u0 = stepper.initial_state(w)
     ref = stepper.Stepper(w).run(u0, n)
     for graph in (False, True):
-        s = Solver(w)
+        s = Solver(w, kernel=kernel)
         u = s.pack(u0)
         s.run(u, n, graph=graph)
         torch_cuda.cuda.synchronize()
@@ -60,14 +62,15 @@ def test_ldg_matches_oracle(torch_cuda, p, rk, scheme, q, per_stage):
         assert stats.rel_l2(got, u0) > 1e-6
 
 
-def test_ldg_edge_meshes_and_batch(torch_cuda):
+@pytest.mark.parametrize("kernel", ["fused", "stage"])
+def test_ldg_edge_meshes_and_batch(torch_cuda, kernel):
     from paper_2404_03399_amd.solver import Solver
     ws = [replace(_w(2, "heun", "adg_at", 2, False, ne=ne, pe=pe, nu=nu, seed=ne), name=f"b{ne}")
-          for ne, pe, nu in ((7, 1, 0.05), (64, 64, 0.1), (130, 13, 0.2), (2, 1, 0.1))]
+          for ne, pe, nu in ((7, 1, 0.05), (64, 64, 0.1), (130, 13, 0.2), (2, 1, 0.1), (1001, 7, 0.1))]
     n = 11
-    _say("viscous Burgers LDG batch: N = 7, 64 (one PE), 130, 2; nu = 0.05..0.2")
+    _say(f"viscous Burgers LDG batch ({kernel}): N = 7, 64 (one PE), 130, 2, 1001; nu = 0.05..0.2")
     u0s = [stepper.initial_state(w) for w in ws]
-    s = Solver(ws)
+    s = Solver(ws, kernel=kernel)
     u = s.pack(u0s)
     s.run(u, n, graph=False)
     torch_cuda.cuda.synchronize()
@@ -85,3 +88,33 @@ def test_viscous_burgers_convergence(torch_cuda):
     r = X.viscous_burgers_convergence()
     assert r["order_dg"] <= -2.8 and r["order_adg_at"] <= -2.8, r
     assert all(a < 1.5 * d for a, d in zip(r["adg_at"], r["dg"])), r
+
+
+@pytest.mark.parametrize("p,rk,scheme,q,per_stage", [(2, "heun", "adg_at", 2, False), (1, "rk4", "adg_at", 0, True)])
+def test_ldg_fused_equals_stage(torch_cuda, p, rk, scheme, q, per_stage):
+    """The fused kernel and the per-stage kernels agree to rounding on a mesh
+    of several tiles with a ragged tail, over enough steps that every delay
+    level and ring slot is used (configurations that stay stable: ALDG with
+    AT(p+1), p = 3 and per-stage delays grows at the PE faces within 40
+    steps here, in the oracle as on the GPU)."""
+    from paper_2404_03399_amd.solver import Solver
+    w = _w(p, rk, scheme, q, per_stage, ne=4080, pe=40, seed=11)
+    n = 40
+    _say(f"viscous Burgers LDG fused vs stage N={w.n_elem} steps={n}")
+    u0 = stepper.initial_state(w)
+    out = {}
+    for kernel in ("fused", "stage"):
+        s = Solver(w, kernel=kernel)
+        u = s.pack(u0)
+        s.run(u, n)
+        torch_cuda.cuda.synchronize()
+        out[kernel] = s.unpack(u)[0]
+        s.close()
+    # the increments over the run (the diffusive step limit keeps them small
+    # against u itself), compared to rounding
+    d_f, d_s = out["fused"] - u0, out["stage"] - u0
+    assert stats.rel_l2(d_s, np.zeros_like(d_s)) > 1e-6
+    assert stats.rel_l2(d_f, d_s) <= 1e-9
+    ref = stepper.Stepper(w).run(u0, n)
+    assert stats.rel_l2(out["fused"], ref) <= 1e-12
+    assert stats.rel_l2(d_f, ref - u0) <= 1e-9

@@ -102,12 +102,17 @@ def test_viscous_burgers_options(L):
     w = W.Workload(name="ldg", equation="viscous_burgers", flux="llf", rk="heun", degree=2, n_elem=64,
                    pe_size=16, probs=("0.3", "0.4", "0.3"), viscosity=0.1, dt=1e-4)
     p = solver.to_problem(w)
-    assert adg.adg_workspace_size([p], adg.adg_options()) > 0          # AUTO -> per-stage kernels
+    fused = adg.adg_workspace_size([p], adg.adg_options())              # AUTO -> fused, q kept on chip
     opt = adg.adg_options()
-    opt.kernel = adg.KERNEL["fused"]
-    with pytest.raises(adg.AdgError) as ei:
-        adg.adg_workspace_size([p], opt)
-    assert ei.value.code == adg.ADG_E_UNSUPPORTED
+    opt.kernel = adg.KERNEL["stage"]
+    assert adg.adg_workspace_size([p], opt) > fused                     # the q pass needs a buffer
+    for field, value in (("lane_elems", 2), ("fused_steps", 2)):       # one element per lane, one step
+        opt = adg.adg_options()
+        opt.kernel = adg.KERNEL["fused"]
+        setattr(opt, field, value)
+        with pytest.raises(adg.AdgError) as ei:
+            adg.adg_workspace_size([p], opt)
+        assert ei.value.code == adg.ADG_E_UNSUPPORTED
     with pytest.raises(adg.AdgError) as ei:
         adg.adg_workspace_size([p], adg.adg_options(), 10)             # no adjoint for local DG
     assert ei.value.code == adg.ADG_E_UNSUPPORTED
