@@ -960,8 +960,17 @@ int adjoint_fused(adg_ctx* c, const double* d_cot_uT, double* d_grad_u0, double*
     double* ck = (double*)(ws + L.ckpt) + tot * k;
     auto state = [&](int64_t i) { return i == 0 ? ck : useg + tot * (i - 1); };
     if (len > 1 && (rc = c->save_records(k, true))) return rc;
-    for (int64_t i = 1; i < len; ++i)
-      ADG_HIP(launch_fused_step(c->rk, c->fused_phys, fa, state(i - 1), state(i), (int32_t)(n0 + i - 1), st));
+    for (int64_t i = 1; i < len;) {
+      if (c->fused_steps == 2 && i + 1 < len) {  // two steps per launch, the first one written too
+        StepArgs f2 = c->fused_args(2);
+        f2.umid = state(i);
+        ADG_HIP(launch_fused_step(c->rk, c->fused_phys, f2, state(i - 1), state(i + 1), (int32_t)(n0 + i - 1), st));
+        i += 2;
+      } else {
+        ADG_HIP(launch_fused_step(c->rk, c->fused_phys, fa, state(i - 1), state(i), (int32_t)(n0 + i - 1), st));
+        i += 1;
+      }
+    }
     for (int64_t i = len - 1; i >= 0; --i) {
       ADG_HIP(launch_adj_fused(c->rk, c->phys, aa, state(i), lam, lamu, ring, adjring, cpart, (int32_t)(n0 + i),
                                st));

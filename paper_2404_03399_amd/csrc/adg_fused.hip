@@ -37,7 +37,7 @@ namespace adg {
 template <int NP, int RK, int PHYS, int R, int K>
 __device__ __forceinline__ void wave_tile(const DevProblem& P, const WorkItem wi, const FusedPtrs& A, int64_t n,
                                           const double* __restrict__ uin, double* __restrict__ uout,
-                                          WaveSmemK<K>& sm, int wv, int lane) {
+                                          double* __restrict__ umid, WaveSmemK<K>& sm, int wv, int lane) {
 #pragma clang fp contract(off)  // explicit FMAs only: rounding independent of the launch shape
   constexpr int S = rk_stages(RK);
   constexpr int HL = fused_halo(RK, R, K);
@@ -148,7 +148,32 @@ __device__ __forceinline__ void wave_tile(const DevProblem& P, const WorkItem wi
     }
   }
 
+  // write the owned elements of the tile
+  bool all_owned = true;
+#pragma unroll
+  for (int r = 0; r < R; ++r) all_owned = all_owned && owned[r];
   double y[R][NP], ks[R][NP], k[NP];
+  auto store = [&](double* __restrict__ dst) {
+    double* __restrict__ uo = dst + P.u_off;
+    if (grouped && all_owned) {
+      double2* __restrict__ uo2 = reinterpret_cast<double2*>(__builtin_assume_aligned(uo, 16));
+#pragma unroll
+      for (int j = 0; j < NP; ++j)
+#pragma unroll
+        for (int r = 0; r < R; r += 2) {
+          double2 v;
+          v.x = y[r][j];
+          v.y = y[r + 1 < R ? r + 1 : r][j];
+          uo2[(j * ld + e[0] + r) >> 1] = v;
+        }
+    } else {
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+        if (owned[r])
+#pragma unroll
+          for (int j = 0; j < NP; ++j) uo[j * ld + e[r]] = y[r][j];
+    }
+  };
 #pragma unroll
   for (int r = 0; r < R; ++r)
 #pragma unroll
@@ -164,6 +189,8 @@ __device__ __forceinline__ void wave_tile(const DevProblem& P, const WorkItem wi
 #pragma unroll
   for (int kk = 0; kk < K; ++kk) {
     if (kk > 0) {
+      // after 2S stages of halo the owned lanes are exact after the first step too
+      if (umid != nullptr) store(umid);
       slot_m = slot_m + 1 == depth ? 0 : slot_m + 1;
 #pragma unroll
       for (int r = 0; r < R; ++r)
@@ -223,28 +250,7 @@ __device__ __forceinline__ void wave_tile(const DevProblem& P, const WorkItem wi
     }
   }
 
-  double* __restrict__ uo = uout + P.u_off;
-  bool all_owned = true;
-#pragma unroll
-  for (int r = 0; r < R; ++r) all_owned = all_owned && owned[r];
-  if (grouped && all_owned) {
-    double2* __restrict__ uo2 = reinterpret_cast<double2*>(__builtin_assume_aligned(uo, 16));
-#pragma unroll
-    for (int j = 0; j < NP; ++j)
-#pragma unroll
-      for (int r = 0; r < R; r += 2) {
-        double2 v;
-        v.x = y[r][j];
-        v.y = y[r + 1 < R ? r + 1 : r][j];
-        uo2[(j * ld + e[0] + r) >> 1] = v;
-      }
-  } else {
-#pragma unroll
-    for (int r = 0; r < R; ++r)
-      if (owned[r])
-#pragma unroll
-        for (int j = 0; j < NP; ++j) uo[j * ld + e[r]] = y[r][j];
-  }
+  store(uout);
 
   // records of steps n + K and n + K + 1 over the levels up to n + K - 1:
   // the part before n and the delay from the start of the launch (formed here
@@ -284,8 +290,8 @@ __global__ __launch_bounds__(kBlock) void k_fused_step(const DevProblem* __restr
                                                        const int64_t* __restrict__ ctr, double* __restrict__ ring,
                                                        double* __restrict__ atsum, int32_t* __restrict__ atk,
                                                        int32_t w_begin, int32_t w_end, const double* __restrict__ uin,
-                                                       double* __restrict__ uout, int32_t step_offset,
-                                                       int32_t single_prob) {
+                                                       double* __restrict__ uout, double* __restrict__ umid,
+                                                       int32_t step_offset, int32_t single_prob) {
   __shared__ WaveSmemK<K> sm;
   const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
   const int lane = (int)(threadIdx.x % kWave);
@@ -295,7 +301,7 @@ __global__ __launch_bounds__(kBlock) void k_fused_step(const DevProblem* __restr
   // a range holding one problem lists its tiles in order: no work-list load
   const WorkItem wi = single_prob >= 0 ? WorkItem{single_prob, w - w_begin} : work[w];
   const FusedPtrs A{ring, atsum, atk};
-  wave_tile<NP, RK, PHYS, R, K>(probs[wi.prob], wi, A, n, uin, uout, sm, wv, lane);
+  wave_tile<NP, RK, PHYS, R, K>(probs[wi.prob], wi, A, n, uin, uout, umid, sm, wv, lane);
 }
 
 // Viscous Burgers in local DG form (Sec. 7), one time step per launch, one
@@ -476,10 +482,10 @@ static void fused_go_r(const StepArgs& a, int gi, const double* uin, double* uou
   const dim3 g(a.grid[gi]), b(kBlock);
   if (a.steps == 2)
     hipLaunchKernelGGL((k_fused_step<NP, RK, PHYS, R, 2>), g, b, 0, st, a.probs, a.work, a.ctr, a.ring, a.atsum, a.atk,
-                       a.group[gi], a.group[gi + 1], uin, uout, off, a.single[gi]);
+                       a.group[gi], a.group[gi + 1], uin, uout, a.umid, off, a.single[gi]);
   else
     hipLaunchKernelGGL((k_fused_step<NP, RK, PHYS, R, 1>), g, b, 0, st, a.probs, a.work, a.ctr, a.ring, a.atsum, a.atk,
-                       a.group[gi], a.group[gi + 1], uin, uout, off, a.single[gi]);
+                       a.group[gi], a.group[gi + 1], uin, uout, nullptr, off, a.single[gi]);
 }
 
 template <int NP, int RK, int PHYS>

@@ -19,6 +19,8 @@ struct StepArgs {
   int32_t lane_elems;        // fused kernel: elements per lane (1, 2 or 4)
   int32_t steps;             // fused kernel: time steps per launch (1 or 2)
   double* qbuf;              // local DG: q = u_x of the current stage input (state layout)
+  double* umid;              // fused kernel, two steps per launch: also write the state after
+                             // the first step here (state layout), or null
 };
 
 // Work items of the fused kernel are sorted by descending np; items with
