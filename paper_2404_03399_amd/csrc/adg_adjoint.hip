@@ -142,6 +142,17 @@ __global__ __launch_bounds__(kBlock) void k_adj_stage(const DevProblem* __restri
   }
 }
 
+// Per-lane PE-face values of a reverse step (lane = the PE lane they belong
+// to): delay, AT sum of past levels (forward recompute), adjoint already
+// collected for the level-n raw flux, and the flux sensitivity to scatter.
+template <int S>
+struct AdjSmem {
+  uint8_t kd[kWavesPerBlock][S][kWave];
+  double atf[kWavesPerBlock][S][kWave];
+  double adjn[kWavesPerBlock][S][kWave];
+  double lf[kWavesPerBlock][S][kWave];
+};
+
 // ------------------------------------------------------ fused adjoint step ---
 // Reverse of one whole RK step n in one launch: one wave64 per tile of
 // T = 64 - 2H owned elements with H halo lanes per side, one element per lane.
@@ -163,7 +174,8 @@ template <int NP, int RK, int PHYS, bool FWD>
 __device__ __forceinline__ void adj_tile(const DevProblem& P, const WorkItem wi, int w, int lane, int32_t n,
                                          const double* __restrict__ uin, const double* __restrict__ lam,
                                          double* __restrict__ lamo, const double* __restrict__ ring,
-                                         double* __restrict__ adjring, double* __restrict__ cpart) {
+                                         double* __restrict__ adjring, double* __restrict__ cpart,
+                                         AdjSmem<rk_stages(RK)>& sm, int wv) {
   constexpr int S = rk_stages(RK);
   constexpr int HL = adj_halo(RK, PHYS == PHYS_BURGERS_LLF);
   constexpr int T = kWave - 2 * HL;
@@ -182,31 +194,32 @@ __device__ __forceinline__ void adj_tile(const DevProblem& P, const WorkItem wi,
     lamp[j] = lp[j * ld + e];
   }
 
-  // PE face on this lane's left face: delays of step n, the applied AT sums of
-  // past levels and the adjoint already collected for the level-n raw fluxes
+  // PE face on this lane's left face.  Its delays of step n, the applied AT
+  // sums of past levels and the adjoint already collected for the level-n raw
+  // fluxes are formed by job lanes, one per (PE lane, stage), with one memory
+  // round trip for the whole wave.
   bool pe = false;
   uint32_t b = 0;
   int depth = 1, slot_n = 0;
-  int kd[S];
-  double atf[S], adjn[S];
-#pragma unroll
-  for (int s = 0; s < S; ++s) { kd[s] = 0; atf[s] = 0.0; adjn[s] = 0.0; }
   if (P.async_faces) {
     depth = P.depth;
     slot_n = (int)((uint32_t)n - fast_div((uint32_t)n, P.depth_div) * (uint32_t)depth);
-    const uint32_t bl = fast_div((uint32_t)e, P.pe_div);
-    pe = (uint32_t)e == bl * P.pe_div.d;
-    if (pe) {
-      b = bl;
-      const uint64_t pre0 = delay_prefix(P.seed, n, 0);
-#pragma unroll
-      for (int s = 0; s < S; ++s) {
-        const uint64_t pre = P.per_stage ? delay_prefix(P.seed, n, s) : pre0;
-        kd[s] = clamp_delay(P.caa ? caa_delay(n) : delay_from_prefix(pre, b, P.thr, P.n_delays), n, P.q);
-        const int64_t rb = P.ring_off + ((int64_t)b * S + s) * depth;
-        adjn[s] = adjring[rb + slot_n];
-        if (FWD && kd[s] > 0) atf[s] = at_past_sum(P, ring + rb, kd[s], slot_n);
-      }
+    b = fast_div((uint32_t)e, P.pe_div);
+    pe = (uint32_t)e == b * P.pe_div.d;
+  }
+  const uint64_t m_pe = __ballot(pe);
+  const int n_jobs = S * __builtin_popcountll(m_pe);
+  for (int g0 = 0; g0 < n_jobs; g0 += kWave) {  // uniform
+    const int g = g0 + lane;
+    const int i = g / S, s = g - i * S;
+    const int tgt = nth_set_lane(m_pe, i);
+    const uint32_t face = (uint32_t)__shfl((int)b, tgt);  // every lane active
+    if (g < n_jobs) {
+      const int kd = pe_delay(P, n, s, face);
+      const int64_t rb = P.ring_off + ((int64_t)face * S + s) * depth;
+      sm.kd[wv][s][tgt] = (uint8_t)kd;
+      sm.adjn[wv][s][tgt] = adjring[rb + slot_n];
+      if constexpr (FWD) sm.atf[wv][s][tgt] = at_old_levels(P, ring + rb, n, kd, n, slot_n, depth);
     }
   }
 
@@ -222,7 +235,7 @@ __device__ __forceinline__ void adj_tile(const DevProblem& P, const WorkItem wi,
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       double F = Physics<PHYS>::fhat(lane_from_left(y[NP - 1]), y[0], a);
-      if (pe && kd[s] > 0) F = atf[s];
+      if (pe && sm.kd[wv][s][lane] > 0) F = sm.atf[wv][s][lane];
       folded_rhs<NP, PHYS>(P, y, F, lane_from_right(F), k);
 #pragma unroll
       for (int j = 0; j < NP; ++j) kept(s, j) = PHYS == PHYS_BURGERS_LLF ? y[j] : k[j];
@@ -260,12 +273,9 @@ __device__ __forceinline__ void adj_tile(const DevProblem& P, const WorkItem wi,
       flux_partials<PHYS>(0.0, 0.0, a, dm, dp);
     double raw = lf;
     if (pe) {
-      const int kk = kd[s];
-      raw = (kk == 0 ? lf : 0.0) + adjn[s];
-      if (owned && kk > 0) {
-        double* __restrict__ rb = adjring + P.ring_off + ((int64_t)b * S + s) * depth;
-        for (int j = 0; j < P.q; ++j) rb[ring_slot(slot_n, kk + j, depth)] += P.atc[kk][j] * lf;
-      }
+      const int kk = sm.kd[wv][s][lane];
+      raw = (kk == 0 ? lf : 0.0) + sm.adjn[wv][s][lane];
+      sm.lf[wv][s][lane] = lf;  // scattered at the end when delayed
     }
     double mu[NP];
 #pragma unroll
@@ -301,6 +311,25 @@ __device__ __forceinline__ void adj_tile(const DevProblem& P, const WorkItem wi,
 #pragma unroll
     for (int j = 0; j < NP; ++j) lo[j * ld + e] = lu[j];
 
+  // the delayed levels' share of the AT sensitivities into the adjoint ring
+  // (levels below n, which nothing in this launch reads), one job lane per
+  // (owned PE lane, stage, level); each ring entry is touched once
+  const uint64_t m_own = __ballot(pe && owned);
+  const int n_sc = S * kMaxQ * __builtin_popcountll(m_own);
+  for (int g0 = 0; g0 < n_sc; g0 += kWave) {  // uniform
+    const int g = g0 + lane;
+    const int i = g / (S * kMaxQ), r = g - i * (S * kMaxQ), s = r / kMaxQ, j = r - s * kMaxQ;
+    const int tgt = nth_set_lane(m_own, i);
+    const uint32_t face = (uint32_t)__shfl((int)b, tgt);  // every lane active
+    if (g < n_sc) {
+      const int kk = sm.kd[wv][s][tgt];
+      if (kk > 0 && j < P.q) {
+        double* __restrict__ at = adjring + P.ring_off + ((int64_t)face * S + s) * depth + ring_slot(slot_n, kk + j, depth);
+        *at = fma(P.atc[kk][j], sm.lf[wv][s][tgt], *at);
+      }
+    }
+  }
+
   // dJ/da share of this tile: every term of K is proportional to a for linear
   // advection, so dK/da = K / a with the stage inputs held fixed.  Fixed
   // butterfly order: deterministic.
@@ -323,8 +352,9 @@ __global__ __launch_bounds__(kBlock) void k_adj_fused(const DevProblem* __restri
   const int lane = (int)(threadIdx.x % kWave);
   const int w = w_begin + xcd_block((int)blockIdx.x, (int)gridDim.x) * kWavesPerBlock + wv;
   if (w >= w_end) return;  // whole wave
+  __shared__ AdjSmem<rk_stages(RK)> sm;
   const WorkItem wi = work[w];
-  adj_tile<NP, RK, PHYS, FWD>(probs[wi.prob], wi, w, lane, n, u, lam, lamo, ring, adjring, cpart);
+  adj_tile<NP, RK, PHYS, FWD>(probs[wi.prob], wi, w, lane, n, u, lam, lamo, ring, adjring, cpart, sm, wv);
 }
 
 template <int RK, int PHYS, int SI>
