@@ -219,7 +219,7 @@ __device__ __forceinline__ void adj_tile(const DevProblem& P, const WorkItem wi,
       const int64_t rb = P.ring_off + ((int64_t)face * S + s) * depth;
       sm.kd[wv][s][tgt] = (uint8_t)kd;
       sm.adjn[wv][s][tgt] = adjring[rb + slot_n];
-      if constexpr (FWD) sm.atf[wv][s][tgt] = at_old_levels(P, ring + rb, n, kd, n, slot_n, depth);
+      if constexpr (FWD) sm.atf[wv][s][tgt] = at_old_levels(P, ring + rb, 0, kd, slot_n, depth);
     }
   }
 

@@ -269,24 +269,24 @@ __device__ __forceinline__ int nth_set_lane(uint64_t mask, int i) {
 // Record slot of step m (steps below 2^31).
 __device__ __forceinline__ int64_t rec_slot(int64_t m) { return (int64_t)((uint32_t)m % (uint32_t)kRecSlots); }
 
-// Part of the AT sum of step m (delay kd >= 1) over the levels m - kd - j
-// that precede step n, j = q-1 down to 0, oldest first, one explicit FMA per
-// level; rb is the ring of one (boundary, stage), slot_n = n mod depth.  The
-// loads are unrolled over kMaxQ and issue together.
-__device__ __forceinline__ double at_old_levels(const DevProblem& P, const double* __restrict__ rb, int64_t m,
-                                                int kd, int64_t n, int slot_n, int depth) {
+// Part of the AT sum of step m = n + ahead (delay kd >= 1) over the levels
+// m - kd - j that precede step n, j = q-1 down to 0, oldest first, one
+// explicit FMA per level; rb is the ring of one (boundary, stage), slot_n =
+// n mod depth.  The loads are unrolled over kMaxQ and issue together.
+__device__ __forceinline__ double at_old_levels(const DevProblem& P, const double* __restrict__ rb, int ahead,
+                                                int kd, int slot_n, int depth) {
 #pragma clang fp contract(off)
   double c[kMaxQ], v[kMaxQ];
   bool use[kMaxQ];
 #pragma unroll
   for (int j = 0; j < kMaxQ; ++j) {
-    const int64_t back = n - (m - kd - j);  // level n - back
+    const int back = kd + j - ahead;  // level n - back
     use[j] = kd > 0 && j < P.q && back >= 1;
     c[j] = 0.0;
     v[j] = 0.0;
     if (use[j]) {
       c[j] = P.atc[kd][j];
-      v[j] = rb[ring_slot(slot_n, (int)back, depth)];
+      v[j] = rb[ring_slot(slot_n, back, depth)];
     }
   }
   double acc = 0.0;

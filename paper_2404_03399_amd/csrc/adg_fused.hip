@@ -144,7 +144,7 @@ __device__ __forceinline__ void wave_tile(const DevProblem& P, const WorkItem wi
       const int kd = pe_delay(P, m, s, bo);
       sm.kdj[wv][lane] = kd;
       sm.part[wv][lane] =
-          at_old_levels(P, A.ring + P.ring_off + ((int64_t)bo * S + s) * depth, m, kd, n, slot_n, depth);
+          at_old_levels(P, A.ring + P.ring_off + ((int64_t)bo * S + s) * depth, K + t, kd, slot_n, depth);
     }
   }
 
@@ -270,11 +270,11 @@ __device__ __forceinline__ void wave_tile(const DevProblem& P, const WorkItem wi
         acc = sm.part[wv][lane];
       } else {
         kd = pe_delay(P, m, s, bo);
-        acc = at_old_levels(P, A.ring + P.ring_off + ((int64_t)bo * S + s) * depth, m, kd, n, slot_n, depth);
+        acc = at_old_levels(P, A.ring + P.ring_off + ((int64_t)bo * S + s) * depth, K + t, kd, slot_n, depth);
       }
 #pragma unroll
       for (int j = kMaxQ - 1; j >= 0; --j) {
-        const int64_t rel = m - kd - j - n;  // level n + rel of this launch
+        const int rel = K + t - kd - j;  // level n + rel of this launch
         if (kd > 0 && j < P.q && rel >= 0 && rel < K) acc = fma(P.atc[kd][j], sm.at[rel][wv][s][src], acc);
       }
       const int64_t rs = rec_slot(m);
@@ -384,7 +384,7 @@ __device__ __forceinline__ void wave_tile_ldg(const DevProblem& P, const WorkIte
       const uint32_t face = left ? fl : fr;
       const int kd = pe_delay(P, n, s, face);
       const double* __restrict__ rb = ring + (v == 1 ? P.ring_off : P.ring2_off) + ((int64_t)face * S + s) * depth;
-      const double val = at_old_levels(P, rb, n, kd, n, slot_n, depth);
+      const double val = at_old_levels(P, rb, 0, kd, slot_n, depth);
       if (v == 0) {
         sm.atu[wv][s][tgt] = val;
         sm.kl[wv][s][tgt] = (uint8_t)kd;
