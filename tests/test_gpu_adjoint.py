@@ -48,6 +48,7 @@ CASES = [
     ("dg", "rk4", 4, "upwind", 70, 7),
     ("adg_at", "rk4", 3, "central", 300, 25),
     ("adg_at", "lsrk3", 2, "upwind", 90, 9),
+    ("adg_at", "rk4", 1, "upwind", 96, 2),  # a PE face every other element: several job passes per wave
 ]
 
 
