@@ -366,6 +366,11 @@ def main():
     roof.update({"kernel": kname, "alg_bytes_per_launch": alg_bytes, "launch_us": launch_s * 1e6,
                  "steps_per_launch": K, "lane_elems": R,
                  "note": "working set 2 x 33.6 MB fits the 256 MB Infinity Cache"})
+    # the same throughput at the per-stage kernels' byte model (34 B per DOF-stage
+    # for RK4): the bandwidth an unfused stepper would need to match it
+    sm = BYTES_PER_DOF_STAGE_STAGEK["rk4"] * value / 1e9
+    roof["stage_model"] = {"bytes_per_dof_stage": BYTES_PER_DOF_STAGE_STAGEK["rk4"], "effective_GBs": sm,
+                           "frac_of_peak": sm / HBM_PEAK_GBS}
 
     out = {
         "metric": "DOF-stage updates/s (fwd, adjoint) vs HBM roofline; batched vs plain",
