@@ -178,6 +178,39 @@ def bench_adjoint(torch, W, Solver, n_steps: int, n_elem: int, stage: bool):
                                                               / torch.linalg.vector_norm(g)),
                                 "dJ_da": ga2}
         s.close()
+    out["burgers"] = bench_adjoint_burgers(torch, W, Solver, stage)
+    return out
+
+
+def bench_adjoint_burgers(torch, W, Solver, stage: bool, n_elem: int = 1 << 18, n_steps: int = 512):
+    """Discrete adjoint of inviscid Burgers (LLF, ADG-AT q=3, p=2, SSP-RK3,
+    PEs of 256, checkpoint every 64) over a window of n_steps steps, with
+    J = 1/2 ||u(T) - u(0)||^2: dJ/du0 through the nonlinear reverse step (the
+    forward stages recomputed in registers), and the per-stage reverse
+    kernels on the same cotangent for comparison."""
+    w = W.c5_adjoint_burgers(n_elem=n_elem, n_steps=n_steps)
+    dofs = w.n_elem * (w.degree + 1)
+    s = Solver(w, n_steps_record=n_steps, ckpt_every=64)
+    u_init = s.initial_state()
+    holder = {}
+
+    def cot_of(u):
+        holder["cot"] = u - u_init
+        return holder["cot"]
+
+    g, _, t_fwd, t_adj = _timed_adjoint(torch, s, n_steps, cot_of)
+    s.close()
+    out = {"workload": f"Burgers LLF ADG-AT(q=3) SSP-RK3 N_E={n_elem} p=2, PE size 256, {n_steps}-step window, "
+                       f"checkpoint every 64, J = 1/2 ||u(T) - u(0)||^2",
+           "reverse_dof_stage_per_s": dofs * 3 * n_steps / t_adj, "adjoint_s": t_adj, "recorded_forward_s": t_fwd,
+           "grad_finite": bool(torch.isfinite(g).all().item())}
+    if stage:
+        s = Solver(w, kernel="stage", n_steps_record=n_steps, ckpt_every=64)
+        g2, _, _, t2 = _timed_adjoint(torch, s, n_steps, lambda u: holder["cot"])
+        s.close()
+        out["stage_kernels"] = {"reverse_dof_stage_per_s": dofs * 3 * n_steps / t2, "adjoint_s": t2,
+                                "grad_rel_l2_vs_fused": float(torch.linalg.vector_norm(g2 - g)
+                                                              / torch.linalg.vector_norm(g))}
     return out
 
 
