@@ -248,7 +248,7 @@ BYTES_PER_DOF_STAGE_LDG_HEUN = 52.0
 
 def bench_viscous_burgers(torch, W, Solver, n_elem: int = 1 << 20, steps: int = 200):
     """Throughput of ALDG(2)-AT2-RK2 (viscous Burgers, P = n_elem / 256) on
-    the fused local DG kernel (one step per launch: 16 B per DOF and step
+    the fused local DG kernel (K steps per launch: 16 B per DOF and launch
     plus the two PE-face rings) and on the per-stage kernels."""
     w = W.viscous_burgers_workload(n_elem, "adg_at", 2, t_final=1e-3)
     from dataclasses import replace
@@ -258,14 +258,15 @@ def bench_viscous_burgers(torch, W, Solver, n_elem: int = 1 << 20, steps: int = 
     finite = True
     for kernel in ("fused", "stage"):
         s = Solver(w, kernel=kernel)
+        K = (s.opt.fused_steps or 2) if kernel == "fused" else 1
         u = s.initial_state()
         g, _ = time_solver(torch, s, u, steps, 20)
         finite = finite and bool(torch.isfinite(u).all().item())
         s.close()
         rate = dofs * 2 * steps / g
         if kernel == "fused":
-            step_bytes = BYTES_PER_DOF_STEP_FUSED * dofs + 2 * ring_bytes_per_step(w)
-            out.update({"dof_stage_per_s": rate, "us_per_step": g / steps * 1e6,
+            step_bytes = BYTES_PER_DOF_STEP_FUSED * dofs / K + 2 * ring_bytes_per_step(w)
+            out.update({"dof_stage_per_s": rate, "us_per_step": g / steps * 1e6, "steps_per_launch": K,
                         "hbm_frac": step_bytes / (g / steps) / 1e9 / HBM_PEAK_GBS})
         else:
             out["stage_kernels"] = {"dof_stage_per_s": rate, "us_per_step": g / steps * 1e6,

@@ -66,10 +66,9 @@ enum adg_status {
   ADG_E_UNSUPPORTED = -7   /* valid request not implemented by this build       */
 };
 
-/* VISCOUS_BURGERS: the fused kernel runs one element per lane and one step
- * per launch (lane_elems and fused_steps above 1 return ADG_E_UNSUPPORTED);
- * the per-stage kernels run it too; adjoint recording returns
- * ADG_E_UNSUPPORTED. */
+/* VISCOUS_BURGERS: the fused kernel runs one element per lane (lane_elems
+ * above 1 returns ADG_E_UNSUPPORTED) and one or two steps per launch; the
+ * per-stage kernels run it too; adjoint recording returns ADG_E_UNSUPPORTED. */
 enum adg_equation { ADG_EQ_ADVECTION = 0, ADG_EQ_BURGERS = 1, ADG_EQ_VISCOUS_BURGERS = 2 };
 enum adg_scheme { ADG_SCHEME_DG = 0, ADG_SCHEME_ADG = 1, ADG_SCHEME_ADG_AT = 2 };
 /* upwind / central: f^ = a (B+ u- + B- u+) (Sec. 2);  llf: local Lax-Friedrichs

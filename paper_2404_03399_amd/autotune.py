@@ -48,8 +48,8 @@ def admissible(workloads) -> List[int]:
 
 
 def configs(workloads) -> List[Tuple[int, int]]:
-    if workloads[0].equation == "viscous_burgers":  # the local DG kernel has one shape
-        return [(1, 1)]
+    if workloads[0].equation == "viscous_burgers":  # the local DG kernel: one element per lane
+        return [(1, k) for k in STEPS_PER_LAUNCH]
     return [(r, k) for r in admissible(workloads) for k in STEPS_PER_LAUNCH]
 
 

@@ -553,8 +553,8 @@ int adg_workspace_size(const adg_problem* probs, int32_t n_probs, const adg_opti
   if (lane_elems_of(probs, n_probs, opt) == 0)
     return fail(ADG_E_INVALID, "lane_elems must be 1, 2 or 4 and not exceed the PE size");
   if (fused_steps_of(opt) == 0) return fail(ADG_E_INVALID, "fused_steps must be 0, 1 or 2");
-  if (is_ldg(probs) && k == ADG_KERNEL_FUSED && opt && (opt->lane_elems > 1 || opt->fused_steps > 1))
-    return fail(ADG_E_UNSUPPORTED, "the fused local DG kernel runs one element per lane and one step per launch");
+  if (is_ldg(probs) && k == ADG_KERNEL_FUSED && opt && opt->lane_elems > 1)
+    return fail(ADG_E_UNSUPPORTED, "the fused local DG kernel runs one element per lane");
   if (is_ldg(probs) && n_steps_record > 0)
     return fail(ADG_E_UNSUPPORTED, "no adjoint for viscous Burgers (local DG)");
   *bytes_out = make_layout(probs, n_probs, opt, n_steps_record).total;
@@ -662,7 +662,7 @@ int adg_init(adg_ctx** out, const adg_problem* probs, int32_t n_probs, const adg
   for (int32_t i = 0; i < n_probs; ++i) order[i] = i;
   std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return probs[a].degree > probs[b].degree; });
   c->lane_elems = lane_elems_of(probs, n_probs, opt);
-  c->fused_steps = is_ldg(probs) ? 1 : fused_steps_of(opt);
+  c->fused_steps = fused_steps_of(opt);
   std::vector<WorkItem> wfk[2], ws_;
   std::vector<int32_t> first(n_probs + 1, 0);
   for (int K = 1; K <= 2; ++K) {

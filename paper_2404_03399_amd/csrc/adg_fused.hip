@@ -304,37 +304,40 @@ __global__ __launch_bounds__(kBlock) void k_fused_step(const DevProblem* __restr
   wave_tile<NP, RK, PHYS, R, K>(probs[wi.prob], wi, A, n, uin, uout, umid, sm, wv, lane);
 }
 
-// Viscous Burgers in local DG form (Sec. 7), one time step per launch, one
-// element per lane, halo S lanes per side.  Per stage: u-hat at a face is the
-// trace of the element on its left (alternating flux); q = Kr u-hat_right -
-// Kl u-hat_left - Kd u; the total flux at a face is G = LLF(u-, u+) - nu q+
-// with q+ from the element on its right; the element update is
-// Kl G_left - Kr G_right + Kd (u^2/2 - nu q).  u-hat_left comes from the left
-// lane by a lane shift and u-hat_right is the lane's own trace, so q needs no
-// data from the right; G_right comes from the right lane.  Each stage then
-// depends on one lane to either side, as the inviscid update does.  At a PE
-// face the element right of it writes the raw level-n u-hat and G to their
-// rings; every lane holding the face as its left face takes the AT
+// Viscous Burgers in local DG form (Sec. 7): K in {1, 2} time steps per
+// launch, one element per lane, halo K S lanes per side.  Per stage: u-hat at
+// a face is the trace of the element on its left (alternating flux); q = Kr
+// u-hat_right - Kl u-hat_left - Kd u; the total flux at a face is G =
+// LLF(u-, u+) - nu q+ with q+ from the element on its right; the element
+// update is Kl G_left - Kr G_right + Kd (u^2/2 - nu q).  u-hat_left comes from
+// the left lane by a lane shift and u-hat_right is the lane's own trace, so q
+// needs no data from the right; G_right comes from the right lane.  Each
+// stage then depends on one lane to either side, as the inviscid update does.
+// At a PE face the element right of it writes the raw level-m u-hat and G to
+// their rings; every lane holding the face as its left face takes the AT
 // combinations of past levels of both, and every lane holding it as its right
-// face the u-hat combination (all those levels were written by earlier
-// launches, so the combinations are formed at the start of the launch).
-template <int S>
+// face the u-hat combination.  The levels before n were written by earlier
+// launches, so these sums are formed at the start of the launch; for the
+// second step a delay of 1 also needs level n, which each lane adds from its
+// own raw values (the left-face u-hat and G it computes, and for the right
+// face its own trace, which is that face's u-hat).
+template <int S, int K>
 struct LdgSmem {
-  double atu[kWavesPerBlock][S][kWave];   // left face: u-hat
-  double atg[kWavesPerBlock][S][kWave];   // left face: G
-  double atur[kWavesPerBlock][S][kWave];  // right face: u-hat
-  uint8_t kl[kWavesPerBlock][S][kWave];   // delays of the left face
-  uint8_t kr[kWavesPerBlock][S][kWave];   // delays of the right face
+  double atu[K][kWavesPerBlock][S][kWave];   // left face: u-hat
+  double atg[K][kWavesPerBlock][S][kWave];   // left face: G
+  double atur[K][kWavesPerBlock][S][kWave];  // right face: u-hat
+  uint8_t kl[K][kWavesPerBlock][S][kWave];   // delays of the left face
+  uint8_t kr[K][kWavesPerBlock][S][kWave];   // delays of the right face
 };
 
-template <int NP, int RK>
+template <int NP, int RK, int K>
 __device__ __forceinline__ void wave_tile_ldg(const DevProblem& P, const WorkItem wi, double* __restrict__ ring,
                                               int64_t n, const double* __restrict__ uin, double* __restrict__ uout,
-                                              LdgSmem<rk_stages(RK)>& sm, int wv, int lane) {
+                                              LdgSmem<rk_stages(RK), K>& sm, int wv, int lane) {
 #pragma clang fp contract(off)  // explicit FMAs only
   constexpr int S = rk_stages(RK);
-  constexpr int HL = fused_halo(RK, 1, 1);
-  constexpr int T = fused_tile(RK, 1, 1);
+  constexpr int HL = fused_halo(RK, 1, K);
+  constexpr int T = fused_tile(RK, 1, K);
   const int N = (int)P.n_elem;
   const int e0 = wi.tile * T;
   const int teff = (N - e0) < T ? (N - e0) : T;
@@ -362,37 +365,40 @@ __device__ __forceinline__ void wave_tile_ldg(const DevProblem& P, const WorkIte
     br = fast_div(e1, P.pe_div);
     pe_r = e1 == br * pes;
   }
-  // The delays and AT sums of the launch, one job lane per (PE lane, stage,
-  // value): the left-face u-hat and G of each lane with a PE left face, the
-  // right-face u-hat of each lane with a PE right face.  Each job draws its
-  // delay and sums its past levels; the target lane reads both from LDS.
+  // The delays and the AT sums over the levels before n, one job lane per
+  // (PE lane, step, stage, value): the left-face u-hat and G of each lane with
+  // a PE left face, the right-face u-hat of each lane with a PE right face.
+  // Each job draws its delay and sums its past levels; the target lane reads
+  // both from LDS.
+  constexpr int KS = K * S;
   const uint64_t m_l = __ballot(pe), m_r = __ballot(pe_r);
-  const int n_l = 2 * S * __builtin_popcountll(m_l);
-  const int n_jobs = n_l + S * __builtin_popcountll(m_r);
+  const int n_l = 2 * KS * __builtin_popcountll(m_l);
+  const int n_jobs = n_l + KS * __builtin_popcountll(m_r);
   for (int g0 = 0; g0 < n_jobs; g0 += kWave) {  // uniform
     const int g = g0 + lane;
     const bool left = g < n_l;
     const int h = left ? g : g - n_l;
-    const int per = left ? 2 * S : S;
+    const int per = left ? 2 * KS : KS;
     const int i = h / per, r = h - i * per;
-    const int v = left ? r / S : 2;  // 0: u-hat, 1: G (left face); 2: u-hat (right face)
-    const int s = r - (left ? v * S : 0);
+    const int v = left ? r / KS : 2;  // 0: u-hat, 1: G (left face); 2: u-hat (right face)
+    const int rr = r - (left ? v * KS : 0);
+    const int kk = rr / S, s = rr - kk * S;
     const int tl = nth_set_lane(m_l, i), tr = nth_set_lane(m_r, i);
     const uint32_t fl = (uint32_t)__shfl((int)b, tl), fr = (uint32_t)__shfl((int)br, tr);  // every lane active
     if (g < n_jobs) {
       const int tgt = left ? tl : tr;
       const uint32_t face = left ? fl : fr;
-      const int kd = pe_delay(P, n, s, face);
+      const int kd = pe_delay(P, n + kk, s, face);
       const double* __restrict__ rb = ring + (v == 1 ? P.ring_off : P.ring2_off) + ((int64_t)face * S + s) * depth;
-      const double val = at_old_levels(P, rb, 0, kd, slot_n, depth);
+      const double val = at_old_levels(P, rb, kk, kd, slot_n, depth);
       if (v == 0) {
-        sm.atu[wv][s][tgt] = val;
-        sm.kl[wv][s][tgt] = (uint8_t)kd;
+        sm.atu[kk][wv][s][tgt] = val;
+        sm.kl[kk][wv][s][tgt] = (uint8_t)kd;
       } else if (v == 1) {
-        sm.atg[wv][s][tgt] = val;
+        sm.atg[kk][wv][s][tgt] = val;
       } else {
-        sm.atur[wv][s][tgt] = val;
-        sm.kr[wv][s][tgt] = (uint8_t)kd;
+        sm.atur[kk][wv][s][tgt] = val;
+        sm.kr[kk][wv][s][tgt] = (uint8_t)kd;
       }
     }
   }
@@ -402,42 +408,62 @@ __device__ __forceinline__ void wave_tile_ldg(const DevProblem& P, const WorkIte
   for (int j = 0; j < NP; ++j) y[j] = u0[j];
   const double nu = P.nu;
   const double dt = P.dt;
+  int slot_m = slot_n;
 #pragma unroll
-  for (int s = 0; s < S; ++s) {
-    const bool delayed = pe && sm.kl[wv][s][lane] != 0;
-    const int64_t rs = ((int64_t)b * S + s) * depth + slot_n;
-    const double um = lane_from_left(y[NP - 1]);  // u- at the left face, and its u-hat
-    double hl = um;
-    if (pe) {
-      if (owned) ring[P.ring2_off + rs] = um;
-      if (delayed) hl = sm.atu[wv][s][lane];
+  for (int kk = 0; kk < K; ++kk) {
+    if (kk > 0) {
+      slot_m = slot_m + 1 == depth ? 0 : slot_m + 1;
+#pragma unroll
+      for (int j = 0; j < NP; ++j) u0[j] = y[j];
     }
-    double hr = y[NP - 1];  // u-hat at the right face: this element's own trace
-    if (pe_r && sm.kr[wv][s][lane] != 0) hr = sm.atur[wv][s][lane];
 #pragma unroll
-    for (int i = 0; i < NP; ++i) {
-      double v = fma(-P.Kl[i], hl, P.Kr[i] * hr);
+    for (int s = 0; s < S; ++s) {
+      const int64_t rs = ((int64_t)b * S + s) * depth + slot_m;
+      const double um = lane_from_left(y[NP - 1]);  // u- at the left face, and its u-hat
+      double hl = um;
+      if (pe) {
+        if (owned) ring[P.ring2_off + rs] = um;
+        if constexpr (K == 2) {  // level n completes step n+1's u-hat sum when its delay is 1
+          if (kk == 0 && sm.kl[1][wv][s][lane] == 1) sm.atu[1][wv][s][lane] = fma(P.atc[1][0], um, sm.atu[1][wv][s][lane]);
+        }
+        if (sm.kl[kk][wv][s][lane] != 0) hl = sm.atu[kk][wv][s][lane];
+      }
+      double hr = y[NP - 1];  // u-hat at the right face: this element's own trace
+      if (pe_r) {
+        if constexpr (K == 2) {
+          if (kk == 0 && sm.kr[1][wv][s][lane] == 1)
+            sm.atur[1][wv][s][lane] = fma(P.atc[1][0], hr, sm.atur[1][wv][s][lane]);
+        }
+        if (sm.kr[kk][wv][s][lane] != 0) hr = sm.atur[kk][wv][s][lane];
+      }
 #pragma unroll
-      for (int j = 0; j < NP; ++j) v = fma(-P.Kd[i * kMaxNp + j], y[j], v);
-      q[i] = v;
+      for (int i = 0; i < NP; ++i) {
+        double v = fma(-P.Kl[i], hl, P.Kr[i] * hr);
+#pragma unroll
+        for (int j = 0; j < NP; ++j) v = fma(-P.Kd[i * kMaxNp + j], y[j], v);
+        q[i] = v;
+      }
+      double G = fma(-nu, q[0], Physics<PHYS_BURGERS_LLF>::fhat(um, y[0], 1.0));
+      if (pe) {
+        if (owned) ring[P.ring_off + rs] = G;
+        if constexpr (K == 2) {
+          if (kk == 0 && sm.kl[1][wv][s][lane] == 1) sm.atg[1][wv][s][lane] = fma(P.atc[1][0], G, sm.atg[1][wv][s][lane]);
+        }
+        if (sm.kl[kk][wv][s][lane] != 0) G = sm.atg[kk][wv][s][lane];
+      }
+      const double Gr = lane_from_right(G);
+      double g[NP];
+#pragma unroll
+      for (int j = 0; j < NP; ++j) g[j] = fma(0.5 * y[j], y[j], -nu * q[j]);
+#pragma unroll
+      for (int i = 0; i < NP; ++i) {
+        double v = fma(-P.Kr[i], Gr, P.Kl[i] * G);
+#pragma unroll
+        for (int j = 0; j < NP; ++j) v = fma(P.Kd[i * kMaxNp + j], g[j], v);
+        k[i] = v;
+      }
+      rk_update<NP, RK>(s, dt, u0, y, ks, k);
     }
-    double G = fma(-nu, q[0], Physics<PHYS_BURGERS_LLF>::fhat(um, y[0], 1.0));
-    if (pe) {
-      if (owned) ring[P.ring_off + rs] = G;
-      if (delayed) G = sm.atg[wv][s][lane];
-    }
-    const double Gr = lane_from_right(G);
-    double g[NP];
-#pragma unroll
-    for (int j = 0; j < NP; ++j) g[j] = fma(0.5 * y[j], y[j], -nu * q[j]);
-#pragma unroll
-    for (int i = 0; i < NP; ++i) {
-      double v = fma(-P.Kr[i], Gr, P.Kl[i] * G);
-#pragma unroll
-      for (int j = 0; j < NP; ++j) v = fma(P.Kd[i * kMaxNp + j], g[j], v);
-      k[i] = v;
-    }
-    rk_update<NP, RK>(s, dt, u0, y, ks, k);
   }
   if (owned) {
     double* __restrict__ uo = uout + P.u_off;
@@ -446,27 +472,31 @@ __device__ __forceinline__ void wave_tile_ldg(const DevProblem& P, const WorkIte
   }
 }
 
-template <int NP, int RK>
+template <int NP, int RK, int K>
 __global__ __launch_bounds__(kBlock) void k_fused_ldg(const DevProblem* __restrict__ probs,
                                                       const WorkItem* __restrict__ work,
                                                       const int64_t* __restrict__ ctr, double* __restrict__ ring,
                                                       int32_t w_begin, int32_t w_end, const double* __restrict__ uin,
                                                       double* __restrict__ uout, int32_t step_offset,
                                                       int32_t single_prob) {
-  __shared__ LdgSmem<rk_stages(RK)> sm;
+  __shared__ LdgSmem<rk_stages(RK), K> sm;
   const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
   const int lane = (int)(threadIdx.x % kWave);
   const int w = w_begin + xcd_block((int)blockIdx.x, (int)gridDim.x) * kWavesPerBlock + wv;
   if (w >= w_end) return;  // whole wave
   const int64_t n = ctr[0] + step_offset;
   const WorkItem wi = single_prob >= 0 ? WorkItem{single_prob, w - w_begin} : work[w];
-  wave_tile_ldg<NP, RK>(probs[wi.prob], wi, ring, n, uin, uout, sm, wv, lane);
+  wave_tile_ldg<NP, RK, K>(probs[wi.prob], wi, ring, n, uin, uout, sm, wv, lane);
 }
 
 template <int NP, int RK>
 static void fused_ldg_go(const StepArgs& a, int gi, const double* uin, double* uout, int32_t off, hipStream_t st) {
-  hipLaunchKernelGGL((k_fused_ldg<NP, RK>), dim3(a.grid[gi]), dim3(kBlock), 0, st, a.probs, a.work, a.ctr, a.ring,
-                     a.group[gi], a.group[gi + 1], uin, uout, off, a.single[gi]);
+  if (a.steps == 2)
+    hipLaunchKernelGGL((k_fused_ldg<NP, RK, 2>), dim3(a.grid[gi]), dim3(kBlock), 0, st, a.probs, a.work, a.ctr,
+                       a.ring, a.group[gi], a.group[gi + 1], uin, uout, off, a.single[gi]);
+  else
+    hipLaunchKernelGGL((k_fused_ldg<NP, RK, 1>), dim3(a.grid[gi]), dim3(kBlock), 0, st, a.probs, a.work, a.ctr,
+                       a.ring, a.group[gi], a.group[gi + 1], uin, uout, off, a.single[gi]);
 }
 
 template <int RK>
@@ -512,7 +542,7 @@ static void fused_phys(int phys, const StepArgs& a, const double* uin, double* u
     case PHYS_ADV_UPWIND: fused_np<RK, PHYS_ADV_UPWIND>(a, uin, uout, off, st); break;
     case PHYS_ADV_UPWIND_POS: fused_np<RK, PHYS_ADV_UPWIND_POS>(a, uin, uout, off, st); break;
     case PHYS_ADV_CENTRAL: fused_np<RK, PHYS_ADV_CENTRAL>(a, uin, uout, off, st); break;
-    case PHYS_BURGERS_LDG: fused_ldg_np<RK>(a, uin, uout, off, st); break;  // one step, one element per lane
+    case PHYS_BURGERS_LDG: fused_ldg_np<RK>(a, uin, uout, off, st); break;  // one element per lane
     default: fused_np<RK, PHYS_BURGERS_LLF>(a, uin, uout, off, st); break;
   }
 }

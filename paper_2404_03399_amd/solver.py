@@ -76,8 +76,8 @@ class Solver:
         if lane_elems == "auto":
             # elements per lane and (unless given) steps per launch, tuned together
             from . import autotune
-            fused = kernel in ("fused", "auto") and self.workloads[0].equation != "viscous_burgers"
-            lane_elems, k = autotune.tune(self.workloads) if fused else (0, 0)  # local DG: one shape
+            fused = kernel in ("fused", "auto")
+            lane_elems, k = autotune.tune(self.workloads) if fused else (0, 0)
             fused_steps = fused_steps or k
         self.opt.lane_elems = int(lane_elems)
         self.opt.fused_steps = int(fused_steps)

@@ -118,3 +118,28 @@ def test_ldg_fused_equals_stage(torch_cuda, p, rk, scheme, q, per_stage):
     ref = stepper.Stepper(w).run(u0, n)
     assert stats.rel_l2(out["fused"], ref) <= 1e-12
     assert stats.rel_l2(d_f, ref - u0) <= 1e-9
+
+
+@pytest.mark.parametrize("p,rk,scheme,q,per_stage,ne,pe", [
+    (2, "heun", "adg_at", 2, False, 300, 20), (1, "rk4", "adg_at", 0, True, 130, 13),
+    (3, "ssprk3", "adg", 0, True, 97, 1), (2, "lsrk3", "adg_at", 3, False, 200, 8), (4, "heun", "dg", 0, False, 64, 16)])
+def test_ldg_two_steps_per_launch_bitwise(torch_cuda, p, rk, scheme, q, per_stage, ne, pe):
+    """Two time steps per fused local DG launch (halo 2S; the second step's AT
+    sums formed from the ring plus each lane's own level-n values) give
+    bitwise the one-step results, and both match the oracle."""
+    from paper_2404_03399_amd.solver import Solver
+    w = _w(p, rk, scheme, q, per_stage, ne=ne, pe=pe, seed=ne + p)
+    u0 = stepper.initial_state(w)
+    _say(f"viscous Burgers LDG two-step launches p={p} {rk} {scheme} q={q} N={ne} pe={pe}")
+    out = {}
+    for K in (1, 2):
+        for n, graph in ((19, False), (32, True)):
+            s = Solver(w, fused_steps=K)
+            u = s.pack(u0)
+            s.run(u, n, graph=graph)
+            torch_cuda.cuda.synchronize()
+            out[K, n] = s.unpack(u)[0]
+            s.close()
+    assert np.array_equal(out[1, 19], out[2, 19])
+    assert np.array_equal(out[1, 32], out[2, 32])
+    assert stats.rel_l2(out[2, 19], stepper.Stepper(w).run(u0, 19)) <= 1e-12

@@ -106,13 +106,14 @@ def test_viscous_burgers_options(L):
     opt = adg.adg_options()
     opt.kernel = adg.KERNEL["stage"]
     assert adg.adg_workspace_size([p], opt) > fused                     # the q pass needs a buffer
-    for field, value in (("lane_elems", 2), ("fused_steps", 2)):       # one element per lane, one step
-        opt = adg.adg_options()
-        opt.kernel = adg.KERNEL["fused"]
-        setattr(opt, field, value)
-        with pytest.raises(adg.AdgError) as ei:
-            adg.adg_workspace_size([p], opt)
-        assert ei.value.code == adg.ADG_E_UNSUPPORTED
+    opt = adg.adg_options()
+    opt.kernel = adg.KERNEL["fused"]
+    opt.fused_steps = 1
+    assert adg.adg_workspace_size([p], opt) > 0                         # one or two steps per launch
+    opt.lane_elems = 2                                                  # one element per lane only
+    with pytest.raises(adg.AdgError) as ei:
+        adg.adg_workspace_size([p], opt)
+    assert ei.value.code == adg.ADG_E_UNSUPPORTED
     with pytest.raises(adg.AdgError) as ei:
         adg.adg_workspace_size([p], adg.adg_options(), 10)             # no adjoint for local DG
     assert ei.value.code == adg.ADG_E_UNSUPPORTED
