@@ -226,6 +226,7 @@ def bench_experiments():
     f10b = X.error_vs_delay("at4", n_elem=128, delay_counts=(1, 2, 3, 4))
     caa = X.error_caa("at2")
     vb = X.viscous_burgers_convergence()
+    bc = X.burgers_convergence()
     def slim(r):
         return {k: r[k] for k in ("n_elem", "n_pe", "delay_counts", "mean", "delay_moment", "stable", "fit")}
     return {"wall_s": time.perf_counter() - t0, "n_real": f9a["n_real"],
@@ -237,7 +238,27 @@ def bench_experiments():
             "fig10_at2": slim(f10a), "fig10_at4": slim(f10b),
             "caa_at2": {k: caa[k] for k in ("n_elems", "order_caa", "order_dg", "ratio_to_dg")},
             "fig11_viscous_burgers": {k: vb[k] for k in ("n_elems", "n_ref", "t_final", "dg", "adg_at",
-                                                           "order_dg", "order_adg_at")}}
+                                                           "order_dg", "order_adg_at")},
+            "burgers_to_half": {k: bc[k] for k in ("n_elems", "t_final", "n_pe", "dg", "adg_at",
+                                                    "order_dg", "order_adg_at")}}
+
+
+def bench_burgers(torch, W, Solver, n_elem: int = 1 << 22, steps: int = 200):
+    """Full-size inviscid Burgers window: 2^22 elements, p=2, LLF, ADG-AT
+    (q=3), SSP-RK3, 16384 PEs of 256, on the fused kernel at its tuned shape."""
+    w = W.c3_burgers(n_elem=n_elem, n_steps=steps)
+    s = Solver(w, lane_elems="auto")
+    K, R = s.opt.fused_steps or 2, s.opt.lane_elems or 1
+    u = s.initial_state()
+    g, _ = time_solver(torch, s, u, steps, 20)
+    finite = bool(torch.isfinite(u).all().item())
+    s.close()
+    dofs = w.n_elem * (w.degree + 1)
+    rate = dofs * 3 * steps / g
+    step_bytes = BYTES_PER_DOF_STEP_FUSED * dofs / K + ring_bytes_per_step(w)
+    return {"workload": f"Burgers LLF ADG-AT(q=3) SSP-RK3, N_E={n_elem}, p=2, PE size 256", "lane_elems": R,
+            "steps_per_launch": K, "dof_stage_per_s": rate, "us_per_step": g / steps * 1e6,
+            "hbm_frac": step_bytes / (g / steps) / 1e9 / HBM_PEAK_GBS, "state_finite": finite}
 
 
 # Local DG per-stage kernels, Heun: q pass reads Y and writes q (16 B/DOF);
@@ -470,6 +491,7 @@ def main():
     if not args.no_experiments:
         out["experiments"] = bench_experiments()
         out["viscous_burgers"] = bench_viscous_burgers(torch, W, Solver)
+        out["burgers"] = bench_burgers(torch, W, Solver)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
         out["cpu_baseline"]["host"] = {"cpu_count": os.cpu_count()}

@@ -31,6 +31,7 @@ import json
 import math
 import sys
 import time
+from dataclasses import replace
 from fractions import Fraction
 from typing import Dict, List, Sequence
 
@@ -225,13 +226,40 @@ def viscous_burgers_convergence(n_elems=(32, 64, 128), ref_factor: int = 8, t_fi
     return out
 
 
+def burgers_convergence(n_elems=(256, 512, 1024, 2048, 4096), t_final: float = 0.5, n_pe: int = 16,
+                        sigma: float = 0.01) -> dict:
+    """Inviscid Burgers of the full-size Burgers configuration (p = 2, LLF,
+    SSP-RK3, u0 = 0.5 + sin x, delays {0..3}, AT3) run to t_final before the
+    shock on small meshes with n_pe PEs: mean |u - u_exact| at the nodes for
+    synchronous DG and ADG-AT, and their orders in N_E."""
+    from .solver import Solver
+
+    out = {"n_elems": list(n_elems), "t_final": t_final, "n_pe": n_pe, "sigma": sigma}
+    for scheme in ("dg", "adg_at"):
+        errs = []
+        for ne in n_elems:
+            dt, n = W.time_step(W.TWO_PI, ne, sigma, 1.5, t_final)
+            w = replace(W.c3_burgers(n_elem=ne, n_steps=n, sigma=sigma, scheme=scheme), dt=dt, pe_size=ne // n_pe)
+            s = Solver(w)
+            try:
+                u = s.initial_state()
+                s.run(u, n, graph=True)
+                errs.append(float(s.error_stats(u, s.exact_burgers_state(t_final))[0][0]))
+            finally:
+                s.close()
+        out[scheme] = errs
+        out["order_" + scheme] = loglog_slope(n_elems, errs)
+    return out
+
+
 def main(argv=None) -> int:
     t0 = time.perf_counter()
     out = {"error_vs_pe": [error_vs_pe("at2", n_elems=(64, 128, 256, 512, 1024)),
                            error_vs_pe("at4", n_elems=(64, 128, 256, 512))],
            "error_vs_delay": [error_vs_delay("at2", n_elem=512), error_vs_delay("at4", n_elem=128)],
            "communication_avoiding": [error_caa("at2"), error_caa("at4", n_elems=(64, 128, 256, 512))],
-           "viscous_burgers": viscous_burgers_convergence()}
+           "viscous_burgers": viscous_burgers_convergence(),
+           "burgers": burgers_convergence()}
     out["wall_s"] = time.perf_counter() - t0
     print(json.dumps(out))
     return 0

@@ -189,6 +189,38 @@ class Solver:
             self.view(u, i).copy_(v)
         return u
 
+    def exact_burgers_state(self, t: float, iters: int = 60) -> torch.Tensor:
+        """Nodal values of the inviscid Burgers solution before the first
+        shock, u(x, t) = u0(xi) with x = xi + u0(xi) t, by Newton's method on
+        the characteristic foot xi (raises once characteristics cross)."""
+        u = self.empty_state()
+        for i, w in enumerate(self.workloads):
+            x = self.nodes(i)
+
+            def u0(z):
+                v = torch.full_like(z, w.ic.offset)
+                for k, a, ph in zip(w.ic.kappa, w.ic.amp, w.ic.phase):
+                    v = v + a * torch.sin(k * z + ph)
+                return v
+
+            def du0(z):
+                v = torch.zeros_like(z)
+                for k, a, ph in zip(w.ic.kappa, w.ic.amp, w.ic.phase):
+                    v = v + a * k * torch.cos(k * z + ph)
+                return v
+
+            xi = x - u0(x) * t
+            for _ in range(iters):
+                dg = 1.0 + du0(xi) * t
+                if bool((dg <= 0).any()):
+                    raise ValueError("characteristics crossed: a shock has formed")
+                step = (xi + u0(xi) * t - x) / dg
+                xi = xi - step
+                if float(step.abs().max()) < 1e-15 * (1.0 + float(x.abs().max())):
+                    break
+            self.view(u, i).copy_(u0(xi))
+        return u
+
     def delay_schedule(self, i: int, step0: int, n_steps: int):
         w = self.workloads[i]
         return adg.adg_delay_schedule(self.probs[i], step0, n_steps, adg.RK_STAGES[w.rk], w.n_pe)
