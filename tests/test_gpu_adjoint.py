@@ -259,3 +259,35 @@ def test_full_size_dot_product_and_speed_fd(torch_cuda):
     fd = (J(1.0 + h) - J(1.0 - h)) / (2 * h)
     assert abs(ga[0] - fd) <= 1e-6 * max(1.0, abs(fd)), (ga[0], fd)
     s.close()
+
+
+def test_burgers_gradient_against_central_difference(torch_cuda):
+    """Burgers (p=2, LLF, ADG-AT q=3, SSP-RK3) on 2^10 elements over 100
+    steps, checkpoint every 16: <dJ/du0, v> against a central difference of
+    the GPU forward map along a random direction v, J = 1/2 ||u(T)||^2."""
+    torch = torch_cuda
+    from paper_2404_03399_amd.solver import Solver
+    w = replace(W.c5_adjoint_burgers(n_elem=1 << 10, n_steps=100), pe_size=64)
+    n = 100
+    rng = np.random.default_rng(1)
+    _say("Burgers gradient vs central difference, N=1024, 100 steps")
+    s = Solver(w, n_steps_record=n, ckpt_every=16)
+    u0 = s.initial_state()
+    v = s.pack(rng.standard_normal((w.n_elem, w.degree + 1)))
+    u = u0.clone()
+    s.run(u, n, graph=True, record=True)
+    g, _ = s.adjoint(u.clone(), want_speed=False)
+    torch.cuda.synchronize()
+    s.close()
+
+    def J(x0):
+        so = Solver(w)
+        uu = x0.clone()
+        so.run(uu, n, graph=True)
+        torch.cuda.synchronize()
+        so.close()
+        return 0.5 * float((uu * uu).sum())
+    h = 1e-6
+    fd = (J(u0 + h * v) - J(u0 - h * v)) / (2 * h)
+    ad = float((g * v).sum())
+    assert abs(ad - fd) <= 1e-6 * max(1.0, abs(fd)), (ad, fd)
