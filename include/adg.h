@@ -127,8 +127,8 @@ typedef struct adg_options {
                                   asynchronous problem's pe_size); 0 -> 1 */
   uint32_t flags;              /* reserved, 0 */
   uint32_t fused_steps;        /* fused kernel: time steps per launch, 1 or 2 (halo of 2S elements per side,
-                                  half the state traffic per step); 0 -> 2.  Results are bitwise the same
-                                  with lane_elems 1, equal to rounding otherwise. */
+                                  half the state traffic per step); 0 -> 2.  Every (lane_elems,
+                                  fused_steps) pair gives bitwise the same results. */
 } adg_options;
 
 typedef struct adg_ctx adg_ctx;  /* opaque, host side, library owned */

@@ -8,8 +8,8 @@ traffic per step at the price of a wider halo.  The tuner times each
 admissible pair on the caller's own problems (same kernels, a few
 graph-replayed steps on a scratch copy of the initial state) and caches the
 winner in a JSON file keyed by device, integrator, equation/flux, degrees
-and size.  Every pair agrees with the others to rounding (bitwise across
-steps per launch with one element per lane).
+and size.  Every pair gives bitwise the same states (the kernels use
+explicit FMAs with contraction off), so tuning never changes results.
 
     R, K = autotune.tune(workloads)               # tuned (or cached) pair
     R = autotune.lane_elems(workloads)            # its elements per lane

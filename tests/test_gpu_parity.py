@@ -447,3 +447,25 @@ def test_autotuned_lane_elems(torch_cuda, tmp_path, monkeypatch):
     assert len(cache) == 1 and list(cache.values())[0]["lane_elems"] == r
     assert autotune.lane_elems(w) == r
     _check(torch_cuda, w, 12, "fused", graph=True, lane_elems=r)
+
+
+@pytest.mark.parametrize("ne,pe,p,rk,phys", [(1000, 40, 3, "rk4", "upwind"), (1001, 77, 2, "ssprk3", "central"),
+                                             (640, 8, 1, "heun", "llf"), (512, 16, 4, "lsrk3", "upwind")])
+def test_every_launch_shape_bitwise(torch_cuda, ne, pe, p, rk, phys):
+    """Elements per lane R in {1, 2, 4} and steps per launch K in {1, 2}:
+    every multiply-add is an explicit FMA with contraction off, so all six
+    launch shapes give bitwise the same states."""
+    eq = "burgers" if phys == "llf" else "advection"
+    ic = W.MultiSine((1, 2), (1.0, 0.5), (0.3, 0.9), offset=0.5 if eq == "burgers" else 0.0)
+    sig = {1: 0.05, 2: 0.01, 3: 0.005, 4: 0.001}[p]
+    w = W.Workload(name=f"shape_{ne}", equation=eq, flux=phys, rk=rk, degree=p, n_elem=ne, pe_size=pe,
+                   probs=W.DELAYS_C2, seed=9 + ne, per_stage=True, ic=ic,
+                   dt=sig * W.TWO_PI / ne / (1.5 if eq == "burgers" else 1.0))
+    u0 = stepper.initial_state(w)
+    n = 15
+    _say(f"launch shapes bitwise: N={ne} pe={pe} p={p} {rk} {phys} steps={n}")
+    outs = [gpu_run(torch_cuda, w, u0, n, "fused", graph=False, lane_elems=R, fused_steps=K)
+            for R in (1, 2, 4) for K in (1, 2) if R <= pe]
+    for o in outs[1:]:
+        assert np.array_equal(outs[0], o)
+    assert stats.rel_l2(outs[0], oracle_run(w, u0, n)) <= TOL
