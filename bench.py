@@ -93,6 +93,22 @@ def time_solver(torch, solver, u, steps, warmup, graph=True):
     return ev0.elapsed_time(ev1) / 1e3, wall
 
 
+def run_metrics(torch, s, w, u, n_done: int, sample_steps: int = 64):
+    """Per-run metrics of the timed forward run: drift of the discrete
+    integral of u over the run (conservation), and the histogram of the
+    clamped delays the kernels draw, over the first sample_steps steps, beside
+    the probabilities asked for."""
+    import numpy as np
+    u0 = s.initial_state()
+    i0 = s.error_stats(u0, u0)[0][2]
+    i1 = s.error_stats(u, u)[0][2]
+    k = np.asarray(s.delay_schedule(0, 1000, sample_steps))  # past the start-up clamp
+    counts = np.bincount(k.ravel(), minlength=w.n_delays)
+    return {"steps": n_done, "integral_start": i0, "integral_end": i1, "integral_drift": abs(i1 - i0),
+            "delay_histogram": {"sample_steps": sample_steps, "draws": int(k.size),
+                                "fraction": (counts / k.size).tolist(), "asked": [float(p) for p in w.probs]}}
+
+
 def cpu_baseline(w, steps: int):
     """The FP64 oracle on a bounded window of the same workload, one thread."""
     from threadpoolctl import threadpool_limits
@@ -447,6 +463,7 @@ def main():
         "roofline": roof,
         "wall_s": wall,
         "state_finite": finite,
+        "run_metrics": run_metrics(torch, s, w, u, args.warmup + args.steps),
     }
     if args.extras:
         ex = {}

@@ -66,7 +66,9 @@ _LIB = None
 
 
 def library_path() -> str:
-    return _build.LIB
+    """The in-tree libadg.so, or the build named by ADG_LIBRARY (e.g. the
+    host-AddressSanitizer build)."""
+    return os.environ.get("ADG_LIBRARY") or _build.LIB
 
 
 def lib() -> C.CDLL:

@@ -1,6 +1,8 @@
 """Build the HIP library libadg.so for gfx950 (in-tree, no JIT cache).
 
     python -m paper_2404_03399_amd.build
+
+build_asan.py builds a variant with the host code under AddressSanitizer.
 """
 from __future__ import annotations
 
@@ -53,26 +55,29 @@ def _run(cmd, verbose):
         print(res.stderr, file=sys.stderr)
 
 
-def build(verbose: bool = False, jobs: int = 0) -> str:
-    """Compile every unit to an object (in parallel), then link libadg.so."""
+def build(verbose: bool = False, jobs: int = 0, extra=(), libdir: str = LIBDIR) -> str:
+    """Compile every unit to an object (in parallel), then link libdir/libadg.so
+    (extra: more compiler options for every unit)."""
     from concurrent.futures import ThreadPoolExecutor
-    objdir = os.path.join(LIBDIR, "obj")
+    lib = os.path.join(libdir, "libadg.so")
+    objdir = os.path.join(libdir, "obj")
     os.makedirs(objdir, exist_ok=True)
     cc = hipcc()
+    extra = list(extra)
     objs, cmds = [], []
     for src, defs in UNITS:
         tag = "".join(d.split("=")[-1] for d in defs if d.startswith("-D"))
         obj = os.path.join(objdir, os.path.splitext(src)[0] + (f"_{tag}" if tag else "") + ".o")
         objs.append(obj)
-        cmds.append([cc] + flags() + defs + ["-c", os.path.join(CSRC, src), "-o", obj])
+        cmds.append([cc] + flags() + extra + defs + ["-c", os.path.join(CSRC, src), "-o", obj])
     jobs = jobs or max(1, min(len(cmds), (os.cpu_count() or 2) - 1))
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         for f in [ex.submit(_run, c, verbose) for c in cmds]:
             f.result()
-    tmp = LIB + ".tmp"
+    tmp = lib + ".tmp"
     _run([cc, f"--offload-arch={ARCH}", "-shared", "-fPIC"] + objs + ["-o", tmp], verbose)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":

@@ -469,3 +469,25 @@ def test_every_launch_shape_bitwise(torch_cuda, ne, pe, p, rk, phys):
     for o in outs[1:]:
         assert np.array_equal(outs[0], o)
     assert stats.rel_l2(outs[0], oracle_run(w, u0, n)) <= TOL
+
+
+@pytest.mark.parametrize("p,rk,sig,probs", [(1, "rk4", 0.05, ("0", "0", "0", "1")),
+                                            (2, "ssprk3", 0.01, ("0", "0", "1")),
+                                            (3, "rk4", 0.005, ("0", "0", "0", "1"))])
+def test_worst_case_delays(torch_cuda, p, rk, sig, probs):
+    """Every face at the largest delay L-1 at every step and stage (after the
+    start-up clamp): the deepest ring levels and the largest AT weights, on
+    both kernel families, against the oracle."""
+    ne = 200
+    w = W.Workload(name=f"worst_{p}", degree=p, rk=rk, n_elem=ne, pe_size=20, probs=probs, seed=1,
+                   per_stage=True, dt=sig * W.TWO_PI / ne, ic=W.PAPER_MULTISINE)
+    from paper_2404_03399_amd.solver import Solver
+    s = Solver(w)
+    k = np.asarray(s.delay_schedule(0, 0, 40))
+    s.close()
+    q, L = p + 1, len(probs)
+    for n in range(40):  # k = min(L - 1, max(0, n - q + 1)): the clamp only at the start
+        assert (k[n] == min(L - 1, max(0, n - q + 1))).all(), n
+    _say(f"worst-case delays: p={p} {rk} L={len(probs)} N={ne} steps=60")
+    for kernel in ("fused", "stage"):
+        _check(torch_cuda, w, 60, kernel, graph=True)
