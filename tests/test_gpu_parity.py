@@ -471,13 +471,18 @@ def test_every_launch_shape_bitwise(torch_cuda, ne, pe, p, rk, phys):
     assert stats.rel_l2(outs[0], oracle_run(w, u0, n)) <= TOL
 
 
-@pytest.mark.parametrize("p,rk,sig,probs", [(1, "rk4", 0.05, ("0", "0", "0", "1")),
-                                            (2, "ssprk3", 0.01, ("0", "0", "1")),
-                                            (3, "rk4", 0.005, ("0", "0", "0", "1"))])
-def test_worst_case_delays(torch_cuda, p, rk, sig, probs):
+@pytest.mark.parametrize("p,rk,sig,probs,tol", [(1, "rk4", 0.05, ("0", "0", "0", "1"), TOL),
+                                                (2, "ssprk3", 0.01, ("0", "0", "1"), TOL),
+                                                (3, "rk4", 0.005, ("0", "0", "0", "1"), 1e-9)])
+def test_worst_case_delays(torch_cuda, p, rk, sig, probs, tol):
     """Every face at the largest delay L-1 at every step and stage (after the
     start-up clamp): the deepest ring levels and the largest AT weights, on
-    both kernel families, against the oracle."""
+    both kernel families, against the oracle.  With q = 4 at delay 3 the AT
+    weights are (20, -45, 36, -10): each combination multiplies rounding
+    differences by up to 111, and over 60 steps of every face at that delay
+    they reach 1e-10 relative; the bar 1e-9 stays two orders below the
+    change from taking the weights of q = 3 or the level of delay 2 instead
+    (2.3e-7 here, in the oracle)."""
     ne = 200
     w = W.Workload(name=f"worst_{p}", degree=p, rk=rk, n_elem=ne, pe_size=20, probs=probs, seed=1,
                    per_stage=True, dt=sig * W.TWO_PI / ne, ic=W.PAPER_MULTISINE)
@@ -490,4 +495,4 @@ def test_worst_case_delays(torch_cuda, p, rk, sig, probs):
         assert (k[n] == min(L - 1, max(0, n - q + 1))).all(), n
     _say(f"worst-case delays: p={p} {rk} L={len(probs)} N={ne} steps=60")
     for kernel in ("fused", "stage"):
-        _check(torch_cuda, w, 60, kernel, graph=True)
+        _check(torch_cuda, w, 60, kernel, graph=True, tol=tol)
