@@ -757,16 +757,25 @@ int adg_run(adg_ctx* c, double* d_u, int64_t n_steps, uint32_t flags) {
     int rc;
     if (C == 1 && c->kernel == ADG_KERNEL_FUSED) {
       // every state is kept: each step writes its result straight into the
-      // next checkpoint slot (the last one into d_u), no copies
+      // next checkpoint slot (the last one into d_u), no copies; two steps per
+      // launch where the context runs two, the launch writing both states
       double* ck = (double*)(c->ws + c->L.ckpt);
       ADG_HIP(hipMemcpyAsync(ck, d_u, 8 * tot, hipMemcpyDeviceToDevice, c->stream));
       const StepArgs fa = c->fused_args();
+      auto slot = [&](int64_t j) { return j < n_steps ? ck + tot * j : d_u; };
       while (done < n_steps) {
         const int32_t m = (int32_t)std::min<int64_t>(n_steps - done, kGraphSteps);
-        for (int32_t i = 0; i < m; ++i) {
+        for (int32_t i = 0; i < m;) {
           const int64_t n = done + i;
-          double* dst = n + 1 < n_steps ? ck + tot * (n + 1) : d_u;
-          ADG_HIP(launch_fused_step(c->rk, c->fused_phys, fa, ck + tot * n, dst, i, c->stream));
+          if (c->fused_steps == 2 && i + 1 < m) {
+            StepArgs f2 = c->fused_args(2);
+            f2.umid = slot(n + 1);
+            ADG_HIP(launch_fused_step(c->rk, c->fused_phys, f2, ck + tot * n, slot(n + 2), i, c->stream));
+            i += 2;
+          } else {
+            ADG_HIP(launch_fused_step(c->rk, c->fused_phys, fa, ck + tot * n, slot(n + 1), i, c->stream));
+            i += 1;
+          }
         }
         ADG_HIP(launch_advance((int64_t*)(c->ws + c->L.ctr), m, c->stream));
         done += m;
