@@ -267,6 +267,35 @@ def test_step_by_step_equals_run(torch_cuda):
     s.close()
 
 
+@pytest.mark.parametrize("scheme,q", [("adg_at", 0), ("adg", 0), ("adg_at", 1)])
+def test_mixed_calls_keep_the_records(torch_cuda, scheme, q):
+    """Single steps, odd and even runs and graph replays interleaved in one
+    context (one-step and two-step launches starting at odd and even step
+    indices, the PE-face records handed over between them) equal one
+    uninterrupted run bitwise; q = 1 exercises a delay of 1 at step 1."""
+    torch = torch_cuda
+    from paper_2404_03399_amd.solver import Solver
+    w = replace(W.c2_advection_large(scheme, n_elem=4096), pe_size=64, at_levels=q)
+    u0 = stepper.initial_state(w)
+    _say(f"mixed adg_step / adg_run calls, {scheme} q={q}")
+    s = Solver(w)
+    u = s.pack(u0)
+    plan = [("step", 1), ("run", 3), ("step", 1), ("run", 4), ("graph", 17), ("step", 1), ("run", 5), ("graph", 33)]
+    for kind, m in plan:
+        if kind == "step":
+            s.step(u)
+        else:
+            s.run(u, m, graph=(kind == "graph"))
+    torch.cuda.synchronize()
+    total = sum(m for _, m in plan)
+    assert s.steps_taken() == total
+    a = s.unpack(u)[0]
+    s.close()
+    b = gpu_run(torch, w, u0, total, "fused", graph=False)
+    assert np.array_equal(a, b)
+    assert stats.rel_l2(a, oracle_run(w, u0, total)) <= TOL
+
+
 # ---- full sizes, bench launch configuration -----------------------------------
 def test_c2_full_size_window(torch_cuda):
     w = W.c2_advection_large("adg_at")
