@@ -142,15 +142,93 @@ __global__ __launch_bounds__(kBlock) void k_adj_stage(const DevProblem* __restri
   }
 }
 
+// One reverse RK step of a lane's element in Butcher form: lamp = lambda^{m+1}
+// in, lu = lambda^m out, keep = the forward stage values (FWD).  On a lane
+// whose left face is a PE face, kd(s) and adjn(s) give the face's delay at
+// (m, s) and the adjoint already collected for its level-m raw flux, and
+// on_lf(s, lf) receives the face sensitivity to scatter.  Returns the lane's
+// dJ/da share (FWD, advection, owned lanes).  Explicit FMAs with contraction
+// off: every kernel that reverses a step does it with the same roundings.
+template <int NP, int RK, int PHYS, bool FWD, class KdF, class AdjF, class LfF>
+__device__ __forceinline__ double adj_reverse(const DevProblem& P, const double (&lamp)[NP], double (&lu)[NP],
+                                              const double (&keep)[rk_stages(RK)][NP], bool pe, bool owned,
+                                              KdF kd_of, AdjF adjn_of, LfF on_lf) {
+#pragma clang fp contract(off)
+  constexpr int S = rk_stages(RK);
+  const double a = P.speed, dt = P.dt;
+  double Q[S][NP];
+#pragma unroll
+  for (int j = 0; j < NP; ++j) lu[j] = lamp[j];
+#pragma unroll
+  for (int s = 0; s < S; ++s)
+#pragma unroll
+    for (int j = 0; j < NP; ++j) Q[s][j] = 0.0;
+  double ca = 0.0;
+#pragma unroll
+  for (int s = S - 1; s >= 0; --s) {
+    double lk[NP];
+    const double bs = dt * bt_b<RK>(s);
+#pragma unroll
+    for (int i = 0; i < NP; ++i) lk[i] = s < S - 1 ? fma(bs, lamp[i], dt * Q[s][i]) : bs * lamp[i];
+    double cl = 0.0, cr = 0.0;
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+      cl = fma(P.Kl[i], lk[i], cl);
+      cr = fma(P.Kr[i], lk[i], cr);
+    }
+    // sensitivity of the flux applied at the left face (both neighbours' lifts)
+    const double lf = cl - lane_from_left(cr);
+    double dm, dp;
+    if constexpr (PHYS == PHYS_BURGERS_LLF)
+      flux_partials<PHYS>(lane_from_left(keep[s][NP - 1]), keep[s][0], a, dm, dp);
+    else
+      flux_partials<PHYS>(0.0, 0.0, a, dm, dp);
+    double raw = lf;
+    if (pe) {
+      const int kk = kd_of(s);
+      raw = (kk == 0 ? lf : 0.0) + adjn_of(s);
+      on_lf(s, lf);
+    }
+    double mu[NP];
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+      double v = 0.0;
+#pragma unroll
+      for (int i = 0; i < NP; ++i) v = fma(P.Kd[i * kMaxNp + j], lk[i], v);
+      if constexpr (PHYS == PHYS_BURGERS_LLF)
+        mu[j] = (2.0 * keep[s][j]) * v;
+      else
+        mu[j] = v;
+    }
+    mu[0] = fma(raw, dp, mu[0]);
+    mu[NP - 1] += lane_from_right(raw * dm);  // the right face is the next lane's left face
+#pragma unroll
+    for (int j = 0; j < NP; ++j) lu[j] += mu[j];
+#pragma unroll
+    for (int i = 0; i < s; ++i) {
+      const double c = bt_a<RK>(s, i);
+      if (c != 0.0)
+#pragma unroll
+        for (int j = 0; j < NP; ++j) Q[i][j] = fma(c, mu[j], Q[i][j]);
+    }
+    if constexpr (FWD && PHYS != PHYS_BURGERS_LLF) {
+      if (owned)
+#pragma unroll
+        for (int i = 0; i < NP; ++i) ca = fma(lk[i], keep[s][i], ca);
+    }
+  }
+  return ca;
+}
+
 // Per-lane PE-face values of a reverse step (lane = the PE lane they belong
-// to): delay, AT sum of past levels (forward recompute), adjoint already
-// collected for the level-n raw flux, and the flux sensitivity to scatter.
+// to): delay, AT sum of past levels (forward recompute), and the adjoint
+// already collected for the level-n raw flux, replaced once read by the flux
+// sensitivity to scatter.
 template <int S>
 struct AdjSmem {
   uint8_t kd[kWavesPerBlock][S][kWave];
   double atf[kWavesPerBlock][S][kWave];
   double adjn[kWavesPerBlock][S][kWave];
-  double lf[kWavesPerBlock][S][kWave];
 };
 
 // ------------------------------------------------------ fused adjoint step ---
@@ -244,67 +322,10 @@ __device__ __forceinline__ void adj_tile(const DevProblem& P, const WorkItem wi,
   }
 
   // reverse stages
-  double lu[NP], Q[S][NP];
-#pragma unroll
-  for (int j = 0; j < NP; ++j) lu[j] = lamp[j];
-#pragma unroll
-  for (int s = 0; s < S; ++s)
-#pragma unroll
-    for (int j = 0; j < NP; ++j) Q[s][j] = 0.0;
-  double ca = 0.0;
-#pragma unroll
-  for (int s = S - 1; s >= 0; --s) {
-    double lk[NP];
-    const double bs = dt * bt_b<RK>(s);
-#pragma unroll
-    for (int i = 0; i < NP; ++i) lk[i] = s < S - 1 ? bs * lamp[i] + dt * Q[s][i] : bs * lamp[i];
-    double cl = 0.0, cr = 0.0;
-#pragma unroll
-    for (int i = 0; i < NP; ++i) {
-      cl += P.Kl[i] * lk[i];
-      cr += P.Kr[i] * lk[i];
-    }
-    // sensitivity of the flux applied at the left face (both neighbours' lifts)
-    const double lf = cl - lane_from_left(cr);
-    double dm, dp;
-    if constexpr (PHYS == PHYS_BURGERS_LLF)
-      flux_partials<PHYS>(lane_from_left(kept(s, NP - 1)), kept(s, 0), a, dm, dp);
-    else
-      flux_partials<PHYS>(0.0, 0.0, a, dm, dp);
-    double raw = lf;
-    if (pe) {
-      const int kk = sm.kd[wv][s][lane];
-      raw = (kk == 0 ? lf : 0.0) + sm.adjn[wv][s][lane];
-      sm.lf[wv][s][lane] = lf;  // scattered at the end when delayed
-    }
-    double mu[NP];
-#pragma unroll
-    for (int j = 0; j < NP; ++j) {
-      double v = 0.0;
-#pragma unroll
-      for (int i = 0; i < NP; ++i) v += P.Kd[i * kMaxNp + j] * lk[i];
-      if constexpr (PHYS == PHYS_BURGERS_LLF)
-        mu[j] = 2.0 * kept(s, j) * v;
-      else
-        mu[j] = v;
-    }
-    mu[0] += raw * dp;
-    mu[NP - 1] += lane_from_right(raw * dm);  // the right face is the next lane's left face
-#pragma unroll
-    for (int j = 0; j < NP; ++j) lu[j] += mu[j];
-#pragma unroll
-    for (int i = 0; i < s; ++i) {
-      const double c = bt_a<RK>(s, i);
-      if (c != 0.0)
-#pragma unroll
-        for (int j = 0; j < NP; ++j) Q[i][j] += c * mu[j];
-    }
-    if constexpr (FWD && PHYS != PHYS_BURGERS_LLF) {
-      if (owned)
-#pragma unroll
-        for (int i = 0; i < NP; ++i) ca += lk[i] * kept(s, i);
-    }
-  }
+  double lu[NP];
+  const double ca = adj_reverse<NP, RK, PHYS, FWD>(
+      P, lamp, lu, keep, pe, owned, [&](int s) { return (int)sm.kd[wv][s][lane]; },
+      [&](int s) { return sm.adjn[wv][s][lane]; }, [&](int s, double lf) { sm.adjn[wv][s][lane] = lf; });
 
   double* __restrict__ lo = lamo + P.u_off;
   if (owned)
@@ -325,7 +346,7 @@ __device__ __forceinline__ void adj_tile(const DevProblem& P, const WorkItem wi,
       const int kk = sm.kd[wv][s][tgt];
       if (kk > 0 && j < P.q) {
         double* __restrict__ at = adjring + P.ring_off + ((int64_t)face * S + s) * depth + ring_slot(slot_n, kk + j, depth);
-        *at = fma(P.atc[kk][j], sm.lf[wv][s][tgt], *at);
+        *at = fma(P.atc[kk][j], sm.adjn[wv][s][tgt], *at);
       }
     }
   }
@@ -334,10 +355,130 @@ __device__ __forceinline__ void adj_tile(const DevProblem& P, const WorkItem wi,
   // advection, so dK/da = K / a with the stage inputs held fixed.  Fixed
   // butterfly order: deterministic.
   if constexpr (FWD && PHYS != PHYS_BURGERS_LLF) {
+    double cs = ca;
 #pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) ca += __shfl_xor(ca, o, kWave);
-    if (lane == 0) cpart[w] += ca / a;
+    for (int o = kWave / 2; o > 0; o >>= 1) cs += __shfl_xor(cs, o, kWave);
+    if (lane == 0) cpart[w] += cs / a;
   }
+}
+
+// Two reverse steps per launch without the forward stages (linear
+// advection, dJ/du0 only): lambda^n from lambda^{n+2}, halo 2S lanes.  Step
+// n+1 is reversed first.  Its PE-face sensitivity with delay 1 lands at level
+// n, which step n reads in the same launch: every lane holding that face adds
+// it to its own copy of step n's collected adjoint (the same FMA the adjoint
+// ring would take) instead of waiting for the ring.  At the end one job lane
+// per (owned PE lane, stage, level below n) adds both steps' shares to the
+// adjoint ring, step n+1's first, so each entry is touched once per launch
+// and sums in the order of one step per launch.
+template <int S>
+struct AdjSmem2 {
+  uint8_t kd[2][kWavesPerBlock][S][kWave];
+  double adjn[2][kWavesPerBlock][S][kWave];  // collected adjoint, then (once read) the sensitivity lf
+};
+
+template <int NP, int RK, int PHYS>
+__device__ __forceinline__ void adj_tile2(const DevProblem& P, const WorkItem wi, int lane, int32_t n,
+                                          const double* __restrict__ lam, double* __restrict__ lamo,
+                                          double* __restrict__ adjring, AdjSmem2<rk_stages(RK)>& sm, int wv) {
+  constexpr int S = rk_stages(RK);
+  constexpr int HL = 2 * adj_halo(RK, false);
+  constexpr int T = kWave - 2 * HL;
+  const int N = (int)P.n_elem;
+  const int e0 = wi.tile * T;
+  const int teff = (N - e0) < T ? (N - e0) : T;
+  const int x = e0 - HL + lane;
+  const int e = N < kWave ? wrap_elem(x, N) : wrap_once(x, N);
+  const bool owned = lane >= HL && lane < kWave - HL && (x - e0) < teff;
+  const int64_t ld = P.ld;
+  const double* __restrict__ lp = lam + P.u_off;
+  double lamp[NP];
+#pragma unroll
+  for (int j = 0; j < NP; ++j) lamp[j] = lp[j * ld + e];
+
+  bool pe = false;
+  uint32_t b = 0;
+  int depth = 1, slot_n = 0;
+  if (P.async_faces) {
+    depth = P.depth;
+    slot_n = (int)((uint32_t)n - fast_div((uint32_t)n, P.depth_div) * (uint32_t)depth);
+    b = fast_div((uint32_t)e, P.pe_div);
+    pe = (uint32_t)e == b * P.pe_div.d;
+  }
+  // delays and collected adjoint of levels n+1 (t = 0) and n (t = 1), one job
+  // lane per (PE lane, step, stage)
+  const uint64_t m_pe = __ballot(pe);
+  const int n_jobs = 2 * S * __builtin_popcountll(m_pe);
+  for (int g0 = 0; g0 < n_jobs; g0 += kWave) {  // uniform
+    const int g = g0 + lane;
+    const int i = g / (2 * S), r = g - i * (2 * S), t = r / S, s = r - t * S;
+    const int tgt = nth_set_lane(m_pe, i);
+    const uint32_t face = (uint32_t)__shfl((int)b, tgt);  // every lane active
+    if (g < n_jobs) {
+      const int32_t m = n + 1 - t;
+      const int kd = pe_delay(P, m, s, face);
+      const int slot_m = t == 0 ? (slot_n + 1 == depth ? 0 : slot_n + 1) : slot_n;
+      sm.kd[t][wv][s][tgt] = (uint8_t)kd;
+      sm.adjn[t][wv][s][tgt] = adjring[P.ring_off + ((int64_t)face * S + s) * depth + slot_m];
+    }
+  }
+
+  const double keep[S][NP] = {};  // no forward stages: the Jacobian is constant
+  double l1[NP], l0[NP];
+  // step n + 1: a delay of 1 deposits c_0(1) lf at level n, which step n reads
+  adj_reverse<NP, RK, PHYS, false>(
+      P, lamp, l1, keep, pe, owned, [&](int s) { return (int)sm.kd[0][wv][s][lane]; },
+      [&](int s) { return sm.adjn[0][wv][s][lane]; },
+      [&](int s, double lf) {
+        sm.adjn[0][wv][s][lane] = lf;
+        if (sm.kd[0][wv][s][lane] == 1) sm.adjn[1][wv][s][lane] = fma(P.atc[1][0], lf, sm.adjn[1][wv][s][lane]);
+      });
+  adj_reverse<NP, RK, PHYS, false>(
+      P, l1, l0, keep, pe, owned, [&](int s) { return (int)sm.kd[1][wv][s][lane]; },
+      [&](int s) { return sm.adjn[1][wv][s][lane]; }, [&](int s, double lf) { sm.adjn[1][wv][s][lane] = lf; });
+
+  double* __restrict__ lo = lamo + P.u_off;
+  if (owned)
+#pragma unroll
+    for (int j = 0; j < NP; ++j) lo[j * ld + e] = l0[j];
+
+  // levels n - d, d = 1 .. L + q - 2, of each owned PE face and stage
+  constexpr int W = (kMaxL - 1) + (kMaxQ - 1);
+  const uint64_t m_own = __ballot(pe && owned);
+  const int n_sc = S * W * __builtin_popcountll(m_own);
+  for (int g0 = 0; g0 < n_sc; g0 += kWave) {  // uniform
+    const int g = g0 + lane;
+    const int i = g / (S * W), r = g - i * (S * W), s = r / W, d = 1 + (r - s * W);
+    const int tgt = nth_set_lane(m_own, i);
+    const uint32_t face = (uint32_t)__shfl((int)b, tgt);  // every lane active
+    if (g < n_sc) {
+      const int k1 = sm.kd[0][wv][s][tgt], k0 = sm.kd[1][wv][s][tgt];
+      const int j1 = 1 + d - k1, j0 = d - k0;  // level n - d from step n+1 and from step n
+      const bool u1 = k1 > 0 && j1 >= 0 && j1 < P.q, u0 = k0 > 0 && j0 >= 0 && j0 < P.q;
+      if ((u1 || u0) && d < depth) {
+        double* __restrict__ at = adjring + P.ring_off + ((int64_t)face * S + s) * depth + ring_slot(slot_n, d, depth);
+        double v = *at;
+        if (u1) v = fma(P.atc[k1][j1], sm.adjn[0][wv][s][tgt], v);
+        if (u0) v = fma(P.atc[k0][j0], sm.adjn[1][wv][s][tgt], v);
+        *at = v;
+      }
+    }
+  }
+}
+
+template <int NP, int RK, int PHYS>
+__global__ __launch_bounds__(kBlock) void k_adj_fused2(const DevProblem* __restrict__ probs,
+                                                       const WorkItem* __restrict__ work, int32_t w_begin,
+                                                       int32_t w_end, const double* __restrict__ lam,
+                                                       double* __restrict__ lamo, double* __restrict__ adjring,
+                                                       int32_t n) {
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+  const int lane = (int)(threadIdx.x % kWave);
+  const int w = w_begin + xcd_block((int)blockIdx.x, (int)gridDim.x) * kWavesPerBlock + wv;
+  if (w >= w_end) return;  // whole wave
+  __shared__ AdjSmem2<rk_stages(RK)> sm;
+  const WorkItem wi = work[w];
+  adj_tile2<NP, RK, PHYS>(probs[wi.prob], wi, lane, n, lam, lamo, adjring, sm, wv);
 }
 
 template <int NP, int RK, int PHYS, bool FWD>
@@ -431,6 +572,45 @@ static void adj_fused_rk(int phys, const AdjArgs& a, const double* u, const doub
       else adj_fused_go<RK, PHYS_ADV_UPWIND, false>(a, u, lam, lamo, ring, adjring, cpart, n, st);
       break;
   }
+}
+
+template <int RK, int PHYS>
+static void adj_fused2_go(const AdjArgs& a, const double* lam, double* lamo, double* adjring, int32_t n,
+                          hipStream_t st) {
+  for (int gi = 0; gi < 4; ++gi) {
+    const int32_t wb = a.group[gi], we = a.group[gi + 1];
+    if (we <= wb) continue;
+    const dim3 grid(a.grid[gi]), block(kBlock);
+    switch (gi) {
+      case 0: hipLaunchKernelGGL((k_adj_fused2<5, RK, PHYS>), grid, block, 0, st, a.probs, a.work, wb, we, lam, lamo,
+                                 adjring, n); break;
+      case 1: hipLaunchKernelGGL((k_adj_fused2<4, RK, PHYS>), grid, block, 0, st, a.probs, a.work, wb, we, lam, lamo,
+                                 adjring, n); break;
+      case 2: hipLaunchKernelGGL((k_adj_fused2<3, RK, PHYS>), grid, block, 0, st, a.probs, a.work, wb, we, lam, lamo,
+                                 adjring, n); break;
+      default: hipLaunchKernelGGL((k_adj_fused2<2, RK, PHYS>), grid, block, 0, st, a.probs, a.work, wb, we, lam, lamo,
+                                  adjring, n); break;
+    }
+  }
+}
+
+template <int RK>
+static void adj_fused2_rk(int phys, const AdjArgs& a, const double* lam, double* lamo, double* adjring, int32_t n,
+                          hipStream_t st) {
+  if (phys == PHYS_ADV_CENTRAL) adj_fused2_go<RK, PHYS_ADV_CENTRAL>(a, lam, lamo, adjring, n, st);
+  else adj_fused2_go<RK, PHYS_ADV_UPWIND>(a, lam, lamo, adjring, n, st);
+}
+
+hipError_t launch_adj_fused2(int rk, int phys, const AdjArgs& a, const double* lam, double* lamo, double* adjring,
+                             int32_t n, hipStream_t stream) {
+  if (phys == PHYS_BURGERS_LLF) return hipErrorInvalidValue;  // the Burgers Jacobian needs the forward stages
+  switch (rk) {
+    case RK_HEUN: adj_fused2_rk<RK_HEUN>(phys, a, lam, lamo, adjring, n, stream); break;
+    case RK_SSP3: adj_fused2_rk<RK_SSP3>(phys, a, lam, lamo, adjring, n, stream); break;
+    case RK_LS3: adj_fused2_rk<RK_LS3>(phys, a, lam, lamo, adjring, n, stream); break;
+    default: adj_fused2_rk<RK_RK4>(phys, a, lam, lamo, adjring, n, stream); break;
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_adj_fused(int rk, int phys, const AdjArgs& a, const double* u, const double* lam, double* lamo,

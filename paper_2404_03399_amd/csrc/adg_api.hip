@@ -229,9 +229,9 @@ struct Layout {
   int64_t groups, gstats;  // ensemble statistics: group CSR (2n+1 int32) and 4 doubles per group
   // adjoint recording (-1 if not recording); ckrec holds the fused kernel's
   // PE-face records (AT sums, delays) at every checkpoint plus one spare slot
-  int64_t ckpt, useg, ybuf, lam, q, adjring, cpart, ckrec, work_a;
+  int64_t ckpt, useg, ybuf, lam, q, adjring, cpart, ckrec, work_a, work_a2;
   int64_t total;
-  int32_t n_work_f, n_work_f2, n_work_s, n_work_a;
+  int32_t n_work_f, n_work_f2, n_work_s, n_work_a, n_work_a2;
   int64_t rec_atsum_bytes, rec_atk_bytes, rec_bytes;
   int64_t total_doubles;
   int64_t ring_doubles;
@@ -270,6 +270,8 @@ int kernel_of(const adg_problem*, const adg_options* opt) {
 }
 
 bool is_ldg(const adg_problem* probs) { return probs[0].equation == ADG_EQ_VISCOUS_BURGERS; }
+// linear advection can reverse two steps per launch (no forward stages needed)
+bool adj_two_steps(const adg_problem* probs) { return probs[0].equation == ADG_EQ_ADVECTION; }
 
 Layout make_layout(const adg_problem* probs, int32_t n, const adg_options* opt, int64_t n_rec) {
   Layout L{};
@@ -278,12 +280,14 @@ Layout make_layout(const adg_problem* probs, int32_t n, const adg_options* opt, 
   const int T = fused_tile((int)probs[0].rk, R, 1);
   const int T2 = fused_tile((int)probs[0].rk, R, 2);
   const int T1 = adj_tile_elems((int)probs[0].rk, probs[0].equation == ADG_EQ_BURGERS);
-  int64_t nwf = 0, nwf2 = 0, nws = 0, nwa = 0, tot = 0, ring = 0, at = 0;
+  const int TA2 = adj_tile_elems2((int)probs[0].rk);
+  int64_t nwf = 0, nwf2 = 0, nws = 0, nwa = 0, nwa2 = 0, tot = 0, ring = 0, at = 0;
   for (int32_t i = 0; i < n; ++i) {
     const adg_problem& p = probs[i];
     nwf += (p.n_elem + T - 1) / T;
     nwf2 += (p.n_elem + T2 - 1) / T2;
     nwa += (p.n_elem + T1 - 1) / T1;
+    nwa2 += (p.n_elem + TA2 - 1) / TA2;
     nws += (p.n_elem + kBlock - 1) / kBlock;
     tot += ld_of(p) * (p.degree + 1);
     if (async_of(p)) {
@@ -297,6 +301,7 @@ Layout make_layout(const adg_problem* probs, int32_t n, const adg_options* opt, 
   L.n_work_f2 = (int32_t)nwf2;
   L.n_work_s = (int32_t)nws;
   L.n_work_a = n_rec > 0 ? (int32_t)nwa : 0;
+  L.n_work_a2 = n_rec > 0 && adj_two_steps(probs) ? (int32_t)nwa2 : 0;
   L.total_doubles = tot;
   L.ring_doubles = ring;
   const int kern = kernel_of(probs, opt);
@@ -324,7 +329,7 @@ Layout make_layout(const adg_problem* probs, int32_t n, const adg_options* opt, 
   L.n_rec = n_rec;
   L.ckpt_every = (opt && opt->ckpt_every > 0) ? opt->ckpt_every : 64;
   L.n_ckpt = rec ? (n_rec + L.ckpt_every - 1) / L.ckpt_every : 0;
-  L.ckpt = L.useg = L.ybuf = L.lam = L.q = L.adjring = L.cpart = L.ckrec = L.work_a = -1;
+  L.ckpt = L.useg = L.ybuf = L.lam = L.q = L.adjring = L.cpart = L.ckrec = L.work_a = L.work_a2 = -1;
   L.rec_atsum_bytes = 8 * S * std::max<int64_t>(at, 1);
   L.rec_atk_bytes = 4 * std::max<int64_t>(at, 1);
   L.rec_bytes = align_up(L.rec_atsum_bytes, kAlign) + align_up(L.rec_atk_bytes, kAlign);
@@ -343,6 +348,7 @@ Layout make_layout(const adg_problem* probs, int32_t n, const adg_options* opt, 
     } else {
       L.ckrec = take(L.rec_bytes * (L.n_ckpt + 1));
       L.work_a = take((int64_t)sizeof(WorkItem) * nwa);
+      if (L.n_work_a2 > 0) L.work_a2 = take((int64_t)sizeof(WorkItem) * nwa2);
       L.cpart = take(8 * nwa);
     }
   }
@@ -376,9 +382,9 @@ struct adg_ctx {
   int32_t lane_elems = 2;
   int32_t fused_steps = 2;
   // fused adjoint work list (recording contexts of the fused kernel)
-  std::vector<WorkItem> work_a;
-  int32_t group_a[5] = {0, 0, 0, 0, 0};
-  int32_t grid_a[4] = {1, 1, 1, 1};
+  std::vector<WorkItem> work_a, work_a2;
+  int32_t group_a[5] = {0, 0, 0, 0, 0}, group_a2[5] = {0, 0, 0, 0, 0};
+  int32_t grid_a[4] = {1, 1, 1, 1}, grid_a2[4] = {1, 1, 1, 1};
 
   StepArgs base_args(int64_t work_off, int32_t n_work, int K = 1) const {
     StepArgs a{};
@@ -401,12 +407,12 @@ struct adg_ctx {
     return K == 2 ? base_args(L.work_f2, L.n_work_f2, 2) : base_args(L.work_f, L.n_work_f, 1);
   }
   StepArgs stage_args() const { return base_args(L.work_s, L.n_work_s); }
-  AdjArgs adj_args() const {
+  AdjArgs adj_args(int K = 1) const {
     AdjArgs a{};
     a.probs = (const DevProblem*)(ws + L.probs);
-    a.work = (const WorkItem*)(ws + L.work_a);
-    for (int i = 0; i < 5; ++i) a.group[i] = group_a[i];
-    for (int i = 0; i < 4; ++i) a.grid[i] = grid_a[i];
+    a.work = (const WorkItem*)(ws + (K == 2 ? L.work_a2 : L.work_a));
+    for (int i = 0; i < 5; ++i) a.group[i] = K == 2 ? group_a2[i] : group_a[i];
+    for (int i = 0; i < 4; ++i) a.grid[i] = K == 2 ? grid_a2[i] : grid_a[i];
     return a;
   }
   // copy the fused kernel's PE-face records to / from checkpoint slot k
@@ -693,20 +699,22 @@ int adg_init(adg_ctx** out, const adg_problem* probs, int32_t n_probs, const adg
     for (int64_t t = 0; t < nt; ++t) ws_.push_back(WorkItem{i, (int32_t)t});
   }
   first[n_probs] = (int32_t)ws_.size();
-  if (c->L.work_a >= 0) {  // fused adjoint: one element per lane, same degree grouping
-    const int T1 = adj_tile_elems(c->rk, probs[0].equation == ADG_EQ_BURGERS);
-    c->work_a.reserve(c->L.n_work_a);
+  // fused adjoint: one element per lane, same degree grouping
+  auto adj_list = [&](int T1, std::vector<WorkItem>& wl, int32_t* grp, int32_t* grd) {
     for (int np = 5, gi = 0; np >= 2; --np, ++gi) {
-      c->group_a[gi] = (int32_t)c->work_a.size();
+      grp[gi] = (int32_t)wl.size();
       for (int32_t i : order) {
         if ((int)probs[i].degree + 1 != np) continue;
         const int64_t nt = (probs[i].n_elem + T1 - 1) / T1;
-        for (int64_t t = 0; t < nt; ++t) c->work_a.push_back(WorkItem{i, (int32_t)t});
+        for (int64_t t = 0; t < nt; ++t) wl.push_back(WorkItem{i, (int32_t)t});
       }
     }
-    c->group_a[4] = (int32_t)c->work_a.size();
-    for (int gi = 0; gi < 4; ++gi) c->grid_a[gi] = fused_grid(c->group_a[gi + 1] - c->group_a[gi]);
-  }
+    grp[4] = (int32_t)wl.size();
+    for (int gi = 0; gi < 4; ++gi) grd[gi] = fused_grid(grp[gi + 1] - grp[gi]);
+  };
+  if (c->L.work_a >= 0)
+    adj_list(adj_tile_elems(c->rk, probs[0].equation == ADG_EQ_BURGERS), c->work_a, c->group_a, c->grid_a);
+  if (c->L.work_a2 >= 0) adj_list(adj_tile_elems2(c->rk), c->work_a2, c->group_a2, c->grid_a2);
 
   auto up = [&](int64_t off, const void* src, int64_t bytes) -> int {
     ADG_HIP(hipMemcpyAsync(c->ws + off, src, bytes, hipMemcpyHostToDevice, c->stream));
@@ -719,6 +727,8 @@ int adg_init(adg_ctx** out, const adg_problem* probs, int32_t n_probs, const adg
       (rc = up(c->L.first_s, first.data(), (int64_t)sizeof(int32_t) * first.size())) ||
       (c->L.work_a >= 0 &&
        (rc = up(c->L.work_a, c->work_a.data(), (int64_t)sizeof(WorkItem) * c->work_a.size()))) ||
+      (c->L.work_a2 >= 0 &&
+       (rc = up(c->L.work_a2, c->work_a2.data(), (int64_t)sizeof(WorkItem) * c->work_a2.size()))) ||
       (rc = reset_device(c))) {
     delete c;
     return rc;
@@ -956,8 +966,15 @@ int adjoint_fused(adg_ctx* c, const double* d_cot_uT, double* d_grad_u0, double*
   // they are recomputed only for dJ/da
   const bool need_fwd = c->phys == PHYS_BURGERS_LLF || h_grad_speed != nullptr;
   if (!need_fwd) {
-    for (int64_t n = N - 1; n >= 0; --n) {
-      ADG_HIP(launch_adj_fused(c->rk, c->phys, aa, nullptr, lam, lamu, ring, adjring, cpart, (int32_t)n, st));
+    const AdjArgs aa2 = c->adj_args(2);
+    for (int64_t n = N - 1; n >= 0;) {
+      if (c->fused_steps == 2 && L.work_a2 >= 0 && n >= 1) {  // steps n and n - 1 in one launch
+        ADG_HIP(launch_adj_fused2(c->rk, c->phys, aa2, lam, lamu, adjring, (int32_t)(n - 1), st));
+        n -= 2;
+      } else {
+        ADG_HIP(launch_adj_fused(c->rk, c->phys, aa, nullptr, lam, lamu, ring, adjring, cpart, (int32_t)n, st));
+        n -= 1;
+      }
       std::swap(lam, lamu);
     }
   }

@@ -87,6 +87,13 @@ struct AdjArgs {
 hipError_t launch_adj_fused(int rk, int phys, const AdjArgs& a, const double* u, const double* lam, double* lamo,
                             const double* ring, double* adjring, double* cpart, int32_t n, hipStream_t stream);
 
+// Reverse of steps n + 1 and n (absolute indices) for linear advection without
+// the forward states (dJ/du0 only): lamo = lambda^n from lam = lambda^{n+2},
+// halo 2S lanes (work list of adj_tile_elems2 elements per item).
+hipError_t launch_adj_fused2(int rk, int phys, const AdjArgs& a, const double* lam, double* lamo, double* adjring,
+                             int32_t n, hipStream_t stream);
+__host__ __device__ constexpr int adj_tile_elems2(int rk) { return kWave - 4 * adj_halo(rk, false); }
+
 // ctr[0] := value (one lane).
 hipError_t launch_set_counter(int64_t* ctr, int64_t value, hipStream_t stream);
 
