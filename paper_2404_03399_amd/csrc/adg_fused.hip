@@ -232,7 +232,8 @@ __device__ __forceinline__ void wave_tile(const DevProblem& P, const WorkItem wi
           if (wave_pe_right) {
             const bool right_pe = r + 1 < R ? pe[r + 1] : pe_right;
             const double fr = r + 1 < R ? F[r + 1] : f_last;
-            // exactly 0 unless the right face is a delayed PE face
+            // 0 at an interior face; at a PE face the applied flux minus the
+            // exact a u_p (for a synchronous one the rounding error of a u_p)
             const double corr = right_pe ? fma(-a, y[r][NP - 1], fr) : 0.0;
 #pragma unroll
             for (int i = 0; i < NP; ++i) k[i] = fma(-P.Kr[i], corr, k[i]);
