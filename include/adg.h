@@ -185,7 +185,8 @@ int adg_run(adg_ctx* ctx, double* d_u, int64_t n_steps, uint32_t flags);
  * dJ/da per problem to the host array h_grad_speed (n_probs doubles; dt is
  * held fixed; 0 for Burgers).  h_grad_speed may be NULL: for linear
  * advection the reverse sweep then skips the forward recomputation, which
- * only dJ/da needs.  Requires the last adg_run to have used ADG_RUN_RECORD;
+ * only dJ/da needs, and with fused_steps = 2 reverses two steps per launch;
+ * dJ/du(0) is bitwise the same either way.  Requires the last adg_run to have used ADG_RUN_RECORD;
  * the recording stays valid (the adjoint may be called again) and the
  * context may keep stepping afterwards.  Synchronises the stream when
  * h_grad_speed is given. */

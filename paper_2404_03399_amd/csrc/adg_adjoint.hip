@@ -1,5 +1,6 @@
 // Discrete adjoint kernels: one launch per reverse RK stage (RK registers in
-// HBM), and the fused reverse step (one launch per step and degree group).
+// HBM), the fused reverse step (one launch per step and degree group), and
+// for linear advection without dJ/da two fused reverse steps per launch.
 #include "adg_device.hpp"
 
 namespace adg {

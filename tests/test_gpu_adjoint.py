@@ -69,17 +69,17 @@ def test_adjoint_matches_oracle(torch_cuda, kernel, scheme, rk, p, flux, ne, pe)
     assert abs(ga - ga_o) <= 1e-12 * max(1.0, abs(ga_o)), (ga, ga_o)
 
 
+@pytest.mark.parametrize("n", [22, 23])
 @pytest.mark.parametrize("scheme,rk,p,flux,ne,pe", CASES)
-def test_two_step_reverse_matches_oracle(torch_cuda, scheme, rk, p, flux, ne, pe):
+def test_two_step_reverse_matches_oracle(torch_cuda, scheme, rk, p, flux, ne, pe, n):
     """dJ/du0 alone for linear advection: with two fused steps per launch the
     reverse sweep takes two steps per launch too (no forward recomputation).
-    It matches the oracle and, bitwise, the one-step reverse sweep; 23 steps
-    leave one single step at the end."""
+    It matches the oracle and, bitwise, the one-step reverse sweep; an odd
+    step count leaves one single step at the end."""
     from paper_2404_03399_amd.solver import Solver
     dt = {1: 0.05, 2: 0.02, 3: 0.005, 4: 0.002}[p] * W.TWO_PI / ne
     w = W.Workload(name="adj2", scheme=scheme, rk=rk, degree=p, n_elem=ne, pe_size=pe, flux=flux,
                    probs=W.DELAYS_C2, seed=11, dt=dt, speed=1.3, ic=W.PAPER_MULTISINE)
-    n = 23
     u0 = stepper.initial_state(w)
     ref = np.random.default_rng(4).standard_normal(u0.shape)
     _say(f"two-step reverse {scheme} {rk} p={p} {flux} N={ne} pe={pe} steps={n}")
@@ -141,7 +141,8 @@ def test_checkpoint_interval_does_not_change_gradient(torch_cuda, kernel):
 def test_fused_adjoint_lane_elems_and_batch(torch_cuda, lane_elems):
     """A batched recording (degrees 1..4, different speeds, meshes and PE
     sizes, forward with R elements per lane) against the oracle problem by
-    problem; the adjoint always runs one element per lane."""
+    problem; the adjoint always runs one element per lane.  dJ/du0 without
+    dJ/da (two reverse steps per launch) is bitwise the same."""
     from paper_2404_03399_amd.solver import Solver
     specs = [(1, 90, 15, 1.3, "ssprk3"), (2, 128, 16, 0.7, "ssprk3"), (3, 75, 5, -1.1, "ssprk3"),
              (4, 64, 8, 2.0, "ssprk3")]
@@ -159,10 +160,15 @@ def test_fused_adjoint_lane_elems_and_batch(torch_cuda, lane_elems):
     u = s.pack(u0s)
     s.run(u, n, graph=True, record=True)
     uts = s.unpack(u)
-    g, gs = s.adjoint(s.pack([ut - r for ut, r in zip(uts, refs)]))
+    cot = s.pack([ut - r for ut, r in zip(uts, refs)])
+    g, gs = s.adjoint(cot)
+    # dJ/du0 alone: two reverse steps per launch over the batch's degree groups
+    g2, _ = s.adjoint(cot, want_speed=False)
     torch_cuda.cuda.synchronize()
-    gl = s.unpack(g)
+    gl, gl2 = s.unpack(g), s.unpack(g2)
     s.close()
+    for i in range(len(ws)):
+        assert np.array_equal(gl[i], gl2[i]), i
     for i, w in enumerate(ws):
         ut_o, g_o, ga_o = oadj.gradient(w, u0s[i], n, oadj.misfit_cotangent(refs[i]))
         assert stats.rel_l2(uts[i], ut_o) <= 1e-12
