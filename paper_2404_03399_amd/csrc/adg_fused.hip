@@ -182,8 +182,14 @@ __device__ __forceinline__ void wave_tile(const DevProblem& P, const WorkItem wi
   const double dt = P.dt;
 
   // upwind, a > 0: the interior right-face flux a u_p is part of Kdu; only a
-  // delayed PE face on the right adds -Kr (F_right - a u_p)
-  const bool wave_pe_right = PHYS == PHYS_ADV_UPWIND_POS && __ballot(pe_right) != 0;
+  // PE face on the right adds -Kr (F_right - a u_p).  rpe[r]: the right face
+  // of element r is a PE face; wave_rpe[r] (uniform): it is on some lane.
+  bool rpe[R], wave_rpe[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    rpe[r] = r + 1 < R ? pe[r + 1] : pe_right;
+    wave_rpe[r] = PHYS == PHYS_ADV_UPWIND_POS && __ballot(rpe[r]) != 0;
+  }
 
   int slot_m = slot_n;
 #pragma unroll
@@ -219,7 +225,7 @@ __device__ __forceinline__ void wave_tile(const DevProblem& P, const WorkItem wi
       }
       if constexpr (PHYS == PHYS_ADV_UPWIND_POS) {
         double f_last = 0.0;
-        if (wave_pe_right) f_last = lane_from_right(F[0]);
+        if (wave_rpe[R - 1]) f_last = lane_from_right(F[0]);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
 #pragma unroll
@@ -229,12 +235,11 @@ __device__ __forceinline__ void wave_tile(const DevProblem& P, const WorkItem wi
             for (int j = 0; j < NP; ++j) v = fma(P.Kdu[i * kMaxNp + j], y[r][j], v);
             k[i] = v;
           }
-          if (wave_pe_right) {
-            const bool right_pe = r + 1 < R ? pe[r + 1] : pe_right;
+          if (wave_rpe[r]) {
             const double fr = r + 1 < R ? F[r + 1] : f_last;
             // 0 at an interior face; at a PE face the applied flux minus the
             // exact a u_p (for a synchronous one the rounding error of a u_p)
-            const double corr = right_pe ? fma(-a, y[r][NP - 1], fr) : 0.0;
+            const double corr = rpe[r] ? fma(-a, y[r][NP - 1], fr) : 0.0;
 #pragma unroll
             for (int i = 0; i < NP; ++i) k[i] = fma(-P.Kr[i], corr, k[i]);
           }

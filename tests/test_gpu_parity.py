@@ -479,11 +479,14 @@ def test_autotuned_lane_elems(torch_cuda, tmp_path, monkeypatch):
 
 
 @pytest.mark.parametrize("ne,pe,p,rk,phys", [(1000, 40, 3, "rk4", "upwind"), (1001, 77, 2, "ssprk3", "central"),
-                                             (640, 8, 1, "heun", "llf"), (512, 16, 4, "lsrk3", "upwind")])
+                                             (640, 8, 1, "heun", "llf"), (512, 16, 4, "lsrk3", "upwind"),
+                                             (1290, 129, 3, "rk4", "upwind")])
 def test_every_launch_shape_bitwise(torch_cuda, ne, pe, p, rk, phys):
     """Elements per lane R in {1, 2, 4} and steps per launch K in {1, 2}:
     every multiply-add is an explicit FMA with contraction off, so all six
-    launch shapes give bitwise the same states."""
+    launch shapes give bitwise the same states.  With PE size 129 some waves
+    hold PE faces only inside a lane's group of R elements (upwind, a > 0:
+    the left element's correction for the applied PE flux)."""
     eq = "burgers" if phys == "llf" else "advection"
     ic = W.MultiSine((1, 2), (1.0, 0.5), (0.3, 0.9), offset=0.5 if eq == "burgers" else 0.0)
     sig = {1: 0.05, 2: 0.01, 3: 0.005, 4: 0.001}[p]
