@@ -239,10 +239,14 @@ struct Layout {
   int64_t n_rec, ckpt_every, n_ckpt;
 };
 
-// Ring slots per (boundary, stage): the AT window L + q - 1, or, when an
-// adjoint recording horizon is given, the whole run (every level is kept).
+// Ring slots per (boundary, stage): the AT window L + q - 1 plus one, or,
+// when an adjoint recording horizon is given, the whole run (every level is
+// kept).  A two-step launch writes levels n and n + 1 while waves that start
+// later still read levels down to n + 2 - L - q (the local DG kernel's halo
+// waves read the ring at their start); with L + q slots level n + 1 never
+// shares a slot with a level the launch reads.
 int64_t depth_of(const adg_problem& p, int64_t n_rec) {
-  return n_rec > 0 ? n_rec + p.n_delays + q_of(p) : (int64_t)p.n_delays + q_of(p) - 1;
+  return n_rec > 0 ? n_rec + p.n_delays + q_of(p) : (int64_t)p.n_delays + q_of(p);
 }
 
 // Elements per lane of the fused kernel (0 if the request is invalid).

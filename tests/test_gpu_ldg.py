@@ -143,3 +143,30 @@ def test_ldg_two_steps_per_launch_bitwise(torch_cuda, p, rk, scheme, q, per_stag
     assert np.array_equal(out[1, 19], out[2, 19])
     assert np.array_equal(out[1, 32], out[2, 32])
     assert stats.rel_l2(out[2, 19], stepper.Stepper(w).run(u0, 19)) <= 1e-12
+
+
+@pytest.mark.parametrize("scheme,q,probs", [("adg", 0, ("0", "0", "1")), ("adg_at", 1, ("0", "0", "0", "1")),
+                                            ("adg_at", 2, ("0", "0", "1")), ("adg_at", 3, ("0", "1"))])
+def test_two_step_launch_reads_no_level_written_in_it(torch_cuda, scheme, q, probs):
+    """Every PE face at the largest delay L-1 with q AT levels: a two-step
+    launch reads the ring down to level n + 2 - L - q from every wave holding
+    the face while the owner writes levels n and n + 1.  With a small
+    viscosity the time step is large enough for neighbouring levels to
+    differ visibly, so a slot shared by a written and a read level would show
+    against the oracle and between one and two steps per launch."""
+    from paper_2404_03399_amd.solver import Solver
+    w = replace(_w(2, "heun", scheme, q, False, ne=600, pe=2, nu=0.005), probs=probs)
+    n = 20
+    _say(f"viscous Burgers, every face at delay {len(probs) - 1}, {scheme} q={q}, N=600 pe=2 steps={n}")
+    u0 = stepper.initial_state(w)
+    ref = stepper.Stepper(w).run(u0, n)
+    outs = []
+    for K in (1, 2):
+        s = Solver(w, kernel="fused", fused_steps=K)
+        u = s.pack(u0)
+        s.run(u, n, graph=False)
+        torch_cuda.cuda.synchronize()
+        outs.append(s.unpack(u)[0])
+        s.close()
+    assert np.array_equal(outs[0], outs[1])
+    assert stats.rel_l2(outs[1], ref) <= 1e-12, stats.rel_l2(outs[1], ref)
