@@ -368,7 +368,7 @@ struct adg_ctx {
   adg_options opt{};
   int kernel = ADG_KERNEL_FUSED;
   int rk = 0, phys = 0, S = 0;
-  int fused_phys = 0;  // phys of the fused kernel (upwind with a > 0 specialised)
+  int fused_phys = 0;  // phys of the fused kernel (its launcher takes the a > 0 upwind form per work range)
   hipStream_t stream = nullptr;
   char* ws = nullptr;
   Layout L{};
@@ -380,9 +380,9 @@ struct adg_ctx {
   const double* graph_u = nullptr;
   int graph_steps = 0;
 
-  int32_t group[2][5] = {{0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}};  // fused work lists, 1 and 2 steps per launch
-  int32_t grid[2][4] = {{1, 1, 1, 1}, {1, 1, 1, 1}};
-  int32_t single[2][4] = {{-1, -1, -1, -1}, {-1, -1, -1, -1}};
+  int32_t group[2][kFusedRanges + 1] = {};  // fused work lists, 1 and 2 steps per launch
+  int32_t grid[2][kFusedRanges] = {};
+  int32_t single[2][kFusedRanges] = {};
   int32_t lane_elems = 2;
   int32_t fused_steps = 2;
   // fused adjoint work list (recording contexts of the fused kernel)
@@ -399,9 +399,9 @@ struct adg_ctx {
     a.ctr = (int64_t*)(ws + L.ctr);
     a.atsum = (double*)(ws + L.atsum);
     a.atk = (int32_t*)(ws + L.atk);
-    for (int i = 0; i < 5; ++i) a.group[i] = group[K - 1][i];
-    for (int i = 0; i < 4; ++i) a.grid[i] = grid[K - 1][i];
-    for (int i = 0; i < 4; ++i) a.single[i] = single[K - 1][i];
+    for (int i = 0; i <= kFusedRanges; ++i) a.group[i] = group[K - 1][i];
+    for (int i = 0; i < kFusedRanges; ++i) a.grid[i] = grid[K - 1][i];
+    for (int i = 0; i < kFusedRanges; ++i) a.single[i] = single[K - 1][i];
     a.lane_elems = lane_elems;
     a.steps = K;
     a.qbuf = L.qbuf >= 0 ? (double*)(ws + L.qbuf) : nullptr;
@@ -588,11 +588,6 @@ int adg_init(adg_ctx** out, const adg_problem* probs, int32_t n_probs, const adg
   c->rk = (int)probs[0].rk;
   c->phys = phys_of(probs[0]);
   c->fused_phys = c->phys;
-  if (c->phys == PHYS_ADV_UPWIND) {
-    bool pos = true;
-    for (int32_t i = 0; i < n_probs; ++i) pos = pos && probs[i].speed > 0.0;
-    if (pos) c->fused_phys = PHYS_ADV_UPWIND_POS;
-  }
   c->S = rk_stages(c->rk);
   c->stream = (hipStream_t)hip_stream;
   c->ws = (char*)d_workspace;
@@ -679,17 +674,21 @@ int adg_init(adg_ctx** out, const adg_problem* probs, int32_t n_probs, const adg
     const int T = fused_tile(c->rk, c->lane_elems, K);
     std::vector<WorkItem>& wf = wfk[K - 1];
     wf.reserve(K == 1 ? c->L.n_work_f : c->L.n_work_f2);
-    // ranges per degree, np = 5, 4, 3, 2 (order is sorted by degree, descending)
-    for (int np = 5, gi = 0; np >= 2; --np, ++gi) {
+    // ranges per degree, np = 5, 4, 3, 2 (order is sorted by degree,
+    // descending), each split into the a > 0 upwind form and the rest
+    for (int gi = 0; gi < kFusedRanges; ++gi) {
+      const int np = 5 - gi / 2;
+      const bool pos_range = (gi & 1) == 0;
       c->group[K - 1][gi] = (int32_t)wf.size();
       for (int32_t i : order) {
-        if ((int)probs[i].degree + 1 != np) continue;
+        const bool pos = c->phys == PHYS_ADV_UPWIND && probs[i].speed > 0.0;
+        if ((int)probs[i].degree + 1 != np || pos != pos_range) continue;
         const int64_t nt = (probs[i].n_elem + T - 1) / T;
         for (int64_t t = 0; t < nt; ++t) wf.push_back(WorkItem{i, (int32_t)t});
       }
     }
-    c->group[K - 1][4] = (int32_t)wf.size();
-    for (int gi = 0; gi < 4; ++gi) {
+    c->group[K - 1][kFusedRanges] = (int32_t)wf.size();
+    for (int gi = 0; gi < kFusedRanges; ++gi) {
       const int32_t b = c->group[K - 1][gi], e = c->group[K - 1][gi + 1];
       c->grid[K - 1][gi] = fused_grid(e - b);
       bool one = e > b;

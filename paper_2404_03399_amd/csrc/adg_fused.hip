@@ -507,10 +507,15 @@ static void fused_ldg_go(const StepArgs& a, int gi, const double* uin, double* u
 
 template <int RK>
 static void fused_ldg_np(const StepArgs& a, const double* uin, double* uout, int32_t off, hipStream_t st) {
-  if (a.group[1] > a.group[0]) fused_ldg_go<5, RK>(a, 0, uin, uout, off, st);
-  if (a.group[2] > a.group[1]) fused_ldg_go<4, RK>(a, 1, uin, uout, off, st);
-  if (a.group[3] > a.group[2]) fused_ldg_go<3, RK>(a, 2, uin, uout, off, st);
-  if (a.group[4] > a.group[3]) fused_ldg_go<2, RK>(a, 3, uin, uout, off, st);
+  for (int gi = 0; gi < kFusedRanges; ++gi) {
+    if (a.group[gi + 1] <= a.group[gi]) continue;
+    switch (gi / 2) {  // np = 5, 4, 3, 2
+      case 0: fused_ldg_go<5, RK>(a, gi, uin, uout, off, st); break;
+      case 1: fused_ldg_go<4, RK>(a, gi, uin, uout, off, st); break;
+      case 2: fused_ldg_go<3, RK>(a, gi, uin, uout, off, st); break;
+      default: fused_ldg_go<2, RK>(a, gi, uin, uout, off, st); break;
+    }
+  }
 }
 
 template <int NP, int RK, int PHYS, int R>
@@ -533,20 +538,34 @@ static void fused_go(const StepArgs& a, int gi, const double* uin, double* uout,
   }
 }
 
+template <int NP, int RK, int PHYS>
+static void fused_form(const StepArgs& a, int gi, const double* uin, double* uout, int32_t off, hipStream_t st) {
+  if constexpr (PHYS == PHYS_ADV_UPWIND) {
+    if ((gi & 1) == 0) {  // the problems with a > 0
+      fused_go<NP, RK, PHYS_ADV_UPWIND_POS>(a, gi, uin, uout, off, st);
+      return;
+    }
+  }
+  fused_go<NP, RK, PHYS>(a, gi, uin, uout, off, st);
+}
+
 template <int RK, int PHYS>
 static void fused_np(const StepArgs& a, const double* uin, double* uout, int32_t off, hipStream_t st) {
-  // degree ranges np = 5, 4, 3, 2
-  if (a.group[1] > a.group[0]) fused_go<5, RK, PHYS>(a, 0, uin, uout, off, st);
-  if (a.group[2] > a.group[1]) fused_go<4, RK, PHYS>(a, 1, uin, uout, off, st);
-  if (a.group[3] > a.group[2]) fused_go<3, RK, PHYS>(a, 2, uin, uout, off, st);
-  if (a.group[4] > a.group[3]) fused_go<2, RK, PHYS>(a, 3, uin, uout, off, st);
+  for (int gi = 0; gi < kFusedRanges; ++gi) {
+    if (a.group[gi + 1] <= a.group[gi]) continue;
+    switch (gi / 2) {  // np = 5, 4, 3, 2
+      case 0: fused_form<5, RK, PHYS>(a, gi, uin, uout, off, st); break;
+      case 1: fused_form<4, RK, PHYS>(a, gi, uin, uout, off, st); break;
+      case 2: fused_form<3, RK, PHYS>(a, gi, uin, uout, off, st); break;
+      default: fused_form<2, RK, PHYS>(a, gi, uin, uout, off, st); break;
+    }
+  }
 }
 
 template <int RK>
 static void fused_phys(int phys, const StepArgs& a, const double* uin, double* uout, int32_t off, hipStream_t st) {
   switch (phys) {
     case PHYS_ADV_UPWIND: fused_np<RK, PHYS_ADV_UPWIND>(a, uin, uout, off, st); break;
-    case PHYS_ADV_UPWIND_POS: fused_np<RK, PHYS_ADV_UPWIND_POS>(a, uin, uout, off, st); break;
     case PHYS_ADV_CENTRAL: fused_np<RK, PHYS_ADV_CENTRAL>(a, uin, uout, off, st); break;
     case PHYS_BURGERS_LDG: fused_ldg_np<RK>(a, uin, uout, off, st); break;  // one element per lane
     default: fused_np<RK, PHYS_BURGERS_LLF>(a, uin, uout, off, st); break;

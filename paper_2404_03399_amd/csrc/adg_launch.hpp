@@ -13,9 +13,9 @@ struct StepArgs {
   int64_t* ctr;              // ctr[0] = steps completed by earlier batches, ctr[2] = non-finite flag
   double* atsum;             // fused kernel: AT sums of past levels, [kRecSlots][P][S] per problem
   int32_t* atk;              // fused kernel: clamped delays, [kRecSlots][P] words per problem (byte s = stage s)
-  int32_t group[5];          // fused kernel: work-item ranges per degree (below)
-  int32_t grid[4];           // fused kernel: workgroups per degree range
-  int32_t single[4];         // fused kernel: the only problem of a degree range, or -1
+  int32_t group[9];          // fused kernel: work-item ranges per degree and form (below)
+  int32_t grid[8];           // fused kernel: workgroups per range
+  int32_t single[8];         // fused kernel: the only problem of a range, or -1
   int32_t lane_elems;        // fused kernel: elements per lane (1, 2 or 4)
   int32_t steps;             // fused kernel: time steps per launch (1 or 2)
   double* qbuf;              // local DG: q = u_x of the current stage input (state layout)
@@ -23,9 +23,14 @@ struct StepArgs {
                              // the first step here (state layout), or null
 };
 
-// Work items of the fused kernel are sorted by descending np; items with
-// np = 5, 4, 3, 2 occupy [group[0], group[1]), [group[1], group[2]),
-// [group[2], group[3]), [group[3], group[4]).
+// Work items of the fused kernel are sorted by descending np and, within a
+// degree, by form: range g = 2 (5 - np) + v, [group[g], group[g + 1]), holds
+// the items of degree np - 1 that take the a > 0 upwind form (v = 0: upwind
+// advection with a positive speed, whose interior right-face flux is folded
+// into the volume operator) or the general form of the context's equation
+// (v = 1).  Each problem therefore runs the same kernel in a batch as in a
+// context of its own.
+constexpr int kFusedRanges = 8;
 
 // Fused step kernel geometry: one wave64 per work item, R in {1, 2, 4}
 // consecutive elements per lane, K in {1, 2} time steps per launch, halo of

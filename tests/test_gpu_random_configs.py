@@ -17,7 +17,7 @@ import numpy as np
 import pytest
 
 from paper_2404_03399_amd import workloads as W
-from oracle import stats, stepper
+from oracle import adjoint as oadj, stats, stepper
 
 TOL = 1e-12
 N_CASES = 160
@@ -90,15 +90,57 @@ def tolerance(w, u0, n, ref) -> float:
     return max(TOL, 30.0 * stats.rel_l2(stepper.Stepper(w).run(u1, n), ref))
 
 
-def _run(torch, w, u0, n, R, K, graph):
+def draw_batch(case: int):
+    """Two to four problems that may share one context: the equation, flux,
+    integrator, scheme and delay granularity of the first draw, each with its
+    own degree, mesh, PE size, AT levels, delays, seed, speed and step."""
+    rng = np.random.default_rng(9000 + case)
+    first, n, _, K, graph = draw(1000 + 5 * case)
+    ws = [first]
+    for j in range(1, int(rng.integers(2, 5))):
+        w, *_ = draw(1000 + 5 * case + j)
+        q = min(w.at_levels, w.degree + 1) if first.scheme == "adg_at" else 0
+        dx = W.TWO_PI / w.n_elem
+        if first.equation == "advection":
+            dt = SIGMA[w.degree] * dx / abs(w.speed)
+        elif first.equation == "burgers":
+            dt = SIGMA[w.degree] * dx / 1.5
+        else:
+            nu = first.viscosity
+            dt = min(0.002 * dx * dx / nu, 0.01 * dx / 6.0)
+        probs = first.probs if first.caa else w.probs
+        ws.append(W.Workload(name=f"{first.name}_{j}", equation=first.equation, scheme=first.scheme,
+                             flux=first.flux, rk=first.rk, degree=w.degree, n_elem=w.n_elem, pe_size=w.pe_size,
+                             probs=probs, seed=w.seed, per_stage=first.per_stage, caa=first.caa, at_levels=q,
+                             speed=w.speed if first.equation == "advection" else 1.0,
+                             viscosity=first.viscosity, dt=dt, ic=first.ic))
+    async_pes = [w.pe_size for w in ws if w.scheme != "dg" and w.n_elem // w.pe_size > 1]
+    lanes = [1] if first.equation == "viscous_burgers" else [r for r in (1, 2, 4) if r <= min(async_pes or [4])]
+    R = int(rng.choice(lanes))
+    return ws, n, R, K, graph
+
+
+def _run(torch, w, u0, n, R, K, graph, kernel="fused"):
     from paper_2404_03399_amd.solver import Solver
-    s = Solver(w, kernel="fused", lane_elems=R, fused_steps=K)
+    s = Solver(w, kernel=kernel, lane_elems=R, fused_steps=K)
     u = s.pack(u0)
     s.run(u, n, graph=graph)
     torch.cuda.synchronize()
-    out = s.unpack(u)[0]
+    out = s.unpack(u)
     s.close()
-    return out
+    return out if isinstance(w, (list, tuple)) else out[0]
+
+
+def test_batch_draws_share_what_a_context_requires():
+    for c in range(N_BATCH):
+        ws, n, R, K, _ = draw_batch(c)
+        assert 2 <= len(ws) <= 4
+        for w in ws:
+            assert (w.equation, w.flux, w.rk, w.scheme, w.per_stage, w.caa) == \
+                (ws[0].equation, ws[0].flux, ws[0].rk, ws[0].scheme, ws[0].per_stage, ws[0].caa)
+            assert w.n_elem % w.pe_size == 0 and 0 <= w.at_levels <= w.degree + 1
+            if w.scheme != "dg" and w.n_elem // w.pe_size > 1:
+                assert R <= w.pe_size
 
 
 def test_draws_are_valid_and_varied():
@@ -140,3 +182,96 @@ def test_random_config_matches_oracle(torch_cuda, case):
     assert np.array_equal(got, _run(torch_cuda, w, u0, n, R, 3 - K, not graph))
     err, tol = stats.rel_l2(got, ref), tolerance(w, u0, n, ref)
     assert err <= tol, (err, tol)
+    # the per-stage kernels: the same map, rounded in their own order
+    st = _run(torch_cuda, w, u0, n, 0, 0, graph, kernel="stage")
+    err_s = stats.rel_l2(st, ref)
+    assert err_s <= tol, (err_s, tol)
+
+
+N_BATCH = 40
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("case", range(N_BATCH))
+def test_random_batch_matches_single_runs(torch_cuda, case):
+    """A context over several different problems advances each exactly as a
+    context of its own would (bitwise), at any launch shape."""
+    ws, n, R, K, graph = draw_batch(case)
+    _say(f"random batch {case}: {len(ws)} x {ws[0].equation} {ws[0].flux} {ws[0].scheme} {ws[0].rk}, "
+         f"p={[w.degree for w in ws]} N={[w.n_elem for w in ws]} pe={[w.pe_size for w in ws]} "
+         f"steps={n} R={R} K={K} graph={graph}")
+    u0s = [stepper.initial_state(w) for w in ws]
+    outs = _run(torch_cuda, ws, u0s, n, R, K, graph)
+    for w, u0, got in zip(ws, u0s, outs):
+        assert np.array_equal(got, _run(torch_cuda, w, u0, n, 1, 1, False)), w.name
+
+
+N_ADJ = 40
+
+
+def draw_adjoint(case: int):
+    """A forward draw of an equation with an adjoint (not viscous Burgers),
+    with a kernel family and a checkpoint interval."""
+    rng = np.random.default_rng(11000 + case)
+    for attempt in range(20):
+        w, n, R, K, graph = draw(2000 + 20 * case + attempt)
+        if w.equation != "viscous_burgers":
+            break
+    kernel = "stage" if rng.random() < 0.3 else "fused"
+    ckpt = int(rng.choice([1, 2, 5, 7, 64]))
+    return w, n, R, K, graph, kernel, ckpt
+
+
+def adjoint_tolerance(w, u0, n, ref, g_o, ga_o):
+    """Bars for dJ/du0 and dJ/da: 1e-12 (dJ/da: 1e-11, a sum over every
+    element, stage and step), or 30 x the oracle's own change under a
+    rounding-level perturbation of the initial state."""
+    rng = np.random.default_rng(54321)
+    u1 = u0 * (1.0 + 1e-16 * rng.standard_normal(u0.shape))
+    _, g1, ga1 = oadj.gradient(w, u1, n, oadj.misfit_cotangent(ref))
+    tol_g = max(TOL, 30.0 * stats.rel_l2(g1, g_o))
+    tol_a = max(1e-11 * max(1.0, abs(ga_o)), 30.0 * abs(ga1 - ga_o))
+    return tol_g, tol_a
+
+
+def test_adjoint_draws_have_adjoints():
+    kinds = set()
+    for c in range(N_ADJ):
+        w, n, R, K, graph, kernel, ckpt = draw_adjoint(c)
+        assert w.equation in ("advection", "burgers")
+        kinds.add((w.equation, kernel))
+    assert kinds == {("advection", "fused"), ("advection", "stage"), ("burgers", "fused"), ("burgers", "stage")}
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("case", range(N_ADJ))
+def test_random_adjoint_matches_oracle(torch_cuda, case):
+    """Recorded run (any launch shape, graph or not, any checkpoint interval)
+    and adg_adjoint against the oracle's reverse mode; dJ/du0 without dJ/da
+    is bitwise the full call's."""
+    from paper_2404_03399_amd.solver import Solver
+    w, n, R, K, graph, kernel, ckpt = draw_adjoint(case)
+    _say(f"random adjoint {case}: {w.equation} {w.flux} {w.scheme} {w.rk} p={w.degree} N={w.n_elem} "
+         f"pe={w.pe_size} q={w.at_levels} L={w.n_delays} per_stage={w.per_stage} caa={w.caa} a={w.speed:.3f} "
+         f"steps={n} kernel={kernel} C={ckpt} R={R} K={K} graph={graph}")
+    u0 = stepper.initial_state(w)
+    ref = np.random.default_rng(case).standard_normal(u0.shape)
+    ut_o, g_o, ga_o = oadj.gradient(w, u0, n, oadj.misfit_cotangent(ref))
+    fused = kernel == "fused"
+    s = Solver(w, kernel=kernel, n_steps_record=n, ckpt_every=ckpt, lane_elems=R if fused else 0,
+               fused_steps=K if fused else 0)
+    u = s.pack(u0)
+    s.run(u, n, graph=graph, record=True)
+    ut = s.unpack(u)[0]
+    cot = s.pack(ut - ref)
+    g, gs = s.adjoint(cot)
+    g2, gs2 = s.adjoint(cot, want_speed=False)
+    torch_cuda.cuda.synchronize()
+    gl, gl2 = s.unpack(g)[0], s.unpack(g2)[0]
+    s.close()
+    assert gs2 is None and np.array_equal(gl, gl2)
+    tol_g, tol_a = adjoint_tolerance(w, u0, n, ref, g_o, ga_o)
+    assert stats.rel_l2(ut, ut_o) <= tolerance(w, u0, n, ut_o)
+    assert stats.rel_l2(gl, g_o) <= tol_g, (stats.rel_l2(gl, g_o), tol_g)
+    if w.equation == "advection":
+        assert abs(gs[0] - ga_o) <= tol_a, (gs[0], ga_o, tol_a)
