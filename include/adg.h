@@ -43,6 +43,7 @@
  *   - A context is not thread-safe.  All problems of one context advance
  *     together and must share equation, flux, rk and scheme; degree, mesh,
  *     PE size, delays, seed, speed and dt may differ (batched ensembles).
+ *     Each problem of a batch advances bitwise as in a context of its own.
  */
 #ifndef ADG_H
 #define ADG_H

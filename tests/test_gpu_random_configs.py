@@ -39,15 +39,20 @@ def torch_cuda():
     return torch
 
 
-def draw(case: int):
-    """One configuration, a pure function of the case number."""
-    rng = np.random.default_rng(7000 + case)
+def draw(case: int, large: bool = False):
+    """One configuration, a pure function of the case number (large: meshes
+    of 20000 to 100000 elements, so that a launch's waves start in several
+    rounds and late waves meet what early ones wrote)."""
+    rng = np.random.default_rng((31000 if large else 7000) + case)
     eq = str(rng.choice(["advection", "advection", "advection", "burgers", "burgers", "viscous_burgers"]))
     scheme = str(rng.choice(["dg", "adg", "adg_at", "adg_at"]))
     rk = str(rng.choice(["heun", "ssprk3", "rk4", "lsrk3"]))
     p = int(rng.integers(1, 5))
     pe = int(rng.choice(PE_SIZES))
-    n_pe = int(rng.integers(1, max(2, 2000 // pe) + 1))
+    if large:
+        n_pe = int(rng.integers(max(1, 20000 // pe), max(2, 100000 // pe) + 1))
+    else:
+        n_pe = int(rng.integers(1, max(2, 2000 // pe) + 1))
     ne = max(2, pe * n_pe)
     if ne % pe:
         pe = ne
@@ -55,7 +60,7 @@ def draw(case: int):
     probs = ("1/3", "1/3", "1/3") if caa else DELAY_SETS[int(rng.integers(len(DELAY_SETS)))]
     per_stage = False if caa else bool(rng.random() < 0.5)
     q = int(rng.integers(0, p + 2)) if scheme == "adg_at" else 0
-    n_steps = int(rng.integers(5, 26))
+    n_steps = int(rng.integers(4, 11)) if large else int(rng.integers(5, 26))
     graph = bool(rng.random() < 0.5)
     dx = W.TWO_PI / ne
     if eq == "advection":
@@ -186,6 +191,27 @@ def test_random_config_matches_oracle(torch_cuda, case):
     st = _run(torch_cuda, w, u0, n, 0, 0, graph, kernel="stage")
     err_s = stats.rel_l2(st, ref)
     assert err_s <= tol, (err_s, tol)
+
+
+N_LARGE = 24
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("case", range(N_LARGE))
+def test_random_large_config_matches_oracle(torch_cuda, case):
+    """Large meshes: the launch shapes still agree bitwise and the oracle
+    still agrees, with waves dispatched over several rounds."""
+    w, n, R, K, graph = draw(case, large=True)
+    _say(f"random large case {case}: {w.equation} {w.flux} {w.scheme} {w.rk} p={w.degree} N={w.n_elem} "
+         f"pe={w.pe_size} q={w.at_levels} L={w.n_delays} per_stage={w.per_stage} caa={w.caa} "
+         f"steps={n} R={R} K={K} graph={graph}")
+    u0 = stepper.initial_state(w)
+    ref = stepper.Stepper(w).run(u0, n)
+    got = _run(torch_cuda, w, u0, n, R, K, graph)
+    assert np.array_equal(got, _run(torch_cuda, w, u0, n, 1, 1, False))
+    assert np.array_equal(got, _run(torch_cuda, w, u0, n, R, 3 - K, not graph))
+    err, tol = stats.rel_l2(got, ref), tolerance(w, u0, n, ref)
+    assert err <= tol, (err, tol)
 
 
 N_BATCH = 40
