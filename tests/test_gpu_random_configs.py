@@ -301,3 +301,60 @@ def test_random_adjoint_matches_oracle(torch_cuda, case):
     assert stats.rel_l2(gl, g_o) <= tol_g, (stats.rel_l2(gl, g_o), tol_g)
     if w.equation == "advection":
         assert abs(gs[0] - ga_o) <= tol_a, (gs[0], ga_o, tol_a)
+
+
+N_SEQ = 40
+
+
+def draw_sequence(case: int):
+    """A configuration and a random split of its steps into calls: single
+    steps and runs of 1 to 40 steps, each with or without graph replay."""
+    rng = np.random.default_rng(13000 + case)
+    w, _, R, K, _ = draw(4000 + case)
+    calls = []
+    for _ in range(int(rng.integers(3, 9))):
+        if rng.random() < 0.3:
+            calls.append(("step", 1, False))
+        else:
+            calls.append(("run", int(rng.integers(1, 41)), bool(rng.random() < 0.5)))
+    return w, R, K, calls
+
+
+def test_sequence_draws_mix_calls():
+    kinds = set()
+    for c in range(N_SEQ):
+        _, _, _, calls = draw_sequence(c)
+        kinds |= {(k, g, m >= 16) for k, m, g in calls}
+    assert {("step", False, False), ("run", True, True), ("run", False, True), ("run", True, False)} <= kinds
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("case", range(N_SEQ))
+def test_random_call_sequence_equals_one_run(torch_cuda, case):
+    """Steps split over any sequence of adg_step / adg_run calls (graph or
+    direct, runs shorter or longer than the captured batch) give bitwise the
+    state of one uninterrupted run, which matches the oracle (where the
+    oracle's own rounding response stays below 1e-8: a few long viscous
+    draws grow an unstable mode and only the bitwise check is meaningful)."""
+    from paper_2404_03399_amd.solver import Solver
+    w, R, K, calls = draw_sequence(case)
+    total = sum(m for _, m, _ in calls)
+    _say(f"random call sequence {case}: {w.equation} {w.flux} {w.scheme} {w.rk} p={w.degree} N={w.n_elem} "
+         f"pe={w.pe_size} R={R} K={K} calls={calls}")
+    u0 = stepper.initial_state(w)
+    s = Solver(w, kernel="fused", lane_elems=R, fused_steps=K)
+    u = s.pack(u0)
+    for kind, m, graph in calls:
+        if kind == "step":
+            s.step(u)
+        else:
+            s.run(u, m, graph=graph)
+    torch_cuda.cuda.synchronize()
+    assert s.steps_taken() == total
+    got = s.unpack(u)[0]
+    s.close()
+    assert np.array_equal(got, _run(torch_cuda, w, u0, total, R, K, False))
+    ref = stepper.Stepper(w).run(u0, total)
+    err, tol = stats.rel_l2(got, ref), tolerance(w, u0, total, ref)
+    if tol <= 1e-8:
+        assert err <= tol, (err, tol)
