@@ -63,7 +63,7 @@ struct DevProblem {
   int32_t np;            // degree + 1
   int32_t q;             // AT levels (1 for ADG)
   int32_t n_delays;      // L
-  int32_t depth;         // ring slots per (boundary, stage): L + q - 1
+  int32_t depth;         // ring slots per (boundary, stage): L + q, or the recorded steps + L + q
   int32_t per_stage;     // delay key includes the stage
   int32_t scheme;        // Scheme
   int32_t async_faces;   // 1 if PE faces use delayed data (scheme != DG and P > 1)
