@@ -358,3 +358,46 @@ def test_random_call_sequence_equals_one_run(torch_cuda, case):
     err, tol = stats.rel_l2(got, ref), tolerance(w, u0, total, ref)
     if tol <= 1e-8:
         assert err <= tol, (err, tol)
+
+
+N_STATS = 24
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("case", range(N_STATS))
+def test_random_batch_statistics_match_oracle(torch_cuda, case):
+    """adg_error_stats and adg_ensemble_stats on a random batch, after a
+    run, against random reference states: per problem the spatial mean and
+    maximum of |u - ref| and the integral of u (Sec. 6.2 error measure), and
+    per random group of problems the two-pass mean and variance of both."""
+    from paper_2404_03399_amd.solver import Solver
+    ws, n, R, K, graph = draw_batch(200 + case)
+    rng = np.random.default_rng(17000 + case)
+    n_groups = int(rng.integers(1, min(3, len(ws)) + 1))
+    group = [int(g) for g in rng.integers(0, n_groups, len(ws))]
+    group[:n_groups] = list(range(n_groups))  # no empty group
+    _say(f"random statistics {case}: {len(ws)} x {ws[0].equation} {ws[0].scheme}, N={[w.n_elem for w in ws]} "
+         f"groups={group} steps={n} R={R} K={K}")
+    s = Solver(ws, kernel="fused", lane_elems=R, fused_steps=K)
+    u = s.pack([stepper.initial_state(w) for w in ws])
+    s.run(u, n, graph=graph)
+    refs = [rng.standard_normal((w.n_elem, w.degree + 1)) for w in ws]
+    r = s.pack(refs)
+    got = s.error_stats(u, r)
+    ens = s.ensemble_stats(u, r, group, n_groups)
+    torch_cuda.cuda.synchronize()
+    outs = s.unpack(u)
+    s.close()
+    per = []
+    for w, o, rf, g in zip(ws, outs, refs, got):
+        m, mx = stats.mean_abs(o, rf), stats.max_abs(o, rf)
+        assert abs(g[0] - m) <= 1e-13 * max(1.0, m) and g[1] == mx
+        assert abs(g[2] - stepper.Stepper(w).integral(o)) <= 1e-12 * max(1.0, np.abs(o).max() * w.length)
+        per.append((m, mx))
+    for gi in range(n_groups):
+        vals = [per[i] for i in range(len(ws)) if group[i] == gi]
+        m0, v0 = stats.ensemble_mean_var([v[0] for v in vals])
+        m1, v1 = stats.ensemble_mean_var([v[1] for v in vals])
+        assert abs(ens[gi][0] - m0) <= 1e-13 * m0 and abs(ens[gi][2] - m1) <= 1e-13 * m1
+        assert abs(ens[gi][1] - v0) <= 1e-12 * (m0 * m0 + v0)
+        assert abs(ens[gi][3] - v1) <= 1e-12 * (m1 * m1 + v1)
