@@ -2,15 +2,19 @@
 integrator, degree, mesh and PE size (every divisor class: 1, odd, powers of
 two, not a multiple of the lane group), AT levels, delay distribution and
 granularity, the communication-avoiding cycle, speed sign and launch shape
-(R elements per lane, K steps per launch, graph or direct).  Each case is
-compared with the oracle and, bitwise, with the one-element one-step launch
-and with the other steps-per-launch count of the same problem.  The bar is relative L2 <= 1e-12, or 30 times the
-oracle's own response to a relative input perturbation of 1e-16 where that
-is larger: some draws are ill-conditioned (every PE face at the largest
-delay with high-order ALDG-AT turns rounding-level differences into 2e-11
-within 22 steps), and no FP64 evaluation order can agree more closely than
-that; a wrong term or index moves the result by orders of magnitude more.
-The draws are fixed by their seeds, so every run checks the same cases."""
+(R elements per lane, K steps per launch, graph or direct); random batches,
+adjoints, call sequences and statistics.  Each case is compared with the
+oracle and, bitwise, with other launch shapes of the same problem.
+
+The bar is relative L2 <= 1e-12, or 30 times the oracle's own response to a
+relative input perturbation of 1e-16 where that is larger: some draws are
+ill-conditioned (viscous Burgers with AT of high q on the local DG fluxes
+turns rounding-level differences into 1e-12 to 1e-9), and no FP64
+evaluation order can agree more closely than that; a wrong term or index
+moves the result by orders of magnitude more.  Where even that response
+exceeds 1e-8 (an unstable mode, two draws in 400) only the bitwise checks
+are made.  The draws are fixed by their seeds, so every run checks the same
+cases."""
 import sys
 
 import numpy as np
@@ -20,7 +24,8 @@ from paper_2404_03399_amd import workloads as W
 from oracle import adjoint as oadj, stats, stepper
 
 TOL = 1e-12
-N_CASES = 160
+ORACLE_BAR = 1e-8  # above this the oracle's own rounding response makes the comparison meaningless
+N_CASES = 400
 SIGMA = {1: 0.05, 2: 0.01, 3: 0.005, 4: 0.001}
 PE_SIZES = (1, 2, 3, 4, 5, 7, 8, 9, 13, 16, 20, 31, 64, 100, 129)
 DELAY_SETS = (W.DELAYS_C2, ("1/3", "1/3", "1/3"), ("0.3", "0.4", "0.3"), ("0.5", "0.5"), ("0", "0", "1"))
@@ -87,12 +92,21 @@ def draw(case: int, large: bool = False):
     return w, n_steps, R, K, graph
 
 
+def same(a, b) -> bool:
+    """Bitwise-equal states (a NaN of a blown-up draw matches a NaN)."""
+    return np.array_equal(a, b, equal_nan=True)
+
+
 def tolerance(w, u0, n, ref) -> float:
     """The bar for one case: TOL, or 30 x the oracle's own change under a
-    rounding-level (1e-16 relative) perturbation of the initial state."""
+    rounding-level (1e-16 relative) perturbation of the initial state;
+    infinite where the oracle run itself blows up."""
     rng = np.random.default_rng(12345)
     u1 = u0 * (1.0 + 1e-16 * rng.standard_normal(u0.shape))
-    return max(TOL, 30.0 * stats.rel_l2(stepper.Stepper(w).run(u1, n), ref))
+    r1 = stepper.Stepper(w).run(u1, n)
+    if not (np.isfinite(ref).all() and np.isfinite(r1).all()):
+        return float("inf")
+    return max(TOL, 30.0 * stats.rel_l2(r1, ref))
 
 
 def draw_batch(case: int):
@@ -161,8 +175,11 @@ def test_draws_are_valid_and_varied():
 
 
 def test_tolerance_is_tight_except_for_ill_conditioned_draws():
-    """The bar stays at 1e-12 for all but the adversarial draws, and the
-    relaxed bar stays far below what a wrong term would cost."""
+    """The bar stays at 1e-12 for all but a few draws, all of them viscous
+    Burgers with AT on the local DG fluxes (high q), where the oracle itself
+    answers a rounding-level perturbation with 1e-12 or more; in two of
+    them an unstable mode takes that to 1e-5 and only the bitwise checks
+    remain meaningful."""
     relaxed = []
     for c in range(N_CASES):
         w, n, *_ = draw(c)
@@ -170,7 +187,9 @@ def test_tolerance_is_tight_except_for_ill_conditioned_draws():
         tol = tolerance(w, u0, n, stepper.Stepper(w).run(u0, n))
         if tol > TOL:
             relaxed.append((c, tol))
-    assert len(relaxed) <= N_CASES // 20 and all(t < 1e-8 for _, t in relaxed), relaxed
+            assert w.equation == "viscous_burgers" and w.scheme == "adg_at", (c, tol)
+    assert len(relaxed) <= N_CASES // 20, relaxed
+    assert sum(t > ORACLE_BAR for _, t in relaxed) <= N_CASES // 100, relaxed
 
 
 @pytest.mark.gpu
@@ -183,14 +202,15 @@ def test_random_config_matches_oracle(torch_cuda, case):
     u0 = stepper.initial_state(w)
     ref = stepper.Stepper(w).run(u0, n)
     got = _run(torch_cuda, w, u0, n, R, K, graph)
-    assert np.array_equal(got, _run(torch_cuda, w, u0, n, 1, 1, False))
-    assert np.array_equal(got, _run(torch_cuda, w, u0, n, R, 3 - K, not graph))
+    assert same(got, _run(torch_cuda, w, u0, n, 1, 1, False))
+    assert same(got, _run(torch_cuda, w, u0, n, R, 3 - K, not graph))
     err, tol = stats.rel_l2(got, ref), tolerance(w, u0, n, ref)
-    assert err <= tol, (err, tol)
-    # the per-stage kernels: the same map, rounded in their own order
-    st = _run(torch_cuda, w, u0, n, 0, 0, graph, kernel="stage")
-    err_s = stats.rel_l2(st, ref)
-    assert err_s <= tol, (err_s, tol)
+    if tol <= ORACLE_BAR:
+        assert err <= tol, (err, tol)
+        # the per-stage kernels: the same map, rounded in their own order
+        st = _run(torch_cuda, w, u0, n, 0, 0, graph, kernel="stage")
+        err_s = stats.rel_l2(st, ref)
+        assert err_s <= tol, (err_s, tol)
 
 
 N_LARGE = 24
@@ -208,13 +228,14 @@ def test_random_large_config_matches_oracle(torch_cuda, case):
     u0 = stepper.initial_state(w)
     ref = stepper.Stepper(w).run(u0, n)
     got = _run(torch_cuda, w, u0, n, R, K, graph)
-    assert np.array_equal(got, _run(torch_cuda, w, u0, n, 1, 1, False))
-    assert np.array_equal(got, _run(torch_cuda, w, u0, n, R, 3 - K, not graph))
+    assert same(got, _run(torch_cuda, w, u0, n, 1, 1, False))
+    assert same(got, _run(torch_cuda, w, u0, n, R, 3 - K, not graph))
     err, tol = stats.rel_l2(got, ref), tolerance(w, u0, n, ref)
-    assert err <= tol, (err, tol)
+    if tol <= ORACLE_BAR:
+        assert err <= tol, (err, tol)
 
 
-N_BATCH = 40
+N_BATCH = 80
 
 
 @pytest.mark.gpu
@@ -229,10 +250,10 @@ def test_random_batch_matches_single_runs(torch_cuda, case):
     u0s = [stepper.initial_state(w) for w in ws]
     outs = _run(torch_cuda, ws, u0s, n, R, K, graph)
     for w, u0, got in zip(ws, u0s, outs):
-        assert np.array_equal(got, _run(torch_cuda, w, u0, n, 1, 1, False)), w.name
+        assert same(got, _run(torch_cuda, w, u0, n, 1, 1, False)), w.name
 
 
-N_ADJ = 40
+N_ADJ = 100
 
 
 def draw_adjoint(case: int):
@@ -295,7 +316,9 @@ def test_random_adjoint_matches_oracle(torch_cuda, case):
     torch_cuda.cuda.synchronize()
     gl, gl2 = s.unpack(g)[0], s.unpack(g2)[0]
     s.close()
-    assert gs2 is None and np.array_equal(gl, gl2)
+    assert gs2 is None and same(gl, gl2)
+    if tolerance(w, u0, n, ut_o) > ORACLE_BAR:
+        return  # the forward run is ill-conditioned or blows up: only the bitwise check holds
     tol_g, tol_a = adjoint_tolerance(w, u0, n, ref, g_o, ga_o)
     assert stats.rel_l2(ut, ut_o) <= tolerance(w, u0, n, ut_o)
     assert stats.rel_l2(gl, g_o) <= tol_g, (stats.rel_l2(gl, g_o), tol_g)
@@ -303,7 +326,7 @@ def test_random_adjoint_matches_oracle(torch_cuda, case):
         assert abs(gs[0] - ga_o) <= tol_a, (gs[0], ga_o, tol_a)
 
 
-N_SEQ = 40
+N_SEQ = 80
 
 
 def draw_sequence(case: int):
@@ -353,10 +376,10 @@ def test_random_call_sequence_equals_one_run(torch_cuda, case):
     assert s.steps_taken() == total
     got = s.unpack(u)[0]
     s.close()
-    assert np.array_equal(got, _run(torch_cuda, w, u0, total, R, K, False))
+    assert same(got, _run(torch_cuda, w, u0, total, R, K, False))
     ref = stepper.Stepper(w).run(u0, total)
     err, tol = stats.rel_l2(got, ref), tolerance(w, u0, total, ref)
-    if tol <= 1e-8:
+    if tol <= ORACLE_BAR:
         assert err <= tol, (err, tol)
 
 
