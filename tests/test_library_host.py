@@ -172,3 +172,102 @@ def test_autotune_admissible_candidates():
     assert autotune.admissible([w]) == [1, 2, 4]
     assert autotune.admissible([replace(w, pe_size=2, n_elem=64)]) == [1, 2]
     assert autotune.admissible([replace(w, scheme="dg", pe_size=1)]) == [1, 2, 4]
+
+
+def _documented_valid(p, opt, n_rec) -> bool:
+    """The constraints include/adg.h states for one problem and the options."""
+    import math
+    eq, sch, fl = p.equation, p.scheme, p.flux
+    L_, q = p.n_delays, p.at_levels
+    ok = (p.abi_version == adg.ADG_ABI_VERSION and eq in (0, 1, 2) and sch in (0, 1, 2) and p.rk in (0, 1, 2, 3)
+          and 1 <= p.degree <= 4 and 1 <= L_ <= 8 and p.delay_granularity in (0, 1, 2) and p.reserved == 0
+          and p.n_elem >= 2 and p.pe_size >= 1 and p.n_elem % p.pe_size == 0
+          and math.isfinite(p.length) and p.length > 0 and math.isfinite(p.dt) and p.dt > 0
+          and math.isfinite(p.x_left))
+    if not ok:
+        return False
+    if fl in (0, 1) and eq != 0:
+        return False
+    if fl == 2 and eq == 0:
+        return False
+    if fl not in (0, 1, 2):
+        return False
+    if eq == 0 and not (math.isfinite(p.speed) and p.speed != 0):
+        return False
+    if eq == 2 and not (math.isfinite(p.viscosity) and p.viscosity >= 0):
+        return False
+    if eq != 2 and p.viscosity != 0:
+        return False
+    if not (q == 0 or (1 <= q <= 5 and sch == 2)):
+        return False
+    if p.delay_granularity == 2 and L_ != 3:  # the communication-avoiding cycle
+        return False
+    thr = [p.delay_threshold[i] for i in range(L_ - 1)]
+    if any(t > (1 << 53) for t in thr) or any(b < a for a, b in zip(thr, thr[1:])):
+        return False
+    if opt.ckpt_every < 0 or opt.kernel not in (0, 1, 2) or opt.flags != 0 or opt.fused_steps not in (0, 1, 2):
+        return False
+    if opt.lane_elems not in (0, 1, 2, 4):
+        return False
+    async_ = sch != 0 and p.n_elem // p.pe_size > 1
+    if async_ and opt.lane_elems > p.pe_size:
+        return False
+    return 0 <= n_rec <= (1 << 28)
+
+
+def test_random_descriptors_are_validated(L):
+    """Random mutations of valid descriptors and options: adg_state_layout
+    and adg_workspace_size return a documented status and never crash, a
+    valid draw is accepted, and nothing outside the documented constraints
+    is accepted."""
+    import ctypes as C
+    import sys
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    from test_gpu_random_configs import draw
+    rng = np.random.default_rng(2024)
+    ints = [0, 1, 2, 3, 4, 5, 7, 8, 9, 64, -1, 2 ** 31 - 1, 2 ** 32 - 1]
+    dbls = [0.0, -0.0, 1.0, -1.0, 1e-300, 1e300, float("nan"), float("inf"), -float("inf")]
+    fields_i = ["abi_version", "equation", "scheme", "flux", "rk", "degree", "at_levels", "n_delays",
+                "delay_granularity", "reserved", "n_elem", "pe_size"]
+    fields_d = ["x_left", "length", "speed", "dt", "viscosity"]
+    codes = {0, adg.ADG_E_INVALID, adg.ADG_E_ABI, adg.ADG_E_UNSUPPORTED}
+    accepted_invalid = []
+    for it in range(3000):
+        w, *_ = draw(int(rng.integers(400)))
+        p = solver.to_problem(w)
+        opt = adg.adg_options()
+        opt.kernel = int(rng.choice([0, 1, 2]))
+        opt.lane_elems = int(rng.choice([0, 1, 2, 4])) if w.equation != "viscous_burgers" else 0
+        if w.scheme != "dg" and w.n_elem // w.pe_size > 1:
+            opt.lane_elems = min(opt.lane_elems, 1 if w.pe_size < 2 else (2 if w.pe_size < 4 else opt.lane_elems))
+        opt.fused_steps = int(rng.choice([0, 1, 2]))
+        n_rec = 0
+        mutate = it % 4 != 0  # every fourth draw stays valid
+        if mutate:
+            for _ in range(int(rng.integers(1, 4))):
+                r = rng.random()
+                if r < 0.55:
+                    setattr(p, str(rng.choice(fields_i)), int(rng.choice(ints)) % (1 << 32)
+                            if rng.random() < 0.9 else int(rng.integers(0, 1 << 31)))
+                elif r < 0.85:
+                    setattr(p, str(rng.choice(fields_d)), float(rng.choice(dbls)))
+                elif r < 0.92:
+                    p.delay_threshold[int(rng.integers(7))] = int(rng.choice([0, 1 << 52, (1 << 53) + 1, (1 << 64) - 1]))
+                else:
+                    opt.lane_elems = int(rng.choice([-1, 3, 8]))
+                    opt.flags = int(rng.choice([0, 1]))
+                    opt.ckpt_every = int(rng.choice([-1, 0, 5]))
+                    opt.fused_steps = int(rng.choice([0, 3, -1])) % (1 << 32)
+        arr = (adg.adg_problem * 1)(p)
+        offs, lds, tot, out = (C.c_int64 * 1)(), (C.c_int64 * 1)(), C.c_int64(), C.c_int64()
+        rc1 = L.adg_state_layout(arr, 1, offs, lds, C.byref(tot))
+        rc2 = L.adg_workspace_size(arr, 1, C.byref(opt), n_rec, C.byref(out))
+        assert rc1 in codes and rc2 in codes, (it, rc1, rc2)
+        valid = _documented_valid(p, opt, n_rec)
+        if not mutate:
+            assert valid and rc2 == 0, (it, rc2, adg.adg_last_error())
+        if rc2 == 0 and not valid:
+            accepted_invalid.append((it, {f: getattr(p, f) for f in fields_i + fields_d}))
+        if rc2 == 0:
+            assert rc1 == 0 and out.value > 0 and tot.value > 0
+    assert not accepted_invalid, accepted_invalid[:5]
