@@ -443,7 +443,8 @@ __device__ __forceinline__ void adj_tile2(const DevProblem& P, const WorkItem wi
 #pragma unroll
     for (int j = 0; j < NP; ++j) lo[j * ld + e] = l0[j];
 
-  // levels n - d, d = 1 .. L + q - 2, of each owned PE face and stage
+  // levels n - d of each owned PE face and stage that either step reaches:
+  // d >= 1 up to (L - 1) + (q - 1), taken at the largest L and q
   constexpr int W = (kMaxL - 1) + (kMaxQ - 1);
   const uint64_t m_own = __ballot(pe && owned);
   const int n_sc = S * W * __builtin_popcountll(m_own);
