@@ -417,7 +417,10 @@ def main():
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the one-context-per-problem ensemble run")
     ap.add_argument("--no-adjoint-stage", action="store_true", help="skip the per-stage adjoint comparison")
-    ap.add_argument("--no-experiments", action="store_true", help="skip the Sec. 6.2 scaling experiments")
+    ap.add_argument("--no-experiments", action="store_true",
+                    help="skip the Sec. 6.2 scaling experiments and the Burgers / viscous Burgers timings")
+    ap.add_argument("--no-scaling", action="store_true",
+                    help="skip only the Sec. 6.2 scaling experiments (keep the Burgers / viscous Burgers timings)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -536,7 +539,8 @@ def main():
         out["ensemble"] = bench_ensemble(torch, W, Solver, args.ensemble_steps, args.ensemble_real,
                                          not args.no_plain)
     if not args.no_experiments:
-        out["experiments"] = bench_experiments()
+        if not args.no_scaling:
+            out["experiments"] = bench_experiments()
         out["viscous_burgers"] = bench_viscous_burgers(torch, W, Solver)
         out["burgers"] = bench_burgers(torch, W, Solver)
     if not args.no_cpu:
