@@ -110,8 +110,10 @@ class Tape:
         self.u_final = u
 
 
-def gradient(w, u0, n_steps, cot_fn):
-    """Returns (u_T, dJ/du0, dJ/da) where cot_fn(u_T) = dJ/du_T."""
+def gradient(w, u0, n_steps, cot_fn, with_scale=False):
+    """Returns (u_T, dJ/du0, dJ/da) where cot_fn(u_T) = dJ/du_T; with_scale
+    also returns the sum of |terms| of dJ/da, the scale of its rounding
+    error (dJ/da is a cancelling sum over every DOF, stage and step)."""
     tape = Tape(w, u0, n_steps)
     st = tape.st
     a_tab, b_tab = BUTCHER[w.rk]
@@ -121,6 +123,7 @@ def gradient(w, u0, n_steps, cot_fn):
     lam = np.array(cot_fn(tape.u_final), dtype=np.float64)
     adj_ring = {}                    # (level, stage) -> sensitivity of the raw PE flux per boundary
     dj_da = 0.0
+    dj_da_scale = 0.0
     minv = np.linalg.inv(st.mass)
     faces = st.faces
     left_of = (faces - 1) % ne
@@ -138,6 +141,7 @@ def gradient(w, u0, n_steps, cot_fn):
             # dJ/da through the explicit speed dependence of this stage (linear advection)
             if w.equation == "advection":
                 dj_da += float(np.sum(lk * kvals[i])) / st.a
+                dj_da_scale += float(np.sum(np.abs(lk * kvals[i]))) / abs(st.a)
             # transpose of K = (2/dx) M^-1 (S f(y) + phi(-1) F_l - phi(1) F_r)
             wv = (2.0 / st.dx) * (lk @ minv.T)                # M^-T lk per element
             m_i = (wv @ st.stiff) * _dflux_fn(st, y)           # S^T w, times f'(y)
@@ -167,6 +171,8 @@ def gradient(w, u0, n_steps, cot_fn):
             mu[i] = m_i
             lam_u = lam_u + m_i
         lam = lam_u
+    if with_scale:
+        return tape.u_final, lam, dj_da, dj_da_scale
     return tape.u_final, lam, dj_da
 
 
