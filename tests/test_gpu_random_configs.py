@@ -32,7 +32,8 @@ ORACLE_BAR = 1e-8  # above this the oracle's own rounding response makes the com
 N_CASES = 400
 SIGMA = {1: 0.05, 2: 0.01, 3: 0.005, 4: 0.001}
 PE_SIZES = (1, 2, 3, 4, 5, 7, 8, 9, 13, 16, 20, 31, 64, 100, 129)
-DELAY_SETS = (W.DELAYS_C2, ("1/3", "1/3", "1/3"), ("0.3", "0.4", "0.3"), ("0.5", "0.5"), ("0", "0", "1"))
+DELAY_SETS = (W.DELAYS_C2, ("1/3", "1/3", "1/3"), ("0.3", "0.4", "0.3"), ("0.5", "0.5"), ("0", "0", "1"),
+              ("1/8",) * 8, ("0", "0", "0", "0", "0", "0", "0", "1"), ("1",))
 
 
 def _say(msg):
