@@ -273,27 +273,42 @@ __device__ __forceinline__ int64_t rec_slot(int64_t m) { return (int64_t)((uint3
 // m - kd - j that precede step n, j = q-1 down to 0, oldest first, one
 // explicit FMA per level; rb is the ring of one (boundary, stage), slot_n =
 // n mod depth.  The loads are unrolled over kMaxQ and issue together.
-__device__ __forceinline__ double at_old_levels(const DevProblem& P, const double* __restrict__ rb, int ahead,
-                                                int kd, int slot_n, int depth) {
-#pragma clang fp contract(off)
+// Its two halves: the loads (issued together, so that a caller can issue
+// other loads before it waits for these) and the sum.
+struct AtLevels {
   double c[kMaxQ], v[kMaxQ];
   bool use[kMaxQ];
+};
+
+__device__ __forceinline__ void at_old_levels_load(const DevProblem& P, const double* __restrict__ rb, int ahead,
+                                                   int kd, int slot_n, int depth, AtLevels& L) {
 #pragma unroll
   for (int j = 0; j < kMaxQ; ++j) {
     const int back = kd + j - ahead;  // level n - back
-    use[j] = kd > 0 && j < P.q && back >= 1;
-    c[j] = 0.0;
-    v[j] = 0.0;
-    if (use[j]) {
-      c[j] = P.atc[kd][j];
-      v[j] = rb[ring_slot(slot_n, back, depth)];
+    L.use[j] = kd > 0 && j < P.q && back >= 1;
+    L.c[j] = 0.0;
+    L.v[j] = 0.0;
+    if (L.use[j]) {
+      L.c[j] = P.atc[kd][j];
+      L.v[j] = rb[ring_slot(slot_n, back, depth)];
     }
   }
+}
+
+__device__ __forceinline__ double at_old_levels_sum(const AtLevels& L) {
+#pragma clang fp contract(off)
   double acc = 0.0;
 #pragma unroll
   for (int j = kMaxQ - 1; j >= 0; --j)
-    if (use[j]) acc = fma(c[j], v[j], acc);
+    if (L.use[j]) acc = fma(L.c[j], L.v[j], acc);
   return acc;
+}
+
+__device__ __forceinline__ double at_old_levels(const DevProblem& P, const double* __restrict__ rb, int ahead,
+                                                int kd, int slot_n, int depth) {
+  AtLevels L;
+  at_old_levels_load(P, rb, ahead, kd, slot_n, depth, L);
+  return at_old_levels_sum(L);
 }
 
 

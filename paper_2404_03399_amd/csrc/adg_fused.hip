@@ -105,25 +105,19 @@ __device__ __forceinline__ void wave_tile(const DevProblem& P, const WorkItem wi
     }
     const uint32_t e1 = (e[R - 1] + 1 == N) ? 0u : (uint32_t)(e[R - 1] + 1);
     pe_right = e1 == fast_div(e1, P.pe_div) * pes;
-    if (any_pe) {
+  }
+  // the records of this lane's PE face, into registers first: their loads,
+  // the state loads and the record jobs' ring loads below are all issued
+  // before the wave waits for any of them
+  double rec[K][S];
+  if (any_pe) {
 #pragma unroll
-      for (int kk = 0; kk < K; ++kk) {
-        const int64_t rs = rec_slot(n + kk);
-        kp[kk] = A.atk[P.atk_off + rs * P.n_pe + b];
-        const double* __restrict__ src = A.atsum + P.at_off + (rs * P.n_pe + b) * S;
+    for (int kk = 0; kk < K; ++kk) {
+      const int64_t rs = rec_slot(n + kk);
+      kp[kk] = A.atk[P.atk_off + rs * P.n_pe + b];
+      const double* __restrict__ src = A.atsum + P.at_off + (rs * P.n_pe + b) * S;
 #pragma unroll
-        for (int s = 0; s < S; ++s) sm.at[kk][wv][s][lane] = src[s];
-      }
-      if constexpr (K == 2) {
-        if (n == 0) {  // no launch has written the records of step 1: its delays, no past levels
-          kp[1] = 0;
-#pragma unroll
-          for (int s = 0; s < S; ++s) {
-            kp[1] |= pe_delay(P, 1, s, b) << (8 * s);
-            sm.at[1][wv][s][lane] = 0.0;
-          }
-        }
-      }
+      for (int s = 0; s < S; ++s) rec[kk][s] = src[s];
     }
   }
 
@@ -136,16 +130,38 @@ __device__ __forceinline__ void wave_tile(const DevProblem& P, const WorkItem wi
   const uint64_t owners = __ballot(own_pe);
   const int n_jobs = NJ * __builtin_popcountll(owners);
   const bool one_pass = n_jobs <= kWave;
-  if (owners != 0 && one_pass) {  // uniform: every lane takes part in the lane shuffle
+  const bool job_now = owners != 0 && one_pass;
+  int job_kd = 0;
+  AtLevels job_lv;
+  if (job_now) {  // uniform: every lane takes part in the lane shuffle
     const int fi = lane / NJ, jj = lane - fi * NJ, t = jj / S, s = jj - t * S;
     const uint32_t bo = (uint32_t)__shfl((int)b, nth_set_lane(owners, fi));
     if (lane < n_jobs) {
       const int64_t m = n + K + t;
-      const int kd = pe_delay(P, m, s, bo);
-      sm.kdj[wv][lane] = kd;
-      sm.part[wv][lane] =
-          at_old_levels(P, A.ring + P.ring_off + ((int64_t)bo * S + s) * depth, K + t, kd, slot_n, depth);
+      job_kd = pe_delay(P, m, s, bo);
+      at_old_levels_load(P, A.ring + P.ring_off + ((int64_t)bo * S + s) * depth, K + t, job_kd, slot_n, depth,
+                         job_lv);
     }
+  }
+  if (any_pe) {
+#pragma unroll
+    for (int kk = 0; kk < K; ++kk)
+#pragma unroll
+      for (int s = 0; s < S; ++s) sm.at[kk][wv][s][lane] = rec[kk][s];
+    if constexpr (K == 2) {
+      if (n == 0) {  // no launch has written the records of step 1: its delays, no past levels
+        kp[1] = 0;
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+          kp[1] |= pe_delay(P, 1, s, b) << (8 * s);
+          sm.at[1][wv][s][lane] = 0.0;
+        }
+      }
+    }
+  }
+  if (job_now && lane < n_jobs) {
+    sm.kdj[wv][lane] = job_kd;
+    sm.part[wv][lane] = at_old_levels_sum(job_lv);
   }
 
   // write the owned elements of the tile
