@@ -296,9 +296,13 @@ __device__ __forceinline__ void adj_tile(const DevProblem& P, const WorkItem wi,
     if (g < n_jobs) {
       const int kd = pe_delay(P, n, s, face);
       const int64_t rb = P.ring_off + ((int64_t)face * S + s) * depth;
+      // every load of the job before the first LDS write waits for one
+      const double adjn = adjring[rb + slot_n];
+      AtLevels lv;
+      if constexpr (FWD) at_old_levels_load(P, ring + rb, 0, kd, slot_n, depth, lv);
       sm.kd[wv][s][tgt] = (uint8_t)kd;
-      sm.adjn[wv][s][tgt] = adjring[rb + slot_n];
-      if constexpr (FWD) sm.atf[wv][s][tgt] = at_old_levels(P, ring + rb, 0, kd, slot_n, depth);
+      sm.adjn[wv][s][tgt] = adjn;
+      if constexpr (FWD) sm.atf[wv][s][tgt] = at_old_levels_sum(lv);
     }
   }
 
