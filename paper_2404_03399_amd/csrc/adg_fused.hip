@@ -24,8 +24,8 @@ namespace adg {
 // launch at step n the records hold, per face and stage, the delay and AT sum
 // of step n over its past levels and, for step n + 1, the delay and the part
 // of its AT sum over the levels up to n - 1; a two-step launch adds the
-// level-n term of step n + 1 itself (delay 1), from the raw flux the lane has
-// just computed.  So the PE faces of a launch read two records and nothing
+// level-n term of step n + 1 itself (delay 1), from the raw flux the lane
+// computed in the first step.  So the PE faces of a launch read two records and nothing
 // else; no lane reads what another wave writes in the same launch.  The owner
 // wave writes the records of steps n + K and n + K + 1 (levels up to
 // n + K - 1) into slots that no wave of the launch reads (slot = step mod 4),
@@ -231,11 +231,14 @@ __device__ __forceinline__ void wave_tile(const DevProblem& P, const WorkItem wi
         if (pe[r]) {
           const double raw = F[r];
           if (owned[r]) A.ring[P.ring_off + ((int64_t)b * S + s) * depth + slot_m] = raw;
-          if constexpr (K == 2) {  // level n completes step n+1's sum when its delay is 1
-            if (kk == 0 && ((kp[1] >> (8 * s)) & 0xff) == 1)
-              sm.at[1][wv][s][lane] = fma(P.atc[1][0], raw, sm.at[1][wv][s][lane]);
+          const int kd = (kp[kk] >> (8 * s)) & 0xff;
+          if (kd) {
+            double at = sm.at[kk][wv][s][lane];
+            if constexpr (K == 2) {  // delay 1 at step n+1: level n, this lane's raw flux of step n, completes the sum
+              if (kk == 1 && kd == 1) at = fma(P.atc[1][0], sm.at[0][wv][s][lane], at);
+            }
+            F[r] = at;
           }
-          if ((kp[kk] >> (8 * s)) & 0xff) F[r] = sm.at[kk][wv][s][lane];
           sm.at[kk][wv][s][lane] = raw;  // level n + kk, for the records formed at the end
         }
       }
