@@ -140,6 +140,11 @@ int adg_abi_version(void);
 /* Thread-local description of the last failure in this thread ("" if none). */
 const char* adg_last_error(void);
 
+/* Identity of this build: a hash of the library's source files (kernels,
+ * host code and this header), fixed when the library is compiled, so that a
+ * caller can refuse a library built from other sources.  Static string. */
+const char* adg_build_id(void);
+
 /* GLL nodes of the reference element [-1, 1] for the given degree (1..4):
  * writes degree+1 doubles to host array xi.  Lets callers build nodal
  * initial data u[j*ld+e] = u0(x_left + e*dx + (xi[j]+1)*dx/2). */
@@ -175,9 +180,17 @@ int adg_step_count(const adg_ctx* ctx, int64_t* steps);
 /* One RK time step of every problem, in place on the device state d_u. */
 int adg_step(adg_ctx* ctx, double* d_u);
 
-/* n_steps RK time steps in place on d_u.  flags: ADG_RUN_GRAPH,
- * ADG_RUN_RECORD (the context must be at step 0 and n_steps <= the recording
- * horizon given to adg_init), ADG_RUN_CHECK_FINITE. */
+/* n_steps RK time steps in place on d_u (device, state layout, 16-byte
+ * aligned): the RK stages of Sec. 4.2.1 (and the integrators of adg_rk) with
+ * the element update of Sec. 2, PE faces reading the AT combination of
+ * delayed levels (Secs. 4.1, 5), delays drawn as in Sec. 6.1.  flags:
+ * ADG_RUN_GRAPH (steps in batches of 16 replayed from a hipGraph captured
+ * for this d_u on first use; with n_steps = 0 the graph is only captured, so
+ * that a later timed run replays it without capture cost), ADG_RUN_RECORD
+ * (the context must be at step 0 and n_steps <= the recording horizon given
+ * to adg_init), ADG_RUN_CHECK_FINITE.  Errors: ADG_E_INVALID (null or
+ * misaligned d_u, n_steps < 0, step index past 2^31 - 1, unknown flags),
+ * ADG_E_STATE (recording misuse), ADG_E_HIP, ADG_E_NONFINITE. */
 int adg_run(adg_ctx* ctx, double* d_u, int64_t n_steps, uint32_t flags);
 
 /* Discrete adjoint of the recorded run (delay schedule held fixed) for

@@ -34,7 +34,7 @@ ADG_RUN_RECORD = 2
 ADG_RUN_CHECK_FINITE = 4
 
 SYMBOLS = [
-    "adg_abi_version", "adg_last_error", "adg_nodes", "adg_state_layout", "adg_workspace_size",
+    "adg_abi_version", "adg_last_error", "adg_build_id", "adg_nodes", "adg_state_layout", "adg_workspace_size",
     "adg_init", "adg_reset", "adg_step_count", "adg_step", "adg_run", "adg_adjoint",
     "adg_error_stats", "adg_ensemble_stats", "adg_delay_schedule", "adg_destroy",
 ]
@@ -72,7 +72,10 @@ def library_path() -> str:
 
 
 def lib() -> C.CDLL:
-    """Load libadg.so (built in-tree by paper_2404_03399_amd.build)."""
+    """Load libadg.so (built in-tree by paper_2404_03399_amd.build).  Raises
+    ImportError if it is missing, or if it was built from sources other than
+    the ones in this tree (its adg_build_id() differs from the hash of
+    csrc/ and include/): a stale binary is never tested or timed."""
     global _LIB
     if _LIB is None:
         path = library_path()
@@ -84,6 +87,7 @@ def lib() -> C.CDLL:
         sig = {
             "adg_abi_version": ([], C.c_int),
             "adg_last_error": ([], C.c_char_p),
+            "adg_build_id": ([], C.c_char_p),
             "adg_nodes": ([I32, P(D)], C.c_int),
             "adg_state_layout": ([P(adg_problem), I32, P(I64), P(I64), P(I64)], C.c_int),
             "adg_workspace_size": ([P(adg_problem), I32, P(adg_options), I64, P(I64)], C.c_int),
@@ -104,6 +108,10 @@ def lib() -> C.CDLL:
             f.restype = res
         if L.adg_abi_version() != ADG_ABI_VERSION:
             raise ImportError("libadg ABI version mismatch")
+        built, here = L.adg_build_id().decode(), _build.source_hash()
+        if built != here:
+            raise ImportError(f"{path} was built from other sources (build id {built}, sources {here}): "
+                              f"rebuild with python -m paper_2404_03399_amd.build")
         _LIB = L
     return _LIB
 

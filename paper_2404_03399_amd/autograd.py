@@ -33,7 +33,7 @@ class ADGFunction(torch.autograd.Function):
     @staticmethod
     def backward(ctx, grad_out):
         want_speed = ctx.speed_is_tensor and ctx.needs_input_grad[1]
-        g, gs = ctx.solver.adjoint(grad_out, want_speed=want_speed)
+        g, gs = ctx.solver.adjoint(grad_out.contiguous(), want_speed=want_speed)
         gspeed = None
         if want_speed:
             gspeed = torch.tensor(gs[0], dtype=torch.float64, device=ctx.speed_device)

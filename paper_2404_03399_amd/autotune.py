@@ -20,6 +20,7 @@ from __future__ import annotations
 import json
 import math
 import os
+import statistics
 from typing import List, Tuple
 
 CANDIDATES = (1, 2, 4)
@@ -30,14 +31,27 @@ def cache_path() -> str:
     return os.environ.get("ADG_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "adg_tune.json"))
 
 
+def kernel_source_hash() -> str:
+    """Hash of the kernel and library sources: a cached choice made on other
+    kernels is not reused."""
+    import hashlib
+    from . import build
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(build.CSRC)):
+        h.update(name.encode())
+        with open(os.path.join(build.CSRC, name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def _key(workloads, device_name: str) -> str:
     degrees = sorted({w.degree for w in workloads})
     total = sum(w.n_elem for w in workloads)
     bucket = int(round(math.log2(max(total, 1))))
     pes = min((w.pe_size for w in workloads if w.scheme != "dg" and w.n_elem // w.pe_size > 1), default=0)
     w0 = workloads[0]
-    return "|".join(str(x) for x in (device_name, w0.rk, w0.equation, w0.flux, w0.scheme, degrees, bucket,
-                                     len(workloads) > 1, min(pes, 4)))
+    return "|".join(str(x) for x in (device_name, kernel_source_hash(), w0.rk, w0.equation, w0.flux, w0.scheme,
+                                     degrees, bucket, len(workloads) > 1, min(pes, 4)))
 
 
 def admissible(workloads) -> List[int]:
@@ -53,8 +67,12 @@ def configs(workloads) -> List[Tuple[int, int]]:
     return [(r, k) for r in admissible(workloads) for k in STEPS_PER_LAUNCH]
 
 
-def tune(workloads, steps: int = 24, use_cache: bool = True, verbose: bool = False) -> Tuple[int, int]:
-    """(elements per lane, steps per launch) with the shortest time per step."""
+def tune(workloads, steps: int = 32, use_cache: bool = True, verbose: bool = False,
+         reps: int = 3) -> Tuple[int, int]:
+    """(elements per lane, steps per launch) with the shortest time per step:
+    for each pair the step graph is captured first (outside the timing), then
+    `reps` runs of `steps` graph-replayed steps are timed with HIP events and
+    the median is kept."""
     import torch
     from .solver import Solver
 
@@ -72,19 +90,25 @@ def tune(workloads, steps: int = 24, use_cache: bool = True, verbose: bool = Fal
             cache = {}
         if key in cache and "fused_steps" in cache[key]:
             return int(cache[key]["lane_elems"]), int(cache[key]["fused_steps"])
+    steps = max(16, steps - steps % 16)  # whole graph replays only
     timings = {}
     for r, k in configs(workloads):
         s = Solver(workloads, lane_elems=r, fused_steps=k)
         u = s.initial_state()
-        s.run(u, 4, graph=False)
-        torch.cuda.synchronize()
-        ev0 = torch.cuda.Event(enable_timing=True)
-        ev1 = torch.cuda.Event(enable_timing=True)
-        ev0.record()
-        s.run(u, steps, graph=True)
-        ev1.record()
-        torch.cuda.synchronize()
-        timings[(r, k)] = ev0.elapsed_time(ev1) / steps
+        s.capture_graph(u)
+        s.run(u, 16, graph=True)  # warm-up replay
+        stream = s.stream if s.stream is not None else torch.cuda.current_stream()
+        times = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            ev0 = torch.cuda.Event(enable_timing=True)
+            ev1 = torch.cuda.Event(enable_timing=True)
+            ev0.record(stream)
+            s.run(u, steps, graph=True)
+            ev1.record(stream)
+            torch.cuda.synchronize()
+            times.append(ev0.elapsed_time(ev1) / steps)
+        timings[(r, k)] = statistics.median(times)
         s.close()
     best = min(timings, key=timings.get)
     if verbose:

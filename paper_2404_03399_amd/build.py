@@ -55,6 +55,22 @@ def _run(cmd, verbose):
         print(res.stderr, file=sys.stderr)
 
 
+def source_hash() -> str:
+    """Hash of the library's sources (every file under csrc/ and include/),
+    compiled into the library as adg_build_id(); the binding compares the two
+    and refuses a library built from other sources."""
+    import hashlib
+    h = hashlib.sha256()
+    for d in (CSRC, INCLUDE):
+        for name in sorted(os.listdir(d)):
+            path = os.path.join(d, name)
+            if os.path.isfile(path):
+                h.update(name.encode() + b"\0")
+                with open(path, "rb") as fh:
+                    h.update(fh.read())
+    return h.hexdigest()[:24]
+
+
 def build(verbose: bool = False, jobs: int = 0, extra=(), libdir: str = LIBDIR) -> str:
     """Compile every unit to an object (in parallel), then link libdir/libadg.so
     (extra: more compiler options for every unit)."""
@@ -64,9 +80,12 @@ def build(verbose: bool = False, jobs: int = 0, extra=(), libdir: str = LIBDIR) 
     os.makedirs(objdir, exist_ok=True)
     cc = hipcc()
     extra = list(extra)
+    ident = [f'-DADG_SOURCE_HASH="{source_hash()}"']
     objs, cmds = [], []
     for src, defs in UNITS:
         tag = "".join(d.split("=")[-1] for d in defs if d.startswith("-D"))
+        if src == "adg_api.hip":
+            defs = defs + ident
         obj = os.path.join(objdir, os.path.splitext(src)[0] + (f"_{tag}" if tag else "") + ".o")
         objs.append(obj)
         cmds.append([cc] + flags() + extra + defs + ["-c", os.path.join(CSRC, src), "-o", obj])

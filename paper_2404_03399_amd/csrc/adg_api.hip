@@ -20,6 +20,9 @@ int fail(int code, const std::string& msg) {
   return code;
 }
 
+// State vectors are read and written as 16-byte pairs of nodal values.
+bool state_aligned(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
 #define ADG_HIP(expr)                                                                         \
   do {                                                                                        \
     hipError_t e_ = (expr);                                                                   \
@@ -529,6 +532,11 @@ int adg_abi_version(void) { return ADG_ABI_VERSION; }
 
 const char* adg_last_error(void) { return g_err.c_str(); }
 
+#ifndef ADG_SOURCE_HASH
+#error "compile with -DADG_SOURCE_HASH=\"<hash of csrc/ and include/>\" (paper_2404_03399_amd/build.py does)"
+#endif
+const char* adg_build_id(void) { return ADG_SOURCE_HASH; }
+
 int adg_nodes(int32_t degree, double* xi) {
   if (degree < 1 || degree > 4 || !xi) return fail(ADG_E_INVALID, "adg_nodes: degree must be 1..4");
   long double x[kMaxNp];
@@ -758,6 +766,7 @@ int adg_step_count(const adg_ctx* c, int64_t* steps) {
 
 int adg_run(adg_ctx* c, double* d_u, int64_t n_steps, uint32_t flags) {
   if (!c || !d_u) return fail(ADG_E_INVALID, "null argument");
+  if (!state_aligned(d_u)) return fail(ADG_E_INVALID, "d_u must be 16-byte aligned");
   if (n_steps < 0) return fail(ADG_E_INVALID, "n_steps < 0");
   if (c->steps + n_steps >= ((int64_t)1 << 31)) return fail(ADG_E_INVALID, "step index would exceed 2^31 - 1");
   if (flags & ~(ADG_RUN_GRAPH | ADG_RUN_RECORD | ADG_RUN_CHECK_FINITE)) return fail(ADG_E_INVALID, "unknown flags");
@@ -809,11 +818,15 @@ int adg_run(adg_ctx* c, double* d_u, int64_t n_steps, uint32_t flags) {
     if (flags & ADG_RUN_CHECK_FINITE) return adg_run(c, d_u, 0, ADG_RUN_CHECK_FINITE);
     return ADG_OK;
   }
-  c->rec_steps = 0;  // any further step invalidates a recording
+  int rc;
+  if (n_steps == 0 && (flags & ADG_RUN_GRAPH) && (c->graph_u != d_u || !c->graph)) {
+    // capture only: the step graph for d_u, replayed by later runs
+    if ((rc = build_graph(c, d_u))) return rc;
+  }
+  if (n_steps > 0) c->rec_steps = 0;  // any further step invalidates a recording
   double* cur = d_u;
   double* other = c->kernel == ADG_KERNEL_FUSED ? c->state2() : nullptr;
   int64_t left = n_steps;
-  int rc;
   if ((flags & ADG_RUN_GRAPH) && left >= kGraphSteps) {
     if (c->graph_u != d_u || !c->graph) {
       if ((rc = build_graph(c, d_u))) return rc;
@@ -1022,6 +1035,8 @@ int adjoint_fused(adg_ctx* c, const double* d_cot_uT, double* d_grad_u0, double*
 
 int adg_adjoint(adg_ctx* c, const double* d_cot_uT, double* d_grad_u0, double* h_grad_speed) {
   if (!c || !d_cot_uT || !d_grad_u0) return fail(ADG_E_INVALID, "null argument");
+  if (!state_aligned(d_cot_uT) || !state_aligned(d_grad_u0))
+    return fail(ADG_E_INVALID, "d_cot_uT and d_grad_u0 must be 16-byte aligned");
   if (c->rec_steps <= 0) return fail(ADG_E_STATE, "adg_adjoint needs a run recorded with ADG_RUN_RECORD");
   return c->kernel == ADG_KERNEL_FUSED ? adjoint_fused(c, d_cot_uT, d_grad_u0, h_grad_speed)
                                        : adjoint_stage(c, d_cot_uT, d_grad_u0, h_grad_speed);
@@ -1029,6 +1044,7 @@ int adg_adjoint(adg_ctx* c, const double* d_cot_uT, double* d_grad_u0, double* h
 
 int adg_error_stats(adg_ctx* c, const double* d_u, const double* d_ref, double* h_out) {
   if (!c || !d_u || !d_ref || !h_out) return fail(ADG_E_INVALID, "null argument");
+  if (!state_aligned(d_u) || !state_aligned(d_ref)) return fail(ADG_E_INVALID, "d_u and d_ref must be 16-byte aligned");
   const int32_t n = (int32_t)c->probs.size();
   double* part = (double*)(c->ws + c->L.part);
   double* dout = (double*)(c->ws + c->L.stats_out);
@@ -1041,6 +1057,7 @@ int adg_error_stats(adg_ctx* c, const double* d_u, const double* d_ref, double* 
 int adg_ensemble_stats(adg_ctx* c, const double* d_u, const double* d_ref, const int32_t* h_group_of,
                        int32_t n_groups, double* h_out) {
   if (!c || !d_u || !d_ref || !h_group_of || !h_out) return fail(ADG_E_INVALID, "null argument");
+  if (!state_aligned(d_u) || !state_aligned(d_ref)) return fail(ADG_E_INVALID, "d_u and d_ref must be 16-byte aligned");
   const int32_t n = (int32_t)c->probs.size();
   if (n_groups < 1 || n_groups > n) return fail(ADG_E_INVALID, "n_groups must be in 1..n_probs");
   std::vector<int32_t> csr(2 * (size_t)n + 1, 0);  // [gstart (n_groups+1) | members (n)]

@@ -229,6 +229,12 @@ __global__ __launch_bounds__(kBlock) void k_ldg_q(const DevProblem* __restrict__
 }
 
 // ----------------------------------------------------------- statistics ---
+// Maximum that propagates NaN (fmax drops it): a blown-up realization must
+// report a non-finite max error, as a plain maximum over its values would.
+__device__ __forceinline__ double max_nan(double a, double b) {
+  return a != a ? a : (b != b ? b : fmax(a, b));
+}
+
 __global__ __launch_bounds__(kBlock) void k_stats_partial(const DevProblem* __restrict__ probs,
                                                           const WorkItem* __restrict__ work,
                                                           const double* __restrict__ u,
@@ -244,7 +250,7 @@ __global__ __launch_bounds__(kBlock) void k_stats_partial(const DevProblem* __re
       const int64_t i = P.u_off + j * P.ld + e;
       const double d = fabs(u[i] - ref[i]);
       sabs += d;
-      mabs = fmax(mabs, d);
+      mabs = max_nan(mabs, d);
       integ += P.wq[j] * u[i];
     }
   }
@@ -255,7 +261,7 @@ __global__ __launch_bounds__(kBlock) void k_stats_partial(const DevProblem* __re
   for (int w = kBlock / 2; w > 0; w >>= 1) {
     if ((int)threadIdx.x < w) {
       red[0][threadIdx.x] += red[0][threadIdx.x + w];
-      red[1][threadIdx.x] = fmax(red[1][threadIdx.x], red[1][threadIdx.x + w]);
+      red[1][threadIdx.x] = max_nan(red[1][threadIdx.x], red[1][threadIdx.x + w]);
       red[2][threadIdx.x] += red[2][threadIdx.x + w];
     }
     __syncthreads();
@@ -279,7 +285,7 @@ __global__ __launch_bounds__(kBlock) void k_stats_final(const DevProblem* __rest
   double s0 = 0.0, s1 = 0.0, s2 = 0.0;
   for (int32_t i = i0 + threadIdx.x; i < i1; i += kBlock) {
     s0 += part[3 * i];
-    s1 = fmax(s1, part[3 * i + 1]);
+    s1 = max_nan(s1, part[3 * i + 1]);
     s2 += part[3 * i + 2];
   }
   red[0][threadIdx.x] = s0;
@@ -289,7 +295,7 @@ __global__ __launch_bounds__(kBlock) void k_stats_final(const DevProblem* __rest
   for (int w = kBlock / 2; w > 0; w >>= 1) {
     if ((int)threadIdx.x < w) {
       red[0][threadIdx.x] += red[0][threadIdx.x + w];
-      red[1][threadIdx.x] = fmax(red[1][threadIdx.x], red[1][threadIdx.x + w]);
+      red[1][threadIdx.x] = max_nan(red[1][threadIdx.x], red[1][threadIdx.x + w]);
       red[2][threadIdx.x] += red[2][threadIdx.x + w];
     }
     __syncthreads();

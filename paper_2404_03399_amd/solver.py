@@ -81,9 +81,9 @@ class Solver:
             fused_steps = fused_steps or k
         self.opt.lane_elems = int(lane_elems)
         self.opt.fused_steps = int(fused_steps)
-        self.device = torch.device(device)
         self.ws_bytes = adg.adg_workspace_size(self.probs, self.opt, n_steps_record)
-        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=torch.device(device))
+        self.device = self.workspace.device  # with its index
         self.stream = stream
         self.ctx = adg.adg_init(self.probs, self.opt, n_steps_record, self.workspace.data_ptr(),
                                 self.ws_bytes, _stream_handle(stream))
@@ -98,6 +98,27 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+    def state_ptr(self, t: torch.Tensor, name: str = "u") -> int:
+        """Device address of a state vector, after checking that it has this
+        context's layout: float64, contiguous, on this context's device,
+        exactly adg_state_layout's total length and 16-byte aligned.  The
+        kernels index every node plane up to its padded leading dimension, so
+        anything else would be read or written out of bounds (ValueError)."""
+        if not torch.is_tensor(t):
+            raise TypeError(f"{name}: expected a torch.Tensor, got {type(t).__name__}")
+        if t.dtype != torch.float64:
+            raise ValueError(f"{name}: dtype must be torch.float64, got {t.dtype}")
+        if t.device != self.device:
+            raise ValueError(f"{name}: must be on {self.device}, got {t.device}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name}: must be contiguous")
+        if t.numel() != self.total:
+            raise ValueError(f"{name}: must hold {self.total} doubles (adg_state_layout), got {t.numel()}")
+        ptr = t.data_ptr()
+        if ptr % 16:
+            raise ValueError(f"{name}: data must be 16-byte aligned")
+        return ptr
 
     # ---- state packing ---------------------------------------------------
     def empty_state(self) -> torch.Tensor:
@@ -151,32 +172,39 @@ class Solver:
         adg.adg_reset(self.ctx)
 
     def step(self, u: torch.Tensor):
-        adg.adg_step(self.ctx, u.data_ptr())
+        adg.adg_step(self.ctx, self.state_ptr(u))
 
     def run(self, u: torch.Tensor, n_steps: int, graph: bool = True, record: bool = False,
             check_finite: bool = False):
         flags = (adg.ADG_RUN_GRAPH if graph else 0) | (adg.ADG_RUN_RECORD if record else 0) | \
                 (adg.ADG_RUN_CHECK_FINITE if check_finite else 0)
-        adg.adg_run(self.ctx, u.data_ptr(), n_steps, flags)
+        adg.adg_run(self.ctx, self.state_ptr(u), n_steps, flags)
+
+    def capture_graph(self, u: torch.Tensor):
+        """Capture the step graph for buffer u without stepping (adg_run with
+        zero steps and ADG_RUN_GRAPH), so that a later graph run replays it
+        without the capture and instantiation cost."""
+        adg.adg_run(self.ctx, self.state_ptr(u), 0, adg.ADG_RUN_GRAPH)
 
     def adjoint(self, cot: torch.Tensor, want_speed: bool = True):
         """dJ/du0 (device, state layout) and dJ/da per problem (host list, or
         None if want_speed is False) for the last recorded run, given
         cot = dJ/du(T)."""
-        cot = cot.contiguous()
+        cot_ptr = self.state_ptr(cot, "cot")
         grad = torch.empty_like(cot)
-        gs = adg.adg_adjoint(self.ctx, cot.data_ptr(), grad.data_ptr(), len(self.probs), want_speed)
+        gs = adg.adg_adjoint(self.ctx, cot_ptr, self.state_ptr(grad, "grad"), len(self.probs), want_speed)
         return grad, gs
 
     def steps_taken(self) -> int:
         return adg.adg_step_count(self.ctx)
 
     def error_stats(self, u: torch.Tensor, ref: torch.Tensor):
-        return adg.adg_error_stats(self.ctx, u.data_ptr(), ref.data_ptr(), len(self.probs))
+        return adg.adg_error_stats(self.ctx, self.state_ptr(u), self.state_ptr(ref, "ref"), len(self.probs))
 
     def ensemble_stats(self, u: torch.Tensor, ref: torch.Tensor, group_of, n_groups: int):
         """Per group: (mean <E>, var <E>, mean max-err, var max-err)."""
-        return adg.adg_ensemble_stats(self.ctx, u.data_ptr(), ref.data_ptr(), list(group_of), n_groups)
+        return adg.adg_ensemble_stats(self.ctx, self.state_ptr(u), self.state_ptr(ref, "ref"), list(group_of),
+                                      n_groups)
 
     def exact_advection_state(self, t: float) -> torch.Tensor:
         """Nodal values of the exact linear-advection solution u0(x - a t)."""

@@ -1,8 +1,12 @@
 """GPU parity: the HIP stepper (through the C ABI) against the FP64 oracle.
 
-Bar (stated by the method's target): relative L2 difference <= 1e-12 over the
-whole state, FP64 on both sides.  Sizes span several workgroup tiles plus a
-ragged tail; the full-size cases use the launch configuration of bench.py
+Bars (parity_bars.py): relative L2 difference <= 1e-12 over the whole state
+(stated by the method's target), and max |GPU - oracle| over the elements on
+either side of each PE face <= 1e-12 of max |oracle| (an error confined to
+PE-face elements is diluted in the whole-state L2); FP64 on both sides.
+Ill-conditioned cases (every face at the largest delay) take both bars from
+the oracle's own rounding response.  Sizes span several workgroup tiles plus
+a ragged tail; the full-size cases use the launch configuration of bench.py
 (fused kernel, hipGraph replay)."""
 import sys
 from dataclasses import replace
@@ -12,10 +16,9 @@ import pytest
 
 from paper_2404_03399_amd import workloads as W
 from oracle import stats, stepper
+from parity_bars import TOL, derived_bars, pe_max_rel
 
 pytestmark = pytest.mark.gpu
-
-TOL = 1e-12
 
 
 def _say(msg):
@@ -47,14 +50,19 @@ def oracle_run(w, u0, n_steps):
     return stepper.Stepper(w).run(u0, n_steps)
 
 
-def _check(torch, w, n_steps, kernel="fused", graph=True, tol=TOL, lane_elems=0):
+def _check(torch, w, n_steps, kernel="fused", graph=True, lane_elems=0, derive=False):
+    """GPU against oracle in both norms; derive: bars from the oracle's own
+    rounding response (ill-conditioned cases) instead of 1e-12."""
     _say(f"{w.name} p={w.degree} rk={w.rk} flux={w.flux} N={w.n_elem} pe={w.pe_size} "
          f"steps={n_steps} kernel={kernel} graph={graph} lane_elems={lane_elems}")
     u0 = stepper.initial_state(w)
     ref = oracle_run(w, u0, n_steps)
+    tol, tol_pe = derived_bars(w, u0, n_steps, ref) if derive else (TOL, TOL)
     got = gpu_run(torch, w, u0, n_steps, kernel, graph, lane_elems)
     err = stats.rel_l2(got, ref)
-    assert err <= tol, (w.name, err)
+    assert err <= tol, (w.name, err, tol)
+    err_pe = pe_max_rel(got, ref, w)
+    assert err_pe <= tol_pe, (w.name, "PE-face elements", err_pe, tol_pe)
     return got, ref
 
 
@@ -503,18 +511,18 @@ def test_every_launch_shape_bitwise(torch_cuda, ne, pe, p, rk, phys):
     assert stats.rel_l2(outs[0], oracle_run(w, u0, n)) <= TOL
 
 
-@pytest.mark.parametrize("p,rk,sig,probs,tol", [(1, "rk4", 0.05, ("0", "0", "0", "1"), TOL),
-                                                (2, "ssprk3", 0.01, ("0", "0", "1"), TOL),
-                                                (3, "rk4", 0.005, ("0", "0", "0", "1"), 1e-9)])
-def test_worst_case_delays(torch_cuda, p, rk, sig, probs, tol):
+@pytest.mark.parametrize("p,rk,sig,probs", [(1, "rk4", 0.05, ("0", "0", "0", "1")),
+                                            (2, "ssprk3", 0.01, ("0", "0", "1")),
+                                            (3, "rk4", 0.005, ("0", "0", "0", "1"))])
+def test_worst_case_delays(torch_cuda, p, rk, sig, probs):
     """Every face at the largest delay L-1 at every step and stage (after the
     start-up clamp): the deepest ring levels and the largest AT weights, on
     both kernel families, against the oracle.  With q = 4 at delay 3 the AT
     weights are (20, -45, 36, -10): each combination multiplies rounding
-    differences by up to 111, and over 60 steps of every face at that delay
-    they reach 1e-10 relative; the bar 1e-9 stays two orders below the
-    change from taking the weights of q = 3 or the level of delay 2 instead
-    (2.3e-7 here, in the oracle)."""
+    differences by up to 111, so the bars in both norms are 30 times the
+    oracle's own response to a rounding-level perturbation of u0 where that
+    exceeds 1e-12 (parity_bars.derived_bars); taking the weights of q = 3 or
+    the level of delay 2 instead moves the result by 2.3e-7 (in the oracle)."""
     ne = 200
     w = W.Workload(name=f"worst_{p}", degree=p, rk=rk, n_elem=ne, pe_size=20, probs=probs, seed=1,
                    per_stage=True, dt=sig * W.TWO_PI / ne, ic=W.PAPER_MULTISINE)
@@ -527,4 +535,33 @@ def test_worst_case_delays(torch_cuda, p, rk, sig, probs, tol):
         assert (k[n] == min(L - 1, max(0, n - q + 1))).all(), n
     _say(f"worst-case delays: p={p} {rk} L={len(probs)} N={ne} steps=60")
     for kernel in ("fused", "stage"):
-        _check(torch_cuda, w, 60, kernel, graph=True, tol=tol)
+        _check(torch_cuda, w, 60, kernel, graph=True, derive=True)
+
+
+def test_state_tensors_checked_before_the_library(torch_cuda):
+    """Malformed state tensors raise ValueError in the binding before any
+    library call: the step counter does not move and the valid state is
+    untouched."""
+    torch = torch_cuda
+    from paper_2404_03399_amd.solver import Solver
+    w = W.Workload(name="val", n_elem=100, pe_size=10, probs=W.DELAYS_C2, dt=1e-3, ic=W.SINE)
+    s = Solver(w)
+    assert s.total % 64 == 0 and s.total > 100 * 2
+    u = s.initial_state()
+    keep = u.clone()
+    bad = [u.float(), u[:-1], torch.zeros(s.total + 2, dtype=torch.float64, device=u.device)[1:-1],
+           torch.zeros(2 * s.total, dtype=torch.float64, device=u.device)[::2], u.cpu(),
+           torch.zeros(100, 2, dtype=torch.float64, device=u.device)]
+    for t in bad:
+        with pytest.raises(ValueError):
+            s.run(t, 3)
+        with pytest.raises(ValueError):
+            s.step(t)
+        with pytest.raises(ValueError):
+            s.error_stats(t, u)
+        with pytest.raises(ValueError):
+            s.ensemble_stats(u, t, [0], 1)
+    torch.cuda.synchronize()
+    assert s.steps_taken() == 0
+    assert torch.equal(u, keep)
+    s.close()

@@ -271,3 +271,47 @@ def test_random_descriptors_are_validated(L):
         if rc2 == 0:
             assert rc1 == 0 and out.value > 0 and tot.value > 0
     assert not accepted_invalid, accepted_invalid[:5]
+
+
+def test_state_tensor_validation_rejects_wrong_layouts():
+    """Solver.state_ptr, which every stepping, adjoint and statistics call
+    uses for its device pointers, refuses tensors the kernels would index out
+    of bounds: wrong dtype, device, length, non-contiguous or misaligned.
+    Driven here with CPU tensors through a stand-in for the context."""
+    import torch
+    from types import SimpleNamespace
+    from paper_2404_03399_amd.solver import Solver
+    fake = SimpleNamespace(device=torch.device("cpu"), total=128)
+    ok = torch.zeros(128, dtype=torch.float64)
+    assert Solver.state_ptr(fake, ok) == ok.data_ptr()
+    bad = {
+        "float32": torch.zeros(128, dtype=torch.float32),
+        "short": torch.zeros(127, dtype=torch.float64),
+        "long": torch.zeros(129, dtype=torch.float64),
+        "natural layout": torch.zeros(40, 3, dtype=torch.float64),
+        "strided": torch.zeros(256, dtype=torch.float64)[::2],
+        "misaligned": torch.zeros(129, dtype=torch.float64)[1:],
+    }
+    for name, t in bad.items():
+        with pytest.raises(ValueError):
+            Solver.state_ptr(fake, t, name)
+    with pytest.raises(ValueError):
+        Solver.state_ptr(SimpleNamespace(device=torch.device("meta"), total=128), ok)
+    with pytest.raises(TypeError):
+        Solver.state_ptr(fake, np.zeros(128))
+
+
+def test_library_build_id_matches_sources(L):
+    """The loaded library was compiled from the sources in this tree."""
+    from paper_2404_03399_amd import build
+    assert L.adg_build_id().decode() == build.source_hash()
+
+
+def test_stale_library_is_refused(monkeypatch):
+    """A library whose build id differs from the hash of csrc/ and include/
+    is refused on load (a stale binary is never tested or timed)."""
+    from paper_2404_03399_amd import build
+    monkeypatch.setattr(build, "source_hash", lambda: "not-these-sources")
+    monkeypatch.setattr(adg, "_LIB", None)
+    with pytest.raises(ImportError, match="other sources"):
+        adg.lib()
