@@ -50,6 +50,7 @@ def _float_table(rows, b):
 
 BUTCHER = {
     "lsrk3": _float_table(*butcher_from_2n(stp.LSRK3_A, stp.LSRK3_B)),
+    "lsrk4": _float_table(*butcher_from_2n(stp.LSRK4_A, stp.LSRK4_B)),
     "heun": ([[], [1.0]], [0.5, 0.5]),
     "ssprk3": ([[], [1.0], [0.25, 0.25]], [1.0 / 6.0, 1.0 / 6.0, 2.0 / 3.0]),
     "rk4": ([[], [0.5], [0.0, 0.5], [0.0, 0.0, 1.0]], [1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0]),

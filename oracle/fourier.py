@@ -46,12 +46,12 @@ def amplification(p: int, rk: str, flux: str, sigma: float, theta: float) -> np.
         u1 = eye + z
         u2 = 0.75 * eye + 0.25 * (u1 + z @ u1)
         return eye / 3.0 + (2.0 / 3.0) * (u2 + z @ u2)
-    if rk == "lsrk3":
+    if rk in ("lsrk3", "lsrk4"):
         from fractions import Fraction
-        from .stepper import LSRK3_A, LSRK3_B
+        from .stepper import LOW_STORAGE
         du = np.zeros_like(eye, dtype=complex)
         g = eye.astype(complex)
-        for a, b in zip(LSRK3_A, LSRK3_B):
+        for a, b in zip(*LOW_STORAGE[rk]):
             du = float(Fraction(a)) * du + z @ g
             g = g + float(Fraction(b)) * du
         return g

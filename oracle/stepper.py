@@ -31,8 +31,11 @@ Asynchronous PE-boundary flux (Secs. 3, 4.1, 5).  Readings:
   2b + 1).  Oracle-only negative control.
 
 Time integrators: Heun RK2 as printed in Sec. 4.2 (k_i include dt); classical
-RK4 and the Shu-Osher SSP-RK3 (textbook forms; the paper's own low-storage
-schemes are not printed).
+RK4 and the Shu-Osher SSP-RK3 (textbook forms).  The paper integrates with
+low-storage 2N schemes from the works it cites in Sec. 6.1 without printing
+which ones; two published members of that family are built in their 2N
+form: Williamson's three-stage third-order scheme and Carpenter & Kennedy's
+five-stage fourth-order scheme.
 """
 from __future__ import annotations
 
@@ -42,13 +45,26 @@ import numpy as np
 
 from . import basis, atflux, delays
 
-N_STAGES = {"heun": 2, "ssprk3": 3, "rk4": 4, "lsrk3": 3}
+N_STAGES = {"heun": 2, "ssprk3": 3, "rk4": 4, "lsrk3": 3, "lsrk4": 5}
 
 # Williamson's third-order 2N-storage scheme (J. Comput. Phys. 35, 1980), of
 # the low-storage family the paper integrates with (Sec. 6.1):
 #   dU_s = A_s dU_{s-1} + dt L(U_{s-1}),  U_s = U_{s-1} + B_s dU_s,  s = 1..3.
 LSRK3_A = ("0", "-5/9", "-153/128")
 LSRK3_B = ("1/3", "15/16", "8/15")
+
+# Carpenter & Kennedy's five-stage fourth-order 2N-storage scheme (NASA
+# TM-109112, 1994; the 2N family that Kennedy, Carpenter & Lewis 2000, cited
+# in Sec. 6.1, build on), in the same 2N form, s = 1..5.  LSRK4_C are the
+# published stage abscissae, used only to check the Butcher form.
+LSRK4_A = ("0", "-567301805773/1357537059087", "-2404267990393/2016746695238",
+           "-3550918686646/2091501179385", "-1275806237668/842570457699")
+LSRK4_B = ("1432997174477/9575080441755", "5161836677717/13612068292357", "1720146321549/2090206949498",
+           "3134564353537/4481467310338", "2277821191437/14882151754819")
+LSRK4_C = ("0", "1432997174477/9575080441755", "2526269341429/6820363962896", "2006345519317/3224310063776",
+           "2802321613138/2924317926251")
+
+LOW_STORAGE = {"lsrk3": (LSRK3_A, LSRK3_B), "lsrk4": (LSRK4_A, LSRK4_B)}
 
 _M64 = np.uint64(0xFFFFFFFFFFFFFFFF)
 
@@ -245,10 +261,10 @@ class Stepper:
             u1 = u + dt * L(u, n, 0)
             u2 = 0.75 * u + 0.25 * (u1 + dt * L(u1, n, 1))
             return u / 3.0 + (2.0 / 3.0) * (u2 + dt * L(u2, n, 2))
-        if rk == "lsrk3":
+        if rk in LOW_STORAGE:
             du = np.zeros_like(u)
             y = u
-            for s_, (a, b) in enumerate(zip(LSRK3_A, LSRK3_B)):
+            for s_, (a, b) in enumerate(zip(*LOW_STORAGE[rk])):
                 du = float(Fraction(a)) * du + dt * L(y, n, s_)
                 y = y + float(Fraction(b)) * du
             return y

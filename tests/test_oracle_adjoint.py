@@ -17,7 +17,7 @@ def _small(scheme="adg_at", rk="rk4", p=2, ne=12, pe=3, flux="upwind", per_stage
 
 
 @pytest.mark.parametrize("scheme", ["dg", "adg", "adg_at"])
-@pytest.mark.parametrize("rk", ["heun", "ssprk3", "rk4", "lsrk3"])
+@pytest.mark.parametrize("rk", ["heun", "ssprk3", "rk4", "lsrk3", "lsrk4"])
 def test_gradient_equals_dense_jacobian_transpose(scheme, rk):
     w = _small(scheme=scheme, rk=rk)
     n = 9

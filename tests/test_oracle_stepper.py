@@ -177,6 +177,99 @@ def test_williamson_lsrk3_converges_at_third_order():
     np.testing.assert_allclose(st.step(u, 0), ref, rtol=0, atol=1e-14)
 
 
+def _order_conditions(rows, b):
+    """The eight order conditions of a four-stage-order Runge-Kutta method,
+    each as (value, exact target), in exact rationals."""
+    from fractions import Fraction as Fr
+    S = len(b)
+    a = [list(r) + [Fr(0)] * (S - len(r)) for r in rows]
+    c = [sum(r, Fr(0)) for r in a]
+
+    def A(v):
+        return [sum(a[i][j] * v[j] for j in range(S)) for i in range(S)]
+
+    def dot(u, v):
+        return sum(x * y for x, y in zip(u, v))
+
+    c2 = [x * x for x in c]
+    return {"b": (sum(b), Fr(1)), "bc": (dot(b, c), Fr(1, 2)), "bc2": (dot(b, c2), Fr(1, 3)),
+            "bAc": (dot(b, A(c)), Fr(1, 6)), "bc3": (dot(b, [x ** 3 for x in c]), Fr(1, 4)),
+            "bcAc": (dot(b, [x * y for x, y in zip(c, A(c))]), Fr(1, 8)),
+            "bAc2": (dot(b, A(c2)), Fr(1, 12)), "bAAc": (dot(b, A(A(c))), Fr(1, 24)),
+            "bc4 (fifth order)": (dot(b, [x ** 4 for x in c]), Fr(1, 5))}, c
+
+
+def test_carpenter_kennedy_lsrk4_order_conditions():
+    """The published 2N coefficients (A, B), turned into Butcher form exactly,
+    meet all eight fourth-order conditions to the accuracy of their 13-digit
+    rationals (1e-24) and miss the fifth-order condition b.c^4 = 1/5 by
+    about 1e-4; their stage abscissae equal the published c.  A mistyped
+    digit in any coefficient breaks a condition at 1e-13 or more."""
+    from fractions import Fraction as Fr
+    from oracle import adjoint
+    rows, b = adjoint.butcher_from_2n(stepper.LSRK4_A, stepper.LSRK4_B)
+    assert len(b) == 5 and stepper.N_STAGES["lsrk4"] == 5
+    conds, c = _order_conditions(rows, b)
+    fifth = conds.pop("bc4 (fifth order)")
+    for name, (v, t) in conds.items():
+        assert abs(v - t) < Fr(1, 10 ** 24), (name, float(v - t))
+    assert abs(fifth[0] - fifth[1]) > Fr(1, 10 ** 5)
+    for ci, pub in zip(c, stepper.LSRK4_C):
+        assert abs(ci - Fr(pub)) < Fr(1, 10 ** 24)
+    # a one-digit change of one coefficient is caught
+    bad_a = list(stepper.LSRK4_A)
+    bad_a[2] = "-2404267990394/2016746695238"
+    rows2, b2 = adjoint.butcher_from_2n(bad_a, stepper.LSRK4_B)
+    conds2, _ = _order_conditions(rows2, b2)
+    conds2.pop("bc4 (fifth order)")
+    assert max(abs(v - t) for v, t in conds2.values()) > Fr(1, 10 ** 13)
+
+
+def test_lsrk4_stability_polynomial():
+    """One step of a linear problem multiplies by R(Z) = sum_{j<=4} Z^j/j! +
+    g5 Z^5 with g5 = b^T A^4 1 (the only fifth-degree elementary weight of a
+    five-stage explicit method); g5 != 1/120 (the scheme is not fifth order)."""
+    from fractions import Fraction as Fr
+    from oracle import adjoint, fourier
+    rows, b = adjoint.butcher_from_2n(stepper.LSRK4_A, stepper.LSRK4_B)
+    g5 = b[4] * rows[4][3] * rows[3][2] * rows[2][1] * rows[1][0]
+    assert abs(g5 - Fr(1, 120)) > Fr(1, 10 ** 5)
+    for p, th in ((2, 0.7), (3, -1.9)):
+        z = fourier.stage_matrix(p, "upwind", 0.05, th)
+        g = np.eye(p + 1, dtype=complex)
+        term = np.eye(p + 1, dtype=complex)
+        for j in range(1, 5):
+            term = term @ z / j
+            g = g + term
+        g = g + float(g5) * np.linalg.matrix_power(z, 5)
+        np.testing.assert_allclose(fourier.amplification(p, "lsrk4", "upwind", 0.05, th), g, atol=1e-14)
+
+
+def test_lsrk4_converges_at_fourth_order():
+    """DG(3) and ADG(3)-AT4 with the five-stage fourth-order 2N scheme
+    converge at order 4 (Sec. 6.1 matches the integrator's order to the
+    spatial order); the 2N map equals its Butcher form."""
+    e = _series(3, "lsrk4", 0.01, "dg", [32, 64, 128])
+    slopes = np.log2(e[:-1, 0] / e[1:, 0])
+    assert np.all(slopes > 3.85), slopes
+    assert e[:, 2].max() < 1e-12
+    at = _series(3, "lsrk4", 0.01, "adg_at", [32, 64, 128])
+    slopes = np.log2(at[:-1, 0] / at[1:, 0])
+    assert np.all(slopes > 3.8), slopes
+    assert np.all(at[:, 0] < 1.5 * e[:, 0]), (at[:, 0], e[:, 0])
+    w = _wl(scheme="adg_at", rk="lsrk4", degree=3, n_elem=16, pe_size=4, dt=0.01, n_steps=1)
+    st = stepper.Stepper(w)
+    u = stepper.initial_state(w)
+    from oracle import adjoint
+    rows, b = adjoint.BUTCHER["lsrk4"]
+    ks = []
+    for i in range(5):
+        y = u + w.dt * sum((rows[i][j] * ks[j] for j in range(i)), np.zeros_like(u))
+        ks.append(st.operator(y, 0, i))
+    ref = u + w.dt * sum(bi * k for bi, k in zip(b, ks))
+    np.testing.assert_allclose(stepper.Stepper(w).step(u, 0), ref, rtol=0, atol=1e-14)
+
+
 def test_communication_avoiding_cycle():
     """Sec. 7's communication-avoiding runs (L = 3, delays 0, 1, 2 in the three
     steps of every five without communication): ADG(1)-AT2-RK2 keeps second
