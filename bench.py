@@ -58,7 +58,7 @@ def ring_bytes_per_step(w) -> float:
     if w.scheme == "dg" or w.n_pe <= 1:
         return 0.0
     q = (w.at_levels or w.degree + 1) if w.scheme == "adg_at" else 1
-    stages = {"rk4": 4, "ssprk3": 3, "heun": 2, "lsrk3": 3}[w.rk]
+    stages = {"rk4": 4, "ssprk3": 3, "heun": 2, "lsrk3": 3, "lsrk4": 5}[w.rk]
     return w.n_pe * stages * 8.0 * (1 + q)
 
 

@@ -75,11 +75,13 @@ enum adg_scheme { ADG_SCHEME_DG = 0, ADG_SCHEME_ADG = 1, ADG_SCHEME_ADG_AT = 2 }
 /* upwind / central: f^ = a (B+ u- + B- u+) (Sec. 2);  llf: local Lax-Friedrichs
  * 1/2 (f(u-) + f(u+)) - lambda/2 (u+ - u-), lambda = max(|u-|, |u+|) (Sec. 6.1). */
 enum adg_flux { ADG_FLUX_UPWIND = 0, ADG_FLUX_CENTRAL = 1, ADG_FLUX_LLF = 2 };
-/* Heun RK2 as in Sec. 4.2.1; Shu-Osher SSP-RK3; classical RK4; Williamson's
- * third-order 2N-storage scheme (1980), of the low-storage family of Sec. 6.1:
- * dU_s = A_s dU_{s-1} + dt L(U_{s-1}), U_s = U_{s-1} + B_s dU_s,
- * A = (0, -5/9, -153/128), B = (1/3, 15/16, 8/15). */
-enum adg_rk { ADG_RK2_HEUN = 0, ADG_SSPRK3 = 1, ADG_RK4 = 2, ADG_LSRK3 = 3 };
+/* Heun RK2 as in Sec. 4.2.1; Shu-Osher SSP-RK3; classical RK4; and two
+ * 2N-storage schemes of the low-storage family of Sec. 6.1,
+ * dU_s = A_s dU_{s-1} + dt L(U_{s-1}), U_s = U_{s-1} + B_s dU_s:
+ * Williamson's three-stage third-order scheme (1980),
+ * A = (0, -5/9, -153/128), B = (1/3, 15/16, 8/15), and Carpenter & Kennedy's
+ * five-stage fourth-order scheme (1994) with its published coefficients. */
+enum adg_rk { ADG_RK2_HEUN = 0, ADG_SSPRK3 = 1, ADG_RK4 = 2, ADG_LSRK3 = 3, ADG_LSRK4 = 4 };
 /* PER_STEP / PER_STAGE: random delays drawn per step or per (step, stage);
  * CAA: the deterministic communication-avoiding cycle of Sec. 7 (of every five
  * steps the first two synchronise, the next three do not): delays

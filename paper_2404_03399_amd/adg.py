@@ -25,8 +25,8 @@ ADG_E_UNSUPPORTED = -7
 EQUATION = {"advection": 0, "burgers": 1, "viscous_burgers": 2}
 SCHEME = {"dg": 0, "adg": 1, "adg_at": 2}
 FLUX = {"upwind": 0, "central": 1, "llf": 2}
-RK = {"heun": 0, "ssprk3": 1, "rk4": 2, "lsrk3": 3}
-RK_STAGES = {"heun": 2, "ssprk3": 3, "rk4": 4, "lsrk3": 3}
+RK = {"heun": 0, "ssprk3": 1, "rk4": 2, "lsrk3": 3, "lsrk4": 4}
+RK_STAGES = {"heun": 2, "ssprk3": 3, "rk4": 4, "lsrk3": 3, "lsrk4": 5}
 KERNEL = {"auto": 0, "stage": 1, "fused": 2}
 
 ADG_RUN_GRAPH = 1

@@ -24,6 +24,7 @@ LIB = os.path.join(LIBDIR, "libadg.so")
 PRELOAD = ["-mllvm", "-amdgpu-kernarg-preload-count=16"]
 UNITS = [("adg_fused.hip", ["-DADG_RK=0"] + PRELOAD), ("adg_fused.hip", ["-DADG_RK=1"] + PRELOAD),
          ("adg_fused.hip", ["-DADG_RK=2"] + PRELOAD), ("adg_fused.hip", ["-DADG_RK=3"] + PRELOAD),
+         ("adg_fused.hip", ["-DADG_RK=4"] + PRELOAD),
          ("adg_adjoint.hip", []), ("adg_kernels.hip", []), ("adg_api.hip", [])]
 ARCH = "gfx950"
 

@@ -515,7 +515,8 @@ static void adj_si(int si, const StepArgs& a, const AdjPtrs& p, int32_t n, hipSt
     case 0: adj_go<RK, PHYS, 0>(a, p, n, st); break;
     case 1: adj_go<RK, PHYS, 1>(a, p, n, st); break;
     case 2: if constexpr (rk_stages(RK) > 2) adj_go<RK, PHYS, 2>(a, p, n, st); break;
-    default: if constexpr (rk_stages(RK) > 3) adj_go<RK, PHYS, 3>(a, p, n, st); break;
+    case 3: if constexpr (rk_stages(RK) > 3) adj_go<RK, PHYS, 3>(a, p, n, st); break;
+    default: if constexpr (rk_stages(RK) > 4) adj_go<RK, PHYS, 4>(a, p, n, st); break;
   }
 }
 
@@ -536,6 +537,7 @@ hipError_t launch_adj_stage(int rk, int phys, int stage, const StepArgs& a, cons
     case RK_HEUN: adj_phys<RK_HEUN>(phys, stage, a, p, n, stream); break;
     case RK_SSP3: adj_phys<RK_SSP3>(phys, stage, a, p, n, stream); break;
     case RK_LS3: adj_phys<RK_LS3>(phys, stage, a, p, n, stream); break;
+    case RK_LS4: adj_phys<RK_LS4>(phys, stage, a, p, n, stream); break;
     default: adj_phys<RK_RK4>(phys, stage, a, p, n, stream); break;
   }
   return hipGetLastError();
@@ -614,6 +616,7 @@ hipError_t launch_adj_fused2(int rk, int phys, const AdjArgs& a, const double* l
     case RK_HEUN: adj_fused2_rk<RK_HEUN>(phys, a, lam, lamo, adjring, n, stream); break;
     case RK_SSP3: adj_fused2_rk<RK_SSP3>(phys, a, lam, lamo, adjring, n, stream); break;
     case RK_LS3: adj_fused2_rk<RK_LS3>(phys, a, lam, lamo, adjring, n, stream); break;
+    case RK_LS4: adj_fused2_rk<RK_LS4>(phys, a, lam, lamo, adjring, n, stream); break;
     default: adj_fused2_rk<RK_RK4>(phys, a, lam, lamo, adjring, n, stream); break;
   }
   return hipGetLastError();
@@ -625,6 +628,7 @@ hipError_t launch_adj_fused(int rk, int phys, const AdjArgs& a, const double* u,
     case RK_HEUN: adj_fused_rk<RK_HEUN>(phys, a, u, lam, lamo, ring, adjring, cpart, n, stream); break;
     case RK_SSP3: adj_fused_rk<RK_SSP3>(phys, a, u, lam, lamo, ring, adjring, cpart, n, stream); break;
     case RK_LS3: adj_fused_rk<RK_LS3>(phys, a, u, lam, lamo, ring, adjring, cpart, n, stream); break;
+    case RK_LS4: adj_fused_rk<RK_LS4>(phys, a, u, lam, lamo, ring, adjring, cpart, n, stream); break;
     default: adj_fused_rk<RK_RK4>(phys, a, u, lam, lamo, ring, adjring, cpart, n, stream); break;
   }
   return hipGetLastError();

@@ -182,7 +182,7 @@ int validate_one(const adg_problem& p, int idx) {
     return fail(ADG_E_INVALID, at + "viscosity is only for viscous Burgers");
   if (p.scheme > ADG_SCHEME_ADG_AT) return fail(ADG_E_INVALID, at + "unknown scheme");
   if (p.flux > ADG_FLUX_LLF) return fail(ADG_E_INVALID, at + "unknown flux");
-  if (p.rk > ADG_LSRK3) return fail(ADG_E_INVALID, at + "unknown rk");
+  if (p.rk > ADG_LSRK4) return fail(ADG_E_INVALID, at + "unknown rk");
   if (p.degree < 1 || p.degree > 4) return fail(ADG_E_INVALID, at + "degree must be in 1..4");
   if (p.equation == ADG_EQ_ADVECTION && p.flux == ADG_FLUX_LLF)
     return fail(ADG_E_INVALID, at + "llf flux is for Burgers");
@@ -322,7 +322,7 @@ Layout make_layout(const adg_problem* probs, int32_t n, const adg_options* opt, 
   L.ctr = take(8 * sizeof(int64_t));
   L.ring = take(8 * std::max<int64_t>(ring, 1));
   L.atsum = take(8 * S * std::max<int64_t>(at, 1));
-  L.atk = take(4 * std::max<int64_t>(at, 1));
+  L.atk = take((int64_t)sizeof(RecWord) * std::max<int64_t>(at, 1));
   const bool rec = n_rec > 0;
   L.state2 = kern == ADG_KERNEL_FUSED ? take(8 * tot) : -1;
   L.y0 = kern == ADG_KERNEL_STAGE ? take(8 * tot) : -1;
@@ -338,7 +338,7 @@ Layout make_layout(const adg_problem* probs, int32_t n, const adg_options* opt, 
   L.n_ckpt = rec ? (n_rec + L.ckpt_every - 1) / L.ckpt_every : 0;
   L.ckpt = L.useg = L.ybuf = L.lam = L.q = L.adjring = L.cpart = L.ckrec = L.work_a = L.work_a2 = -1;
   L.rec_atsum_bytes = 8 * S * std::max<int64_t>(at, 1);
-  L.rec_atk_bytes = 4 * std::max<int64_t>(at, 1);
+  L.rec_atk_bytes = (int64_t)sizeof(RecWord) * std::max<int64_t>(at, 1);
   L.rec_bytes = align_up(L.rec_atsum_bytes, kAlign) + align_up(L.rec_atk_bytes, kAlign);
   if (rec) {
     // stage kernels recompute a segment into seg slots; the fused adjoint
@@ -401,7 +401,7 @@ struct adg_ctx {
     a.ring = (double*)(ws + L.ring);
     a.ctr = (int64_t*)(ws + L.ctr);
     a.atsum = (double*)(ws + L.atsum);
-    a.atk = (int32_t*)(ws + L.atk);
+    a.atk = (RecWord*)(ws + L.atk);
     for (int i = 0; i <= kFusedRanges; ++i) a.group[i] = group[K - 1][i];
     for (int i = 0; i < kFusedRanges; ++i) a.grid[i] = grid[K - 1][i];
     for (int i = 0; i < kFusedRanges; ++i) a.single[i] = single[K - 1][i];
@@ -480,7 +480,7 @@ int reset_device(adg_ctx* c) {
   ADG_HIP(hipMemsetAsync(c->ws + c->L.ctr, 0, 8 * sizeof(int64_t), c->stream));
   ADG_HIP(hipMemsetAsync(c->ws + c->L.ring, 0, 8 * std::max<int64_t>(c->L.ring_doubles, 1), c->stream));
   ADG_HIP(hipMemsetAsync(c->ws + c->L.atsum, 0, 8 * c->S * std::max<int64_t>(c->L.at_entries, 1), c->stream));
-  ADG_HIP(hipMemsetAsync(c->ws + c->L.atk, 0, 4 * std::max<int64_t>(c->L.at_entries, 1), c->stream));
+  ADG_HIP(hipMemsetAsync(c->ws + c->L.atk, 0, sizeof(RecWord) * std::max<int64_t>(c->L.at_entries, 1), c->stream));
   c->steps = 0;
   c->rec_steps = 0;
   return ADG_OK;

@@ -17,10 +17,19 @@ constexpr int kRecSlots = 4;  // fused kernel PE-face record slots, indexed by s
 enum Phys : int {
   PHYS_ADV_UPWIND = 0, PHYS_ADV_CENTRAL = 1, PHYS_BURGERS_LLF = 2, PHYS_ADV_UPWIND_POS = 3, PHYS_BURGERS_LDG = 4
 };
-enum Rk : int { RK_HEUN = 0, RK_SSP3 = 1, RK_RK4 = 2, RK_LS3 = 3 };
+enum Rk : int { RK_HEUN = 0, RK_SSP3 = 1, RK_RK4 = 2, RK_LS3 = 3, RK_LS4 = 4 };
 enum Scheme : int { SCH_DG = 0, SCH_ADG = 1, SCH_AT = 2 };
 
-__host__ __device__ constexpr int rk_stages(int rk) { return rk == RK_HEUN ? 2 : (rk == RK_RK4 ? 4 : 3); }
+__host__ __device__ constexpr int rk_stages(int rk) {
+  return rk == RK_HEUN ? 2 : (rk == RK_RK4 ? 4 : (rk == RK_LS4 ? 5 : 3));
+}
+constexpr int kMaxStages = 5;
+
+// Packed delays of one PE face and step in the fused kernel's records: byte s
+// holds the clamped delay of stage s (delays < kMaxL <= 255), so that the
+// record jobs of different stages write different bytes of one word.
+using RecWord = uint64_t;
+static_assert(kMaxStages <= (int)sizeof(RecWord), "one byte per stage");
 
 // Division by a run-time invariant 0 < d < 2^31 for dividends n < 2^31 by
 // multiplication (Granlund & Montgomery, PLDI 1994): with l = ceil(log2 d),
@@ -59,7 +68,7 @@ struct DevProblem {
   int64_t ring_off;      // offset of the problem's delay ring (doubles)
   int64_t ring2_off;     // local DG: offset of the u-hat ring (same shape as the flux ring)
   int64_t at_off;        // offset of the problem's AT sums ([kRecSlots][P][S] doubles)
-  int64_t atk_off;       // offset of the problem's delays ([kRecSlots][P] words, byte s = stage s)
+  int64_t atk_off;       // offset of the problem's delays ([kRecSlots][P] RecWords, byte s = stage s)
   int32_t np;            // degree + 1
   int32_t q;             // AT levels (1 for ADG)
   int32_t n_delays;      // L

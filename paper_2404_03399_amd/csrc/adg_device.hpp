@@ -117,6 +117,27 @@ __device__ __forceinline__ void load_operators(const DevProblem& P, double (&Dm)
   }
 }
 
+// 2N-storage low-storage schemes of the family the paper integrates with
+// (Sec. 6.1): dU_s = A_s dU_{s-1} + dt L(U_{s-1}), U_s = U_{s-1} + B_s dU_s.
+// Williamson's three-stage third-order scheme (1980) and Carpenter & Kennedy's
+// five-stage fourth-order scheme (1994), their published coefficients; each
+// ratio of integers below 2^53 is rounded once, by the compiler's division.
+__host__ __device__ constexpr double ls_a(int rk, int s) {
+  if (rk == RK_LS3) return s == 1 ? -5.0 / 9.0 : (s == 2 ? -153.0 / 128.0 : 0.0);
+  return s == 1 ? -567301805773.0 / 1357537059087.0
+       : s == 2 ? -2404267990393.0 / 2016746695238.0
+       : s == 3 ? -3550918686646.0 / 2091501179385.0
+       : s == 4 ? -1275806237668.0 / 842570457699.0 : 0.0;
+}
+__host__ __device__ constexpr double ls_b(int rk, int s) {
+  if (rk == RK_LS3) return s == 0 ? 1.0 / 3.0 : (s == 1 ? 15.0 / 16.0 : 8.0 / 15.0);
+  return s == 0 ? 1432997174477.0 / 9575080441755.0
+       : s == 1 ? 5161836677717.0 / 13612068292357.0
+       : s == 2 ? 1720146321549.0 / 2090206949498.0
+       : s == 3 ? 3134564353537.0 / 4481467310338.0 : 2277821191437.0 / 14882151754819.0;
+}
+__host__ __device__ constexpr bool low_storage(int rk) { return rk == RK_LS3 || rk == RK_LS4; }
+
 // RK update after the stage-s operator value k (oracle's algebraic forms).
 // Every multiply-add is an explicit FMA and nothing else is contracted, so
 // the rounding does not depend on how the compiler schedules the caller
@@ -152,20 +173,16 @@ __device__ __forceinline__ void rk_update(int s, double dt, const double (&u0)[N
 #pragma unroll
       for (int j = 0; j < NP; ++j) y[j] = fma(2.0 / 3.0, fma(dt, k[j], y[j]), u0[j] / 3.0);
     }
-  } else if constexpr (RK == RK_LS3) {
-    // Williamson's 2N-storage form, ks holding dU:
-    // dU = A_s dU + dt k, y = y + B_s dU, A = (0, -5/9, -153/128), B = (1/3, 15/16, 8/15)
-    constexpr double A1 = -5.0 / 9.0, A2 = -153.0 / 128.0;
-    constexpr double B0 = 1.0 / 3.0, B1 = 15.0 / 16.0, B2 = 8.0 / 15.0;
+  } else if constexpr (low_storage(RK)) {
+    // 2N-storage form, ks holding dU: dU = A_s dU + dt k, y = y + B_s dU
+    const double Bs = ls_b(RK, s);
     if (s == 0) {
 #pragma unroll
-      for (int j = 0; j < NP; ++j) { ks[j] = dt * k[j]; y[j] = fma(B0, ks[j], y[j]); }
-    } else if (s == 1) {
-#pragma unroll
-      for (int j = 0; j < NP; ++j) { ks[j] = fma(A1, ks[j], dt * k[j]); y[j] = fma(B1, ks[j], y[j]); }
+      for (int j = 0; j < NP; ++j) { ks[j] = dt * k[j]; y[j] = fma(Bs, ks[j], y[j]); }
     } else {
+      const double As = ls_a(RK, s);
 #pragma unroll
-      for (int j = 0; j < NP; ++j) { ks[j] = fma(A2, ks[j], dt * k[j]); y[j] = fma(B2, ks[j], y[j]); }
+      for (int j = 0; j < NP; ++j) { ks[j] = fma(As, ks[j], dt * k[j]); y[j] = fma(Bs, ks[j], y[j]); }
     }
   } else {  // Heun
     if (s == 0) {
@@ -192,7 +209,6 @@ __device__ __forceinline__ int wrap_once(int x, int N) {
 }
 
 // ------------------------------------------------------ fused step kernel ---
-constexpr int kMaxStages = 4;
 
 // Workgroups are dispatched to the 8 XCDs round robin (workgroup i to XCD
 // i mod 8), and each XCD has its own L2.  Renumbering so that XCD x runs a
@@ -226,9 +242,9 @@ __device__ __forceinline__ double lane_from_right(double v) {
 // R <= PE size a lane's R left faces hold at most one PE face.  part / kdj:
 // per record job (a lane of an owner wave), the sum over the levels before
 // the launch and the delay, formed at the start of the launch.
-template <int K>
+template <int K, int S>
 struct WaveSmemK {
-  double at[K][kWavesPerBlock][kMaxStages][kWave];
+  double at[K][kWavesPerBlock][S][kWave];
   double part[kWavesPerBlock][kWave];
   int32_t kdj[kWavesPerBlock][kWave];
 };
@@ -252,7 +268,7 @@ __device__ __forceinline__ void folded_rhs(const DevProblem& P, const double (&y
 struct FusedPtrs {
   double* __restrict__ ring;
   double* __restrict__ atsum;
-  int32_t* __restrict__ atk;
+  RecWord* __restrict__ atk;
 };
 
 // Lane of the i-th set bit (from 0) of a wave-uniform mask, 0 if there is none.
@@ -313,12 +329,26 @@ __device__ __forceinline__ double at_old_levels(const DevProblem& P, const doubl
 
 
 // --------------------------------------------------------------- adjoint ---
-// Butcher form of the three integrators (the same maps as the forward
-// algebraic forms): Y_i = U + dt sum_{j<i} a_ij K_j, U' = U + dt sum_i b_i K_i.
+// Butcher form of a 2N scheme: U_s = U + dt sum_{j<=s} beta_{s,j} K_j with
+// beta_{s,j} = sum_{l=j..s} B_l prod_{m=j+1..l} A_m (K_j the operator at
+// U_{j-1}); stage s + 1 reads U_s, so a_{s+1,j} = beta_{s,j}, b_j =
+// beta_{S-1,j}.  Evaluated in double at compile time.
+__host__ __device__ constexpr double ls_beta(int rk, int s, int j) {
+  double acc = 0.0, prod = 1.0;
+  for (int l = j; l <= s; ++l) {
+    if (l > j) prod *= ls_a(rk, l);
+    acc += ls_b(rk, l) * prod;
+  }
+  return acc;
+}
+
+// Butcher form of the integrators (the same maps as the forward algebraic
+// forms): Y_i = U + dt sum_{j<i} a_ij K_j, U' = U + dt sum_i b_i K_i.
 template <int RK>
 __device__ constexpr double bt_a(int i, int j) {
   if constexpr (RK == RK_LS3)  // Williamson's scheme in Butcher form: a21 = 1/3, a31 = -3/16, a32 = 15/16
     return i == 1 ? (j == 0 ? 1.0 / 3.0 : 0.0) : (i == 2 && j < 2 ? (j == 0 ? -3.0 / 16.0 : 15.0 / 16.0) : 0.0);
+  if constexpr (RK == RK_LS4) return j < i ? ls_beta(RK, i - 1, j) : 0.0;
   if constexpr (RK == RK_RK4) return (j == i - 1) ? (i == 3 ? 1.0 : 0.5) : 0.0;
   else if constexpr (RK == RK_SSP3) return i == 1 ? (j == 0 ? 1.0 : 0.0) : (i == 2 && j < 2 ? 0.25 : 0.0);
   else return (i == 1 && j == 0) ? 1.0 : 0.0;
@@ -326,6 +356,7 @@ __device__ constexpr double bt_a(int i, int j) {
 template <int RK>
 __device__ constexpr double bt_b(int i) {
   if constexpr (RK == RK_LS3) return i == 0 ? 1.0 / 6.0 : (i == 1 ? 3.0 / 10.0 : 8.0 / 15.0);
+  if constexpr (RK == RK_LS4) return ls_beta(RK, rk_stages(RK) - 1, i);
   if constexpr (RK == RK_RK4) return (i == 0 || i == 3) ? 1.0 / 6.0 : 1.0 / 3.0;
   else if constexpr (RK == RK_SSP3) return i == 2 ? 2.0 / 3.0 : 1.0 / 6.0;
   else return 0.5;

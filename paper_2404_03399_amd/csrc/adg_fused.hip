@@ -1,10 +1,10 @@
 // Fused step kernel: one wave64 per tile, all RK stages of one or two time
-// steps on chip.  Compiled once per integrator (-DADG_RK=0, 1, 2, 3) so that
-// the instantiations build in parallel.
+// steps on chip.  Compiled once per integrator (-DADG_RK=0 .. 4) so that the
+// instantiations build in parallel.
 #include "adg_device.hpp"
 
 #ifndef ADG_RK
-#error "compile once per integrator with -DADG_RK=0, 1, 2 or 3"
+#error "compile once per integrator with -DADG_RK=0, 1, 2, 3 or 4"
 #endif
 
 namespace adg {
@@ -37,7 +37,8 @@ namespace adg {
 template <int NP, int RK, int PHYS, int R, int K>
 __device__ __forceinline__ void wave_tile(const DevProblem& P, const WorkItem wi, const FusedPtrs& A, int64_t n,
                                           const double* __restrict__ uin, double* __restrict__ uout,
-                                          double* __restrict__ umid, WaveSmemK<K>& sm, int wv, int lane) {
+                                          double* __restrict__ umid, WaveSmemK<K, rk_stages(RK)>& sm, int wv,
+                                          int lane) {
 #pragma clang fp contract(off)  // explicit FMAs only: rounding independent of the launch shape
   constexpr int S = rk_stages(RK);
   constexpr int HL = fused_halo(RK, R, K);
@@ -85,7 +86,7 @@ __device__ __forceinline__ void wave_tile(const DevProblem& P, const WorkItem wi
   bool pe_right = false;  // the right face of element R-1 is a PE face
   bool any_pe = false;
   uint32_t b = 0;       // its boundary index
-  int32_t kp[K];        // delays of step n + kk, byte s = stage s
+  RecWord kp[K];        // delays of step n + kk, byte s = stage s
   int depth = 1, slot_n = 0;
 #pragma unroll
   for (int kk = 0; kk < K; ++kk) kp[kk] = 0;
@@ -153,7 +154,7 @@ __device__ __forceinline__ void wave_tile(const DevProblem& P, const WorkItem wi
         kp[1] = 0;
 #pragma unroll
         for (int s = 0; s < S; ++s) {
-          kp[1] |= pe_delay(P, 1, s, b) << (8 * s);
+          kp[1] |= (RecWord)pe_delay(P, 1, s, b) << (8 * s);
           sm.at[1][wv][s][lane] = 0.0;
         }
       }
@@ -231,7 +232,7 @@ __device__ __forceinline__ void wave_tile(const DevProblem& P, const WorkItem wi
         if (pe[r]) {
           const double raw = F[r];
           if (owned[r]) A.ring[P.ring_off + ((int64_t)b * S + s) * depth + slot_m] = raw;
-          const int kd = (kp[kk] >> (8 * s)) & 0xff;
+          const int kd = (int)((kp[kk] >> (8 * s)) & 0xff);
           if (kd) {
             double at = sm.at[kk][wv][s][lane];
             if constexpr (K == 2) {  // delay 1 at step n+1: level n, this lane's raw flux of step n, completes the sum
@@ -313,11 +314,11 @@ template <int NP, int RK, int PHYS, int R, int K>
 __global__ __launch_bounds__(kBlock) void k_fused_step(const DevProblem* __restrict__ probs,
                                                        const WorkItem* __restrict__ work,
                                                        const int64_t* __restrict__ ctr, double* __restrict__ ring,
-                                                       double* __restrict__ atsum, int32_t* __restrict__ atk,
+                                                       double* __restrict__ atsum, RecWord* __restrict__ atk,
                                                        int32_t w_begin, int32_t w_end, const double* __restrict__ uin,
                                                        double* __restrict__ uout, double* __restrict__ umid,
                                                        int32_t step_offset, int32_t single_prob) {
-  __shared__ WaveSmemK<K> sm;
+  __shared__ WaveSmemK<K, rk_stages(RK)> sm;
   const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
   const int lane = (int)(threadIdx.x % kWave);
   const int w = w_begin + xcd_block((int)blockIdx.x, (int)gridDim.x) * kWavesPerBlock + wv;

@@ -109,15 +109,15 @@ __device__ __forceinline__ void stage_elem(const DevProblem& P, int tile, const 
         Uo[i] = Uo[i] + (dt / 6.0) * (Ao[i] + k[j]);
       }
     }
-  } else if constexpr (RK == RK_LS3) {
-    // Williamson's 2N-storage scheme, A = dU: dU = A_s dU + dt k, next = y + B_s dU
-    constexpr double Acoef = SI == 1 ? -5.0 / 9.0 : -153.0 / 128.0;
-    constexpr double Bcoef = SI == 0 ? 1.0 / 3.0 : (SI == 1 ? 15.0 / 16.0 : 8.0 / 15.0);
+  } else if constexpr (low_storage(RK)) {
+    // 2N-storage scheme, A = dU: dU = A_s dU + dt k, next = y + B_s dU
+    constexpr double Acoef = ls_a(RK, SI);
+    constexpr double Bcoef = ls_b(RK, SI);
 #pragma unroll
     for (int j = 0; j < NP; ++j) {
       const int64_t i = j * ld + e;
       const double du = SI == 0 ? dt * k[j] : fma(Acoef, Ao[i], dt * k[j]);
-      if constexpr (SI < 2) {
+      if constexpr (SI < S - 1) {
         Ao[i] = du;
         Yo[i] = fma(Bcoef, du, y[j]);
       } else {
@@ -370,9 +370,13 @@ static void ldg_q_si(int si, const StepArgs& a, const double* yin, int32_t off, 
       if constexpr (rk_stages(RK) > 2)
         hipLaunchKernelGGL((k_ldg_q<RK, 2>), g, b, 0, st, a.probs, a.work, yin, a.qbuf, a.ring, a.ctr, off);
       break;
-    default:
+    case 3:
       if constexpr (rk_stages(RK) > 3)
         hipLaunchKernelGGL((k_ldg_q<RK, 3>), g, b, 0, st, a.probs, a.work, yin, a.qbuf, a.ring, a.ctr, off);
+      break;
+    default:
+      if constexpr (rk_stages(RK) > 4)
+        hipLaunchKernelGGL((k_ldg_q<RK, 4>), g, b, 0, st, a.probs, a.work, yin, a.qbuf, a.ring, a.ctr, off);
       break;
   }
 }
@@ -383,6 +387,7 @@ hipError_t launch_ldg_q(int rk, int stage, const StepArgs& a, const double* yin,
     case RK_HEUN: ldg_q_si<RK_HEUN>(stage, a, yin, step_offset, stream); break;
     case RK_SSP3: ldg_q_si<RK_SSP3>(stage, a, yin, step_offset, stream); break;
     case RK_LS3: ldg_q_si<RK_LS3>(stage, a, yin, step_offset, stream); break;
+    case RK_LS4: ldg_q_si<RK_LS4>(stage, a, yin, step_offset, stream); break;
     default: ldg_q_si<RK_RK4>(stage, a, yin, step_offset, stream); break;
   }
   return hipGetLastError();
@@ -395,7 +400,8 @@ static void stage_si(int si, const StepArgs& a, const double* yin, double* yout,
     case 0: stage_go<RK, PHYS, 0>(a, yin, yout, U, A, off, st); break;
     case 1: stage_go<RK, PHYS, 1>(a, yin, yout, U, A, off, st); break;
     case 2: if constexpr (rk_stages(RK) > 2) stage_go<RK, PHYS, 2>(a, yin, yout, U, A, off, st); break;
-    default: if constexpr (rk_stages(RK) > 3) stage_go<RK, PHYS, 3>(a, yin, yout, U, A, off, st); break;
+    case 3: if constexpr (rk_stages(RK) > 3) stage_go<RK, PHYS, 3>(a, yin, yout, U, A, off, st); break;
+    default: if constexpr (rk_stages(RK) > 4) stage_go<RK, PHYS, 4>(a, yin, yout, U, A, off, st); break;
   }
 }
 
@@ -416,6 +422,7 @@ hipError_t launch_fused_step(int rk, int phys, const StepArgs& a, const double* 
     case RK_HEUN: return launch_fused_rk<RK_HEUN>(phys, a, uin, uout, step_offset, stream);
     case RK_SSP3: return launch_fused_rk<RK_SSP3>(phys, a, uin, uout, step_offset, stream);
     case RK_LS3: return launch_fused_rk<RK_LS3>(phys, a, uin, uout, step_offset, stream);
+    case RK_LS4: return launch_fused_rk<RK_LS4>(phys, a, uin, uout, step_offset, stream);
     default: return launch_fused_rk<RK_RK4>(phys, a, uin, uout, step_offset, stream);
   }
 }
@@ -426,6 +433,7 @@ hipError_t launch_stage(int rk, int phys, int stage, const StepArgs& a, const do
     case RK_HEUN: stage_phys<RK_HEUN>(phys, stage, a, yin, yout, U, A, step_offset, stream); break;
     case RK_SSP3: stage_phys<RK_SSP3>(phys, stage, a, yin, yout, U, A, step_offset, stream); break;
     case RK_LS3: stage_phys<RK_LS3>(phys, stage, a, yin, yout, U, A, step_offset, stream); break;
+    case RK_LS4: stage_phys<RK_LS4>(phys, stage, a, yin, yout, U, A, step_offset, stream); break;
     default: stage_phys<RK_RK4>(phys, stage, a, yin, yout, U, A, step_offset, stream); break;
   }
   return hipGetLastError();

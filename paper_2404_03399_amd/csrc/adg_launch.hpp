@@ -12,7 +12,7 @@ struct StepArgs {
   double* ring;              // delay ring (fluxes), may be null when no PE faces
   int64_t* ctr;              // ctr[0] = steps completed by earlier batches, ctr[2] = non-finite flag
   double* atsum;             // fused kernel: AT sums of past levels, [kRecSlots][P][S] per problem
-  int32_t* atk;              // fused kernel: clamped delays, [kRecSlots][P] words per problem (byte s = stage s)
+  RecWord* atk;              // fused kernel: clamped delays, [kRecSlots][P] words per problem (byte s = stage s)
   int32_t group[9];          // fused kernel: work-item ranges per degree and form (below)
   int32_t grid[8];           // fused kernel: workgroups per range
   int32_t single[8];         // fused kernel: the only problem of a range, or -1

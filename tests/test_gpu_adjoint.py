@@ -48,6 +48,8 @@ CASES = [
     ("dg", "rk4", 4, "upwind", 70, 7),
     ("adg_at", "rk4", 3, "central", 300, 25),
     ("adg_at", "lsrk3", 2, "upwind", 90, 9),
+    ("adg_at", "lsrk4", 3, "upwind", 120, 12),
+    ("adg_at", "lsrk4", 2, "central", 96, 8),
     ("adg_at", "rk4", 1, "upwind", 96, 2),  # a PE face every other element: several job passes per wave
 ]
 
@@ -101,7 +103,7 @@ def test_two_step_reverse_matches_oracle(torch_cuda, scheme, rk, p, flux, ne, pe
 
 @pytest.mark.parametrize("kernel", ["fused", "stage"])
 @pytest.mark.parametrize("rk,p,per_stage", [("ssprk3", 2, True), ("ssprk3", 2, False), ("rk4", 3, True),
-                                            ("heun", 1, False), ("lsrk3", 2, True)])
+                                            ("heun", 1, False), ("lsrk3", 2, True), ("lsrk4", 2, True)])
 def test_burgers_adjoint_matches_oracle(torch_cuda, kernel, rk, p, per_stage):
     # N = 128 spans several fused-adjoint tiles (64 - 2(2S - 1) elements each)
     w = replace(W.c3_burgers(n_elem=128, n_steps=0, sigma=0.02), pe_size=16, per_stage=per_stage, rk=rk,

@@ -38,7 +38,8 @@ def _w(p, rk, scheme, q, per_stage, ne=300, pe=20, nu=0.1, seed=3):
 
 
 CASES = [(2, "heun", "adg_at", 2, False), (2, "heun", "dg", 0, False), (1, "rk4", "adg_at", 0, True),
-         (3, "ssprk3", "adg", 0, True), (2, "lsrk3", "adg_at", 3, False), (4, "rk4", "adg_at", 2, True)]
+         (3, "ssprk3", "adg", 0, True), (2, "lsrk3", "adg_at", 3, False), (4, "rk4", "adg_at", 2, True),
+         (3, "lsrk4", "adg_at", 2, True)]
 
 
 @pytest.mark.parametrize("kernel", ["fused", "stage"])
@@ -122,7 +123,8 @@ def test_ldg_fused_equals_stage(torch_cuda, p, rk, scheme, q, per_stage):
 
 @pytest.mark.parametrize("p,rk,scheme,q,per_stage,ne,pe", [
     (2, "heun", "adg_at", 2, False, 300, 20), (1, "rk4", "adg_at", 0, True, 130, 13),
-    (3, "ssprk3", "adg", 0, True, 97, 1), (2, "lsrk3", "adg_at", 3, False, 200, 8), (4, "heun", "dg", 0, False, 64, 16)])
+    (3, "ssprk3", "adg", 0, True, 97, 1), (2, "lsrk3", "adg_at", 3, False, 200, 8), (4, "heun", "dg", 0, False, 64, 16),
+    (2, "lsrk4", "adg_at", 2, True, 150, 15)])
 def test_ldg_two_steps_per_launch_bitwise(torch_cuda, p, rk, scheme, q, per_stage, ne, pe):
     """Two time steps per fused local DG launch (halo 2S; the second step's AT
     sums formed from the ring plus each lane's own level-n values) give

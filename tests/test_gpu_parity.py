@@ -121,7 +121,7 @@ def test_c1_adg_at_as_specified_until_growth(torch_cuda):
 # ---- operator / integrator / physics matrix on a ragged mesh ------------------
 MATRIX = []
 for p in (1, 2, 3, 4):
-    for rk in ("heun", "ssprk3", "rk4", "lsrk3"):
+    for rk in ("heun", "ssprk3", "rk4", "lsrk3", "lsrk4"):
         for phys in ("upwind", "central", "llf"):
             MATRIX.append((p, rk, phys))
 
@@ -176,6 +176,8 @@ TWO_STEP_CASES = [
     (7, 1, 2, "rk4", "upwind", "adg_at", True, 0, 1),
     (300, 300, 2, "rk4", "central", "adg_at", True, 0, 4),
     (1000, 40, 2, "rk4", "upwind", "dg", True, 0, 2),
+    (1000, 40, 3, "lsrk4", "upwind", "adg_at", True, 0, 2),
+    (333, 9, 2, "lsrk4", "central", "adg_at", False, 0, 1),
 ]
 
 
@@ -488,7 +490,8 @@ def test_autotuned_lane_elems(torch_cuda, tmp_path, monkeypatch):
 
 @pytest.mark.parametrize("ne,pe,p,rk,phys", [(1000, 40, 3, "rk4", "upwind"), (1001, 77, 2, "ssprk3", "central"),
                                              (640, 8, 1, "heun", "llf"), (512, 16, 4, "lsrk3", "upwind"),
-                                             (1290, 129, 3, "rk4", "upwind")])
+                                             (1290, 129, 3, "rk4", "upwind"), (1000, 40, 3, "lsrk4", "upwind"),
+                                             (770, 7, 2, "lsrk4", "llf")])
 def test_every_launch_shape_bitwise(torch_cuda, ne, pe, p, rk, phys):
     """Elements per lane R in {1, 2, 4} and steps per launch K in {1, 2}:
     every multiply-add is an explicit FMA with contraction off, so all six

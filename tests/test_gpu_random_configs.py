@@ -230,6 +230,33 @@ def test_random_config_matches_oracle(torch_cuda, case):
         check_both(st, ref, w, tol, tol_pe)
 
 
+N_LS4 = 60
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("case", range(N_LS4))
+def test_random_lsrk4_config_matches_oracle(torch_cuda, case):
+    """Random draws run with the five-stage fourth-order 2N scheme (the other
+    draws keep their own integrators, so their seeds stay fixed): launch
+    shapes bitwise, both kernel families against the oracle."""
+    from dataclasses import replace
+    w, n, R, K, graph = draw(5000 + case)
+    w = replace(w, rk="lsrk4", name=f"ls4_{case}")
+    _say(f"random lsrk4 case {case}: {w.equation} {w.flux} {w.scheme} p={w.degree} N={w.n_elem} "
+         f"pe={w.pe_size} q={w.at_levels} L={w.n_delays} per_stage={w.per_stage} caa={w.caa} "
+         f"steps={n} R={R} K={K} graph={graph}")
+    u0 = stepper.initial_state(w)
+    ref = stepper.Stepper(w).run(u0, n)
+    got = _run(torch_cuda, w, u0, n, R, K, graph)
+    assert same(got, _run(torch_cuda, w, u0, n, 1, 1, False))
+    assert same(got, _run(torch_cuda, w, u0, n, R, 3 - K, not graph))
+    tol, tol_pe = bars(w, u0, n, ref)
+    if tol <= ORACLE_BAR:
+        check_both(got, ref, w, tol, tol_pe)
+        st = _run(torch_cuda, w, u0, n, 0, 0, graph, kernel="stage")
+        check_both(st, ref, w, tol, tol_pe)
+
+
 N_LARGE = 24
 
 

@@ -62,7 +62,8 @@ def test_layout(L):
 
 
 @pytest.mark.parametrize("rk,per_stage,scheme", [("rk4", True, "adg_at"), ("ssprk3", False, "adg_at"),
-                                                  ("heun", True, "adg"), ("rk4", True, "dg")])
+                                                  ("heun", True, "adg"), ("rk4", True, "dg"),
+                                                  ("lsrk4", True, "adg_at")])
 def test_delay_schedule_bit_exact_vs_oracle(L, rk, per_stage, scheme):
     w = replace(W.c2_advection_large(scheme, n_elem=4096), rk=rk, per_stage=per_stage, seed=12345)
     p = solver.to_problem(w)
@@ -179,7 +180,7 @@ def _documented_valid(p, opt, n_rec) -> bool:
     import math
     eq, sch, fl = p.equation, p.scheme, p.flux
     L_, q = p.n_delays, p.at_levels
-    ok = (p.abi_version == adg.ADG_ABI_VERSION and eq in (0, 1, 2) and sch in (0, 1, 2) and p.rk in (0, 1, 2, 3)
+    ok = (p.abi_version == adg.ADG_ABI_VERSION and eq in (0, 1, 2) and sch in (0, 1, 2) and p.rk in (0, 1, 2, 3, 4)
           and 1 <= p.degree <= 4 and 1 <= L_ <= 8 and p.delay_granularity in (0, 1, 2) and p.reserved == 0
           and p.n_elem >= 2 and p.pe_size >= 1 and p.n_elem % p.pe_size == 0
           and math.isfinite(p.length) and p.length > 0 and math.isfinite(p.dt) and p.dt > 0
