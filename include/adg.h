@@ -147,39 +147,61 @@ const char* adg_last_error(void);
  * caller can refuse a library built from other sources.  Static string. */
 const char* adg_build_id(void);
 
-/* GLL nodes of the reference element [-1, 1] for the given degree (1..4):
- * writes degree+1 doubles to host array xi.  Lets callers build nodal
- * initial data u[j*ld+e] = u0(x_left + e*dx + (xi[j]+1)*dx/2). */
+/* Nodes of the reference element [-1, 1] of the Lagrange basis (Sec. 2,
+ * reference element and basis; Gauss-Lobatto-Legendre points, end points
+ * included) for the given degree (1..4): writes degree+1 doubles to host
+ * array xi.  Lets callers build nodal initial data (the DOFs are nodal
+ * values, Sec. 2) u[j*ld+e] = u0(x_left + e*dx + (xi[j]+1)*dx/2).
+ * ADG_E_INVALID for another degree or a null xi. */
 int adg_nodes(int32_t degree, double* xi);
 
-/* Layout of the state vector for n_probs problems: per-problem offsets and
- * leading dimensions (host arrays of n_probs int64), and the total number of
- * doubles the caller must allocate. */
+/* Layout of the state vector for n_probs problems (the nodal DOFs u^e_j of
+ * every element, Sec. 2): per-problem offsets and leading dimensions (host
+ * arrays of n_probs int64, caller-owned), and the total number of doubles
+ * the caller must allocate on the device.  ADG_E_INVALID for an invalid
+ * problem (see adg_init). */
 int adg_state_layout(const adg_problem* probs, int32_t n_probs, int64_t* offsets, int64_t* lds,
                      int64_t* total_doubles);
 
 /* Device workspace bytes needed by adg_init for these problems, options and
  * an adjoint recording horizon of n_steps_record steps (0 if adg_adjoint
- * is not used). */
+ * is not used): descriptors, work lists, the per-PE-boundary rings of past
+ * face fluxes (depth L + q levels, Secs. 3, 5), the fused kernel's second
+ * state, and with a horizon the checkpoints.  Host-only; ADG_E_INVALID for
+ * invalid problems or options. */
 int adg_workspace_size(const adg_problem* probs, int32_t n_probs, const adg_options* opt,
                        int64_t n_steps_record, int64_t* bytes_out);
 
-/* Validate the problems, build the reference operators, AT table and tile
- * work list on the host, upload them into the caller's device workspace
- * (256-byte aligned, >= adg_workspace_size bytes) on hip_stream (a
- * hipStream_t, NULL = default stream) and reset the step counter and delay
- * history.  n_steps_record must match the value given to
- * adg_workspace_size.  On success *out owns a host-side context. */
+/* Set up the problem statement: u_t + f(u)_x = 0 on a periodic interval
+ * split into n_elem elements (Sec. 2, model problem and mesh), grouped into
+ * P = n_elem / pe_size processing elements (Sec. 2 parallel implementation,
+ * Sec. 3), with delays k < L drawn with probabilities p_k (Sec. 6.1) and a
+ * fixed time step.  Validates the problems, builds the reference operators
+ * (Sec. 2), the AT coefficient table (Sec. 5, Table 1) and the tile work
+ * lists on the host, uploads them into the caller's device workspace
+ * (256-byte aligned, >= adg_workspace_size bytes; caller-owned, untouched
+ * by the caller until adg_destroy) on hip_stream (a hipStream_t, NULL =
+ * default stream) and clears the step counter and delay history.
+ * n_steps_record must match the value given to adg_workspace_size.  On
+ * success *out owns a host-side context.  Errors: ADG_E_INVALID (see the
+ * field comments of adg_problem / adg_options), ADG_E_ABI,
+ * ADG_E_WORKSPACE (missing, small or misaligned workspace),
+ * ADG_E_UNSUPPORTED, ADG_E_HIP. */
 int adg_init(adg_ctx** out, const adg_problem* probs, int32_t n_probs, const adg_options* opt,
              int64_t n_steps_record, void* d_workspace, int64_t workspace_bytes, void* hip_stream);
 
-/* Step counter := 0, delay history := 0, recorded checkpoints dropped. */
+/* Back to t = 0 (Sec. 2 problem statement): step counter := 0, delay
+ * history (rings, Sec. 3) := 0, recorded checkpoints dropped.  Enqueued on
+ * the context's stream.  ADG_E_INVALID for a null context. */
 int adg_reset(adg_ctx* ctx);
 
-/* Number of steps taken since init/reset (host mirror of the device counter). */
+/* Number of steps taken since init/reset (host mirror of the device step
+ * counter that keys the delay draws of Sec. 6.1).  ADG_E_INVALID for null
+ * arguments. */
 int adg_step_count(const adg_ctx* ctx, int64_t* steps);
 
-/* One RK time step of every problem, in place on the device state d_u. */
+/* One RK time step of every problem, in place on the device state d_u:
+ * adg_run with n_steps = 1 and no flags (see there). */
 int adg_step(adg_ctx* ctx, double* d_u);
 
 /* n_steps RK time steps in place on d_u (device, state layout, 16-byte
@@ -195,7 +217,9 @@ int adg_step(adg_ctx* ctx, double* d_u);
  * ADG_E_STATE (recording misuse), ADG_E_HIP, ADG_E_NONFINITE. */
 int adg_run(adg_ctx* ctx, double* d_u, int64_t n_steps, uint32_t flags);
 
-/* Discrete adjoint of the recorded run (delay schedule held fixed) for
+/* Discrete adjoint (not in the paper: the target's differentiation
+ * addition) of the recorded run of the scheme of Secs. 2-5 (delay schedule
+ * held fixed) for
  * J(u(T)) with cotangent d_cot_uT = dJ/du(T) (device, state layout).
  * Writes dJ/du(0) to d_grad_u0 (device, state layout) and, for advection,
  * dJ/da per problem to the host array h_grad_speed (n_probs doubles; dt is
@@ -208,7 +232,8 @@ int adg_run(adg_ctx* ctx, double* d_u, int64_t n_steps, uint32_t flags);
  * h_grad_speed is given. */
 int adg_adjoint(adg_ctx* ctx, const double* d_cot_uT, double* d_grad_u0, double* h_grad_speed);
 
-/* Per-problem error statistics against a reference state (same layout):
+/* Per-problem error statistics against a reference state (same layout;
+ * Sec. 6.2 measures the error as the mean absolute pointwise error):
  * for each problem i writes h_out[3*i + 0] = mean |u - ref| over all nodal
  * values, h_out[3*i + 1] = max |u - ref|, h_out[3*i + 2] = (dx/2) sum_e w^T u^e
  * (the discrete integral).  Deterministic (fixed reduction order).
@@ -226,14 +251,18 @@ int adg_error_stats(adg_ctx* ctx, const double* d_u, const double* d_ref, double
 int adg_ensemble_stats(adg_ctx* ctx, const double* d_u, const double* d_ref, const int32_t* h_group_of,
                        int32_t n_groups, double* h_out);
 
-/* Host-side delay schedule of one problem (same integers the kernels use):
+/* Host-side delay schedule of one problem (Sec. 6.1 delay emulation, or the
+ * Sec. 7 communication-avoiding cycle; same integers the kernels use; the
+ * start-up clamp k <= n - q + 1 applied):
  * h_k[((n - step0) * S + s) * P + b] = clamped delay at step n, RK stage s,
  * boundary b, for n in [step0, step0 + n_steps).  S = number of RK stages,
- * P = number of PEs (P == 1: nothing written). */
+ * P = number of PEs (P == 1: nothing written); h_k is caller-owned host
+ * memory of n_steps * S * P int32.  ADG_E_INVALID for an invalid problem or
+ * arguments. */
 int adg_delay_schedule(const adg_problem* prob, int64_t step0, int64_t n_steps, int32_t* h_k);
 
 /* Release the context (host memory and hipGraphs).  The workspace may be
- * freed afterwards. */
+ * freed afterwards; a null context is accepted. */
 int adg_destroy(adg_ctx* ctx);
 
 #ifdef __cplusplus

@@ -477,10 +477,10 @@ int enqueue_batch(adg_ctx* c, double** cur, double** other, int32_t m, hipStream
 }
 
 int reset_device(adg_ctx* c) {
-  ADG_HIP(hipMemsetAsync(c->ws + c->L.ctr, 0, 8 * sizeof(int64_t), c->stream));
-  ADG_HIP(hipMemsetAsync(c->ws + c->L.ring, 0, 8 * std::max<int64_t>(c->L.ring_doubles, 1), c->stream));
-  ADG_HIP(hipMemsetAsync(c->ws + c->L.atsum, 0, 8 * c->S * std::max<int64_t>(c->L.at_entries, 1), c->stream));
-  ADG_HIP(hipMemsetAsync(c->ws + c->L.atk, 0, sizeof(RecWord) * std::max<int64_t>(c->L.at_entries, 1), c->stream));
+  ADG_HIP(launch_zero(c->ws + c->L.ctr, 8 * sizeof(int64_t), c->stream));
+  ADG_HIP(launch_zero(c->ws + c->L.ring, 8 * std::max<int64_t>(c->L.ring_doubles, 1), c->stream));
+  ADG_HIP(launch_zero(c->ws + c->L.atsum, 8 * c->S * std::max<int64_t>(c->L.at_entries, 1), c->stream));
+  ADG_HIP(launch_zero(c->ws + c->L.atk, sizeof(RecWord) * std::max<int64_t>(c->L.at_entries, 1), c->stream));
   c->steps = 0;
   c->rec_steps = 0;
   return ADG_OK;
@@ -849,7 +849,7 @@ int adg_run(adg_ctx* c, double* d_u, int64_t n_steps, uint32_t flags) {
   c->steps += n_steps;
   if (flags & ADG_RUN_CHECK_FINITE) {
     int64_t* ctr = (int64_t*)(c->ws + c->L.ctr);
-    ADG_HIP(hipMemsetAsync(ctr + 2, 0, sizeof(int64_t), c->stream));
+    ADG_HIP(launch_zero(ctr + 2, sizeof(int64_t), c->stream));
     ADG_HIP(launch_check_finite(c->stage_args(), d_u, c->stream));
     int64_t flag = 0;
     ADG_HIP(hipMemcpyAsync(&flag, ctr + 2, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
@@ -896,8 +896,8 @@ int adjoint_stage(adg_ctx* c, const double* d_cot_uT, double* d_grad_u0, double*
   const size_t bytes = 8 * (size_t)tot;
 
   ADG_HIP(hipMemcpyAsync(lam, d_cot_uT, bytes, hipMemcpyDeviceToDevice, st));
-  ADG_HIP(hipMemsetAsync(adjring, 0, 8 * std::max<int64_t>(L.ring_doubles, 1), st));
-  ADG_HIP(hipMemsetAsync(cpart, 0, 8 * (size_t)L.n_work_s, st));
+  ADG_HIP(launch_zero(adjring, 8 * std::max<int64_t>(L.ring_doubles, 1), st));
+  ADG_HIP(launch_zero(cpart, 8 * (size_t)L.n_work_s, st));
   ADG_HIP(launch_set_counter(ctr, 0, st));  // launches below pass absolute step indices
 
   for (int64_t k = L.n_ckpt - 1; k >= 0; --k) {
@@ -923,7 +923,7 @@ int adjoint_stage(adg_ctx* c, const double* d_cot_uT, double* d_grad_u0, double*
         const double* yin = s == 0 ? u : ybuf + tot * (s - 1);
         ADG_HIP(launch_stage(c->rk, c->phys, s, sa, yin, ybuf + tot * s, u, abuf, n, st));
       }
-      if (S > 1) ADG_HIP(hipMemsetAsync(Q, 0, bytes * (S - 1), st));
+      if (S > 1) ADG_HIP(launch_zero(Q, bytes * (S - 1), st));
       ADG_HIP(hipMemcpyAsync(lamu, lam, bytes, hipMemcpyDeviceToDevice, st));
       for (int s = S - 1; s >= 0; --s) {
         const double* Y = s == 0 ? u : ybuf + tot * (s - 1);
@@ -974,8 +974,8 @@ int adjoint_fused(adg_ctx* c, const double* d_cot_uT, double* d_grad_u0, double*
 
   if ((rc = c->save_records(L.n_ckpt, false))) return rc;
   ADG_HIP(hipMemcpyAsync(lam, d_cot_uT, bytes, hipMemcpyDeviceToDevice, st));
-  ADG_HIP(hipMemsetAsync(adjring, 0, 8 * std::max<int64_t>(L.ring_doubles, 1), st));
-  ADG_HIP(hipMemsetAsync(cpart, 0, 8 * (size_t)std::max<int32_t>(L.n_work_a, 1), st));
+  ADG_HIP(launch_zero(adjring, 8 * std::max<int64_t>(L.ring_doubles, 1), st));
+  ADG_HIP(launch_zero(cpart, 8 * (size_t)std::max<int32_t>(L.n_work_a, 1), st));
   ADG_HIP(launch_set_counter(ctr, 0, st));  // launches below pass absolute step indices
 
   // linear advection: the reverse sweep does not depend on the forward states;

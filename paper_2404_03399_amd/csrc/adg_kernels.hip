@@ -1,6 +1,8 @@
 // Per-stage kernels (one launch per RK stage, RK registers in HBM), the
 // statistics and counter kernels, and the dispatch of the fused step to its
 // per-integrator translation units.
+#include <algorithm>
+
 #include "adg_device.hpp"
 
 namespace adg {
@@ -436,6 +438,23 @@ hipError_t launch_stage(int rk, int phys, int stage, const StepArgs& a, const do
     case RK_LS4: stage_phys<RK_LS4>(phys, stage, a, yin, yout, U, A, step_offset, stream); break;
     default: stage_phys<RK_RK4>(phys, stage, a, yin, yout, U, A, step_offset, stream); break;
   }
+  return hipGetLastError();
+}
+
+// Zero fill of n 8-byte words (grid-stride): the library clears counters,
+// rings and accumulators with a kernel rather than a memset node, so that
+// a caller's graph capture of its calls records only kernels.
+__global__ __launch_bounds__(kBlock) void k_zero(uint64_t* __restrict__ p, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) p[i] = 0;
+}
+
+hipError_t launch_zero(void* p, int64_t bytes, hipStream_t stream) {
+  if (bytes <= 0) return hipSuccess;
+  if (((uintptr_t)p & 7u) != 0 || (bytes & 7) != 0) return hipErrorInvalidValue;
+  const int64_t n = bytes / 8;
+  const int64_t blocks = std::min<int64_t>((n + kBlock - 1) / kBlock, 2048);
+  hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(kBlock), 0, stream, (uint64_t*)p, n);
   return hipGetLastError();
 }
 

@@ -99,6 +99,9 @@ hipError_t launch_adj_fused2(int rk, int phys, const AdjArgs& a, const double* l
                              int32_t n, hipStream_t stream);
 __host__ __device__ constexpr int adj_tile_elems2(int rk) { return kWave - 4 * adj_halo(rk, false); }
 
+// Zero fill of `bytes` bytes at p (8-byte aligned, a multiple of 8).
+hipError_t launch_zero(void* p, int64_t bytes, hipStream_t stream);
+
 // ctr[0] := value (one lane).
 hipError_t launch_set_counter(int64_t* ctr, int64_t value, hipStream_t stream);
 
