@@ -14,6 +14,12 @@ initial data:
   (Fig. 10), fitted against the delay moment of the AT remainder,
   E[k (k+1) ... (k+q-1)] (E[k^2] + E[k] for q = 2; E[k^4] + 6E[k^3] +
   11E[k^2] + 6E[k] for q = 4).
+* `async_vs_pe`, `async_vs_delay`: the same two experiments through the
+  asynchrony term alone, <|u_AT - u_DG|> against the synchronous run of the
+  same mesh.  For AT4 at sigma = 0.01 the asynchrony error is 10^-4 of the
+  discretization error, so the excess of <E> over DG is lost to
+  cancellation, while the term itself (1e-11 to 1e-10 at N_E = 64) is far
+  above rounding.
 * `error_caa`: the deterministic communication-avoiding cycle of Sec. 7
   against synchronous DG over the mesh.
 * `viscous_burgers_convergence`: LDG(2)-RK2 and ALDG(2)-AT2-RK2 for the
@@ -68,6 +74,22 @@ def loglog_slope(xs: Sequence[float], ys: Sequence[float]) -> float:
     return sxy / sxx
 
 
+def loglog_slope_se(xs: Sequence[float], ys: Sequence[float], ses: Sequence[float]):
+    """Weighted least-squares slope of log y against log x, each point
+    weighted by the inverse variance of log y (standard error se of the mean
+    y, delta method: var(log y) = (se / y)^2), and the slope's standard
+    error."""
+    lx = [math.log(x) for x in xs]
+    ly = [math.log(y) for y in ys]
+    w = [(y / se) ** 2 for y, se in zip(ys, ses)]
+    sw = sum(w)
+    mx = sum(wi * a for wi, a in zip(w, lx)) / sw
+    my = sum(wi * b for wi, b in zip(w, ly)) / sw
+    sxx = sum(wi * (a - mx) ** 2 for wi, a in zip(w, lx))
+    sxy = sum(wi * (a - mx) * (b - my) for wi, a, b in zip(w, lx, ly))
+    return sxy / sxx, math.sqrt(1.0 / sxx)
+
+
 def linear_fit(xs: Sequence[float], ys: Sequence[float]) -> Dict[str, float]:
     """y = c0 + c1 x by least squares, with R^2."""
     n = len(xs)
@@ -99,6 +121,90 @@ def run_groups(workloads, group_of, n_groups: int, t_final: float):
         return s.ensemble_stats(u, ref, group_of, n_groups)
     finally:
         s.close()
+
+
+def synchronous_twin(w):
+    """The synchronous DG run of w's mesh, integrator and step (one PE)."""
+    return replace(w, scheme="dg", at_levels=0, probs=("1",), pe_size=w.n_elem, caa=False,
+                   name=f"{w.name}_dg")
+
+
+def run_groups_async(workloads, group_of, n_groups: int):
+    """Advance every problem in one batched context and return, per group,
+    the statistics of the asynchrony term <|u - u_DG|>: each asynchronous
+    run against the synchronous DG run of its own mesh (same integrator,
+    step and initial data).  Both share the spatial and temporal
+    discretization error, so the difference isolates the error that the
+    delayed PE-face fluxes add (the E_f part of the Sec. 4.3 error split),
+    which a difference of two errors against the exact solution can hide by
+    cancellation."""
+    from .solver import Solver
+
+    n_steps = {w.n_steps for w in workloads}
+    if len(n_steps) != 1:
+        raise ValueError("problems of one context must take the same number of steps")
+    n = n_steps.pop()
+    s = Solver(workloads)
+    try:
+        u = s.initial_state()
+        s.run(u, n, graph=True)
+        ref = s.empty_state()
+        twins = {}
+        for i, w in enumerate(workloads):
+            key = (w.n_elem, w.degree, w.rk, w.dt)
+            if key not in twins:
+                sd = Solver(synchronous_twin(w))
+                try:
+                    ud = sd.initial_state()
+                    sd.run(ud, n, graph=True)
+                    twins[key] = sd.view(ud, 0).clone()
+                finally:
+                    sd.close()
+            s.view(ref, i).copy_(twins[key])
+        return s.ensemble_stats(u, ref, group_of, n_groups)
+    finally:
+        s.close()
+
+
+def async_vs_pe(scheme_key: str = "at4", n_elem: int = 64, pe_counts=PE_COUNTS, n_real: int = 32,
+                probs=W.DELAYS_FIG9, t_final: float = 1.0) -> dict:
+    """Fig. 9 through the asynchrony term alone: <|u_AT - u_DG|> against P at
+    one mesh; the Sec. 5 scaling <E_f> ~ (P / N_E) dt^a sum gamma_m E[k^m]
+    predicts slope 1 in P."""
+    ws, grp = W.error_vs_pe_workloads(scheme_key, n_elem, pe_counts, n_real, probs, t_final)
+    st = run_groups_async(ws, grp, len(pe_counts))
+    mean = [x[0] for x in st]
+    std = [math.sqrt(max(x[1], 0.0)) for x in st]
+    out = {"scheme": scheme_key, **W.SCALING_SCHEMES[scheme_key], "n_elem": n_elem, "probs": list(probs),
+           "t_final": t_final, "n_real": n_real, "pe_counts": list(pe_counts), "async_mean": mean,
+           "async_std": std, "slope_vs_pe": None, "slope_se": None}
+    if min(mean) > 0:
+        # the term varies strongly between delay realizations: the slope
+        # carries the standard errors of the means (std / sqrt(n_real))
+        slope, se = loglog_slope_se(pe_counts, mean, [sd / math.sqrt(n_real) for sd in std])
+        out.update({"slope_vs_pe": slope, "slope_se": se})
+    return out
+
+
+def async_vs_delay(scheme_key: str = "at4", n_elem: int = 128, n_pe: int = 16, delay_counts=(1, 2, 3, 4),
+                   n_real: int = 32, sigma: float = 0.005, t_final: float = 1.0) -> dict:
+    """Fig. 10 through the asynchrony term alone: <|u_AT - u_DG|> against the
+    maximum delay L (uniform p_k), beside the delay moment of the AT remainder
+    E[k (k+1) ... (k+q-1)] (zero for L = 1, where the run equals DG), and
+    the ratio of the two (constant where the leading remainder dominates)."""
+    q = W.SCALING_SCHEMES[scheme_key]["degree"] + 1
+    ws, grp = W.error_vs_delay_workloads(scheme_key, n_elem, n_pe, delay_counts, n_real, t_final, sigma=sigma)
+    st = run_groups_async(ws, grp, len(delay_counts))
+    mean = [x[0] for x in st]
+    moments = [float(delay_moment(W.uniform_probs(L), q)) for L in delay_counts]
+    stable = [math.isfinite(m) and m < STABLE_ERROR for m in mean]
+    return {"scheme": scheme_key, "degree": W.SCALING_SCHEMES[scheme_key]["degree"],
+            "rk": W.SCALING_SCHEMES[scheme_key]["rk"], "sigma": sigma, "n_elem": n_elem, "n_pe": n_pe,
+            "t_final": t_final, "n_real": n_real, "q": q, "delay_counts": list(delay_counts),
+            "async_mean": mean, "async_std": [math.sqrt(max(x[1], 0.0)) if math.isfinite(x[1]) else None
+                                              for x in st],
+            "delay_moment": moments, "stable": stable,
+            "ratio_to_moment": [m / d if d > 0 and ok else None for m, d, ok in zip(mean, moments, stable)]}
 
 
 def sync_error(scheme_key: str, n_elem: int, t_final: float) -> float:
@@ -257,6 +363,10 @@ def main(argv=None) -> int:
     out = {"error_vs_pe": [error_vs_pe("at2", n_elems=(64, 128, 256, 512, 1024)),
                            error_vs_pe("at4", n_elems=(64, 128, 256, 512))],
            "error_vs_delay": [error_vs_delay("at2", n_elem=512), error_vs_delay("at4", n_elem=128)],
+           "async_vs_pe": [async_vs_pe("at4", n_elem=64), async_vs_pe("at2", n_elem=1024)],
+           "async_vs_delay": [async_vs_delay("at4", n_elem=128), async_vs_delay("at2", n_elem=512,
+                                                                                delay_counts=(1, 2, 3, 4, 5),
+                                                                                sigma=0.1)],
            "communication_avoiding": [error_caa("at2"), error_caa("at4", n_elems=(64, 128, 256, 512))],
            "viscous_burgers": viscous_burgers_convergence(),
            "burgers": burgers_convergence()}

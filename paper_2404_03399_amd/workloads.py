@@ -178,38 +178,39 @@ def uniform_probs(n_delays: int) -> Tuple[str, ...]:
 
 
 def scaling_workload(scheme_key: str, n_elem: int, n_pe: int, probs, seed: int, t_final: float = 1.0,
-                     scheme: str = "adg_at", name: str = "") -> Workload:
+                     scheme: str = "adg_at", name: str = "", sigma: float = 0.0) -> Workload:
     """One problem of the scaling experiments: linear advection a = 1 on
-    [0, 2 pi), P = n_pe PEs, delays drawn once per step (Section 6.1)."""
+    [0, 2 pi), P = n_pe PEs, delays drawn once per step (Section 6.1);
+    sigma overrides the scheme's Courant number."""
     cfg = SCALING_SCHEMES[scheme_key]
-    dt, n = time_step(TWO_PI, n_elem, cfg["sigma"], 1.0, t_final)
+    dt, n = time_step(TWO_PI, n_elem, sigma or cfg["sigma"], 1.0, t_final)
     return Workload(name=name or f"{scheme_key}_{scheme}_N{n_elem}_P{n_pe}_s{seed}", scheme=scheme,
                     rk=cfg["rk"], degree=cfg["degree"], n_elem=n_elem, pe_size=n_elem // n_pe,
                     probs=tuple(probs), seed=seed, per_stage=False, dt=dt, n_steps=n, ic=SCALING_IC)
 
 
 def error_vs_pe_workloads(scheme_key: str, n_elem: int, pe_counts, n_real: int, probs=DELAYS_FIG9,
-                          t_final: float = 1.0, seed_base: int = 9):
+                          t_final: float = 1.0, seed_base: int = 9, sigma: float = 0.0):
     """Fig. 9 at one mesh: n_real delay realizations for each P (group g =
     index of P).  Seeds are distinct across meshes, P and realizations."""
     out, group = [], []
     for g, npe in enumerate(pe_counts):
         for r in range(n_real):
             seed = (seed_base << 48) | (n_elem << 24) | (npe << 16) | r
-            out.append(scaling_workload(scheme_key, n_elem, npe, probs, seed, t_final))
+            out.append(scaling_workload(scheme_key, n_elem, npe, probs, seed, t_final, sigma=sigma))
             group.append(g)
     return out, group
 
 
 def error_vs_delay_workloads(scheme_key: str, n_elem: int, n_pe: int, delay_counts, n_real: int,
-                             t_final: float = 1.0, seed_base: int = 10):
+                             t_final: float = 1.0, seed_base: int = 10, sigma: float = 0.0):
     """Fig. 10: n_real realizations for each maximum delay L with uniform p_k
     (group g = index of L)."""
     out, group = [], []
     for g, nd in enumerate(delay_counts):
         for r in range(n_real):
             seed = (seed_base << 48) | (nd << 24) | r
-            out.append(scaling_workload(scheme_key, n_elem, n_pe, uniform_probs(nd), seed, t_final))
+            out.append(scaling_workload(scheme_key, n_elem, n_pe, uniform_probs(nd), seed, t_final, sigma=sigma))
             group.append(g)
     return out, group
 
