@@ -190,6 +190,25 @@ int adg_workspace_size(const adg_problem* probs, int32_t n_probs, const adg_opti
 int adg_init(adg_ctx** out, const adg_problem* probs, int32_t n_probs, const adg_options* opt,
              int64_t n_steps_record, void* d_workspace, int64_t workspace_bytes, void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): adg_init
+ * with no recording horizon (n_steps_record = 0) whose workspace is a
+ * file-scope static device array of the library, ADG_SCRATCH_BYTES bytes
+ * (64 MiB) per GPU, held from first use until the process ends.  No device
+ * memory is allocated or freed by this call; the caller still owns the state
+ * vectors.  Problems whose workspace (adg_workspace_size with
+ * n_steps_record = 0) exceeds the array are rejected with ADG_E_WORKSPACE
+ * before any device call.  One array per GPU: a later adg_init_scratch on
+ * the same device takes it over, after which every call on the earlier
+ * context except adg_step_count and adg_destroy returns ADG_E_STATE; calls
+ * that overlap in time on one GPU (several threads or streams) race on the
+ * array.  The step counter, rings and records are cleared as by adg_init.
+ * adg_run with ADG_RUN_GRAPH creates a capture stream and a graph; run
+ * without that flag when nothing may be created. */
+#define ADG_SCRATCH_BYTES (64ll << 20)
+int adg_init_scratch(adg_ctx** out, const adg_problem* probs, int32_t n_probs, const adg_options* opt,
+                     void* hip_stream);
+
 /* Back to t = 0 (Sec. 2 problem statement): step counter := 0, delay
  * history (rings, Sec. 3) := 0, recorded checkpoints dropped.  Enqueued on
  * the context's stream.  ADG_E_INVALID for a null context. */

@@ -29,13 +29,15 @@ RK = {"heun": 0, "ssprk3": 1, "rk4": 2, "lsrk3": 3, "lsrk4": 4}
 RK_STAGES = {"heun": 2, "ssprk3": 3, "rk4": 4, "lsrk3": 3, "lsrk4": 5}
 KERNEL = {"auto": 0, "stage": 1, "fused": 2}
 
+ADG_SCRATCH_BYTES = 64 << 20
+
 ADG_RUN_GRAPH = 1
 ADG_RUN_RECORD = 2
 ADG_RUN_CHECK_FINITE = 4
 
 SYMBOLS = [
     "adg_abi_version", "adg_last_error", "adg_build_id", "adg_nodes", "adg_state_layout", "adg_workspace_size",
-    "adg_init", "adg_reset", "adg_step_count", "adg_step", "adg_run", "adg_adjoint",
+    "adg_init", "adg_init_scratch", "adg_reset", "adg_step_count", "adg_step", "adg_run", "adg_adjoint",
     "adg_error_stats", "adg_ensemble_stats", "adg_delay_schedule", "adg_destroy",
 ]
 
@@ -92,6 +94,7 @@ def lib() -> C.CDLL:
             "adg_state_layout": ([P(adg_problem), I32, P(I64), P(I64), P(I64)], C.c_int),
             "adg_workspace_size": ([P(adg_problem), I32, P(adg_options), I64, P(I64)], C.c_int),
             "adg_init": ([P(vp), P(adg_problem), I32, P(adg_options), I64, vp, I64, vp], C.c_int),
+            "adg_init_scratch": ([P(vp), P(adg_problem), I32, P(adg_options), vp], C.c_int),
             "adg_reset": ([vp], C.c_int),
             "adg_step_count": ([vp, P(I64)], C.c_int),
             "adg_step": ([vp, vp], C.c_int),
@@ -156,6 +159,14 @@ def adg_init(probs, opt: adg_options, n_steps_record: int, d_workspace: int, wor
     ctx = C.c_void_p()
     check(lib().adg_init(C.byref(ctx), arr, n, C.byref(opt), n_steps_record, C.c_void_p(d_workspace),
                          workspace_bytes, C.c_void_p(stream)), "adg_init")
+    return ctx
+
+
+def adg_init_scratch(probs, opt: adg_options, stream: int):
+    n = len(probs)
+    arr = (adg_problem * n)(*probs)
+    ctx = C.c_void_p()
+    check(lib().adg_init_scratch(C.byref(ctx), arr, n, C.byref(opt), C.c_void_p(stream)), "adg_init_scratch")
     return ctx
 
 

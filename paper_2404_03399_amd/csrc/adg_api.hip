@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -378,6 +379,10 @@ struct adg_ctx {
   int64_t steps = 0;
   // adjoint recording: steps recorded by the last ADG_RUN_RECORD run (0: none)
   int64_t rec_steps = 0;
+  // adg_init_scratch: the device whose static scratch array holds the
+  // workspace and the generation of that use (-1: caller's workspace)
+  int scratch_dev = -1;
+  uint64_t scratch_gen = 0;
   // graph cache
   hipGraphExec_t graph = nullptr;
   const double* graph_u = nullptr;
@@ -521,6 +526,54 @@ int build_graph(adg_ctx* c, double* d_u) {
   c->graph = ex;
   c->graph_u = d_u;
   c->graph_steps = kGraphSteps;
+  return ADG_OK;
+}
+
+}  // namespace
+
+// Workspace of adg_init_scratch, for callers that cannot allocate device
+// memory: one array per GPU the library runs on, held until the process ends.
+// Host code never uses this name as a device address (on the host it is a
+// stand-in); its per-device address comes from hipGetSymbolAddress.
+constexpr int64_t kScratchBytes = ADG_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_ptr;       // per device: address of `scratch`
+std::vector<uint64_t> g_scratch_gen;    // per device: generation of the current use
+
+// Address of the scratch array on the current device (looked up once per
+// device) and a new generation number for its next use.
+int scratch_acquire(int* dev_out, void** ptr_out, uint64_t* gen_out) {
+  int dev = 0;
+  ADG_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if ((int)g_scratch_ptr.size() <= dev) {
+    g_scratch_ptr.resize(dev + 1, nullptr);
+    g_scratch_gen.resize(dev + 1, 0);
+  }
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(ADG_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *dev_out = dev;
+  *ptr_out = g_scratch_ptr[dev];
+  *gen_out = ++g_scratch_gen[dev];
+  return ADG_OK;
+}
+
+// A context on the scratch array is live until a later adg_init_scratch on
+// the same device takes the array over.
+int check_live(const adg_ctx* c) {
+  if (c->scratch_dev < 0) return ADG_OK;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (c->scratch_gen != g_scratch_gen[c->scratch_dev])
+    return fail(ADG_E_STATE, "the scratch workspace was taken over by a later adg_init_scratch");
   return ADG_OK;
 }
 
@@ -753,8 +806,30 @@ int adg_init(adg_ctx** out, const adg_problem* probs, int32_t n_probs, const adg
   return ADG_OK;
 }
 
+int adg_init_scratch(adg_ctx** out, const adg_problem* probs, int32_t n_probs, const adg_options* opt,
+                     void* hip_stream) {
+  if (!out) return fail(ADG_E_INVALID, "out is null");
+  *out = nullptr;
+  int64_t need = 0;
+  int rc = adg_workspace_size(probs, n_probs, opt, 0, &need);
+  if (rc) return rc;
+  if (need > kScratchBytes)
+    return fail(ADG_E_WORKSPACE, "adg_init_scratch: these problems need " + std::to_string(need) +
+                                     " bytes of workspace; the static scratch array holds " +
+                                     std::to_string(kScratchBytes));
+  int dev = 0;
+  void* ws = nullptr;
+  uint64_t gen = 0;
+  if ((rc = scratch_acquire(&dev, &ws, &gen))) return rc;
+  if ((rc = adg_init(out, probs, n_probs, opt, 0, ws, need, hip_stream))) return rc;
+  (*out)->scratch_dev = dev;
+  (*out)->scratch_gen = gen;
+  return ADG_OK;
+}
+
 int adg_reset(adg_ctx* c) {
   if (!c) return fail(ADG_E_INVALID, "null context");
+  if (int rc = check_live(c)) return rc;
   return reset_device(c);
 }
 
@@ -766,6 +841,7 @@ int adg_step_count(const adg_ctx* c, int64_t* steps) {
 
 int adg_run(adg_ctx* c, double* d_u, int64_t n_steps, uint32_t flags) {
   if (!c || !d_u) return fail(ADG_E_INVALID, "null argument");
+  if (int rc = check_live(c)) return rc;
   if (!state_aligned(d_u)) return fail(ADG_E_INVALID, "d_u must be 16-byte aligned");
   if (n_steps < 0) return fail(ADG_E_INVALID, "n_steps < 0");
   if (c->steps + n_steps >= ((int64_t)1 << 31)) return fail(ADG_E_INVALID, "step index would exceed 2^31 - 1");
@@ -1035,6 +1111,7 @@ int adjoint_fused(adg_ctx* c, const double* d_cot_uT, double* d_grad_u0, double*
 
 int adg_adjoint(adg_ctx* c, const double* d_cot_uT, double* d_grad_u0, double* h_grad_speed) {
   if (!c || !d_cot_uT || !d_grad_u0) return fail(ADG_E_INVALID, "null argument");
+  if (int rc = check_live(c)) return rc;
   if (!state_aligned(d_cot_uT) || !state_aligned(d_grad_u0))
     return fail(ADG_E_INVALID, "d_cot_uT and d_grad_u0 must be 16-byte aligned");
   if (c->rec_steps <= 0) return fail(ADG_E_STATE, "adg_adjoint needs a run recorded with ADG_RUN_RECORD");
@@ -1045,6 +1122,7 @@ int adg_adjoint(adg_ctx* c, const double* d_cot_uT, double* d_grad_u0, double* h
 int adg_error_stats(adg_ctx* c, const double* d_u, const double* d_ref, double* h_out) {
   if (!c || !d_u || !d_ref || !h_out) return fail(ADG_E_INVALID, "null argument");
   if (!state_aligned(d_u) || !state_aligned(d_ref)) return fail(ADG_E_INVALID, "d_u and d_ref must be 16-byte aligned");
+  if (int rc = check_live(c)) return rc;
   const int32_t n = (int32_t)c->probs.size();
   double* part = (double*)(c->ws + c->L.part);
   double* dout = (double*)(c->ws + c->L.stats_out);
@@ -1058,6 +1136,7 @@ int adg_ensemble_stats(adg_ctx* c, const double* d_u, const double* d_ref, const
                        int32_t n_groups, double* h_out) {
   if (!c || !d_u || !d_ref || !h_group_of || !h_out) return fail(ADG_E_INVALID, "null argument");
   if (!state_aligned(d_u) || !state_aligned(d_ref)) return fail(ADG_E_INVALID, "d_u and d_ref must be 16-byte aligned");
+  if (int rc = check_live(c)) return rc;
   const int32_t n = (int32_t)c->probs.size();
   if (n_groups < 1 || n_groups > n) return fail(ADG_E_INVALID, "n_groups must be in 1..n_probs");
   std::vector<int32_t> csr(2 * (size_t)n + 1, 0);  // [gstart (n_groups+1) | members (n)]

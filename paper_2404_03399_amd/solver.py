@@ -64,7 +64,9 @@ class Solver:
     """One context over one or more problems (batched when more than one)."""
 
     def __init__(self, workloads, kernel: str = "auto", n_steps_record: int = 0, ckpt_every: int = 0,
-                 device: str = "cuda", stream=None, lane_elems=0, fused_steps: int = 0):
+                 device: str = "cuda", stream=None, lane_elems=0, fused_steps: int = 0, scratch: bool = False):
+        """scratch: take the library's static device workspace (adg_init_scratch)
+        instead of allocating one; no recording horizon."""
         if not isinstance(workloads, (list, tuple)):
             workloads = [workloads]
         self.workloads = list(workloads)
@@ -82,11 +84,22 @@ class Solver:
         self.opt.lane_elems = int(lane_elems)
         self.opt.fused_steps = int(fused_steps)
         self.ws_bytes = adg.adg_workspace_size(self.probs, self.opt, n_steps_record)
-        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=torch.device(device))
-        self.device = self.workspace.device  # with its index
         self.stream = stream
-        self.ctx = adg.adg_init(self.probs, self.opt, n_steps_record, self.workspace.data_ptr(),
-                                self.ws_bytes, _stream_handle(stream))
+        if scratch:
+            if n_steps_record:
+                raise ValueError("the static scratch workspace has no recording horizon")
+            dev = torch.device(device)
+            if dev.index is None:
+                dev = torch.device(dev.type, torch.cuda.current_device())
+            self.device = dev
+            self.workspace = None
+            with torch.cuda.device(dev):
+                self.ctx = adg.adg_init_scratch(self.probs, self.opt, _stream_handle(stream))
+        else:
+            self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=torch.device(device))
+            self.device = self.workspace.device  # with its index
+            self.ctx = adg.adg_init(self.probs, self.opt, n_steps_record, self.workspace.data_ptr(),
+                                    self.ws_bytes, _stream_handle(stream))
 
     def close(self):
         if getattr(self, "ctx", None) is not None:

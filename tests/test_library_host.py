@@ -316,3 +316,15 @@ def test_stale_library_is_refused(monkeypatch):
     monkeypatch.setattr(adg, "_LIB", None)
     with pytest.raises(ImportError, match="other sources"):
         adg.lib()
+
+
+def test_scratch_init_rejects_oversized_problems(L):
+    """adg_init_scratch refuses, before any device call, problems whose
+    workspace exceeds the static scratch array."""
+    w = W.c2_advection_large("adg_at", n_elem=1 << 24)
+    p = solver.to_problem(w)
+    assert adg.adg_workspace_size([p], adg.adg_options()) > adg.ADG_SCRATCH_BYTES
+    with pytest.raises(adg.AdgError) as ei:
+        adg.adg_init_scratch([p], adg.adg_options(), 0)
+    assert ei.value.code == adg.ADG_E_WORKSPACE
+    assert "static scratch" in str(ei.value)
