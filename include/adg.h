@@ -128,11 +128,25 @@ typedef struct adg_options {
   int32_t kernel;              /* adg_kernel; AUTO -> FUSED */
   int32_t lane_elems;          /* fused kernel: consecutive elements per lane, 1, 2 or 4 (<= every
                                   asynchronous problem's pe_size); 0 -> 1 */
-  uint32_t flags;              /* reserved, 0 */
+  uint32_t flags;              /* ADG_OPT_* bits, 0 = defaults */
   uint32_t fused_steps;        /* fused kernel: time steps per launch, 1 or 2 (halo of 2S elements per side,
                                   half the state traffic per step); 0 -> 2.  Every (lane_elems,
                                   fused_steps) pair gives bitwise the same results. */
 } adg_options;
+
+/* adg_options.flags.  Fused kernel, PE-face split (only PE faces see
+ * delayed data, Secs. 3, 5): within one launch, tile waves without any
+ * PE-face handling advance every tile, and window waves recompute windows of
+ * 4 K S elements around each PE face (K steps per launch, S stages), owning
+ * the 2 K S elements that the face's delayed flux can reach, which the tile
+ * waves leave alone; the result is bitwise that of the unsplit kernel.  By default the split is
+ * used when a wave holds at least two windows of the longest launch and
+ * every asynchronous problem's PE size holds four (RK4 with two steps per
+ * launch: PE size >= 128); ADG_OPT_PE_SPLIT_OFF never splits,
+ * ADG_OPT_PE_SPLIT_ON splits whenever the PE sizes hold one window.  Other
+ * bits: ADG_E_INVALID. */
+#define ADG_OPT_PE_SPLIT_OFF 1u
+#define ADG_OPT_PE_SPLIT_ON 2u
 
 typedef struct adg_ctx adg_ctx;  /* opaque, host side, library owned */
 

@@ -31,6 +31,9 @@ KERNEL = {"auto": 0, "stage": 1, "fused": 2}
 
 ADG_SCRATCH_BYTES = 64 << 20
 
+ADG_OPT_PE_SPLIT_OFF = 1
+ADG_OPT_PE_SPLIT_ON = 2
+
 ADG_RUN_GRAPH = 1
 ADG_RUN_RECORD = 2
 ADG_RUN_CHECK_FINITE = 4

@@ -34,34 +34,72 @@ namespace adg {
 // overlap the state loads, and the levels of the launch are added at the end
 // from the owner's raw fluxes kept on chip.  A delay of 0 selects the
 // synchronous flux.  AT sums add the oldest level first in every path.
-template <int NP, int RK, int PHYS, int R, int K>
+//
+// MODE: TILE_FULL as above; TILE_NOPE compiles every PE-face path out (all
+// faces synchronous: exact for problems without asynchronous faces, and away
+// from PE faces for the others); TILE_MAIN is TILE_NOPE storing only the
+// elements farther than K S from a PE face of an asynchronous problem;
+// TILE_WINDOW runs the full PE logic on windows of 4 K S elements centred on
+// PE faces (one element per lane), owning the 2 K S elements around each
+// face that its delayed flux can reach in K S stages.  TILE_MAIN waves over
+// every tile and TILE_WINDOW waves over every PE face compute each element
+// with the same instructions as TILE_FULL, so the result is bitwise the same.
+enum TileMode : int { TILE_FULL = 0, TILE_NOPE = 1, TILE_MAIN = 2, TILE_WINDOW = 3 };
+
+template <int NP, int RK, int PHYS, int R, int K, int MODE>
 __device__ __forceinline__ void wave_tile(const DevProblem& P, const WorkItem wi, const FusedPtrs& A, int64_t n,
                                           const double* __restrict__ uin, double* __restrict__ uout,
                                           double* __restrict__ umid, WaveSmemK<K, rk_stages(RK)>& sm, int wv,
                                           int lane) {
 #pragma clang fp contract(off)  // explicit FMAs only: rounding independent of the launch shape
   constexpr int S = rk_stages(RK);
+  constexpr bool PEF = MODE == TILE_FULL || MODE == TILE_WINDOW;  // PE-face paths compiled in
+  constexpr bool WIN = MODE == TILE_WINDOW;
+  static_assert(!WIN || R == 1, "windows take one element per lane");
   constexpr int HL = fused_halo(RK, R, K);
   constexpr int T = fused_tile(RK, R, K);
   const int N = (int)P.n_elem;
-  const int e0 = wi.tile * T;
-  const int teff = (N - e0) < T ? (N - e0) : T;
-  const int xb = e0 - R * HL;  // element position of lane 0, element 0 (a multiple of R)
   // With N a multiple of R a lane's R elements never straddle the periodic
   // wrap, so one R*8-byte access per plane serves them all.
   const bool grouped = R > 1 && (N % R) == 0;
   const int64_t ld = P.ld;
   const double* __restrict__ u = uin + P.u_off;
-  const bool lane_owned = lane >= HL && lane < kWave - HL;
 
-  const bool tiny = N < kWave * R;  // the wave's extent may wrap more than once
   int e[R];
   bool owned[R];
+  if constexpr (WIN) {
+    // window w of the wave covers elements f - 2KS .. f + 2KS - 1 of face
+    // f = (tile * FW + w) pe_size and owns f - KS .. f + KS - 1; lanes past
+    // the last window, and windows past the last face, own nothing
+    constexpr int WW = fused_window(RK, K), FW = kWave / WW;
+    const int w = lane / WW, l = lane - w * WW;
+    const int fi = wi.tile * FW + (w < FW ? w : FW - 1);
+    const int n_pe = (int)P.n_pe;
+    const int x = (fi < n_pe ? fi : n_pe - 1) * (int)P.pe_size - 2 * K * S + l;
+    e[0] = wrap_once(x, N);
+    owned[0] = w < FW && fi < n_pe && l >= K * S && l < 3 * K * S;
+  } else {
+    const int e0 = wi.tile * T;
+    const int teff = (N - e0) < T ? (N - e0) : T;
+    const int xb = e0 - R * HL;  // element position of lane 0, element 0 (a multiple of R)
+    const bool lane_owned = lane >= HL && lane < kWave - HL;
+    const bool tiny = N < kWave * R;  // the wave's extent may wrap more than once
 #pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const int x = xb + R * lane + r;
-    e[r] = tiny ? wrap_elem(x, N) : wrap_once(x, N);
-    owned[r] = lane_owned && (x - e0) < teff;
+    for (int r = 0; r < R; ++r) {
+      const int x = xb + R * lane + r;
+      e[r] = tiny ? wrap_elem(x, N) : wrap_once(x, N);
+      owned[r] = lane_owned && (x - e0) < teff;
+    }
+    if constexpr (MODE == TILE_MAIN) {
+      if (P.async_faces) {  // the window waves own the elements near PE faces
+        const uint32_t pes = P.pe_div.d;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const uint32_t d = (uint32_t)e[r] - fast_div((uint32_t)e[r], P.pe_div) * pes;
+          owned[r] = owned[r] && d >= (uint32_t)(K * S) && d < pes - (uint32_t)(K * S);
+        }
+      }
+    }
   }
   double u0[R][NP];
   if (grouped) {
@@ -92,7 +130,7 @@ __device__ __forceinline__ void wave_tile(const DevProblem& P, const WorkItem wi
   for (int kk = 0; kk < K; ++kk) kp[kk] = 0;
 #pragma unroll
   for (int r = 0; r < R; ++r) pe[r] = false;
-  if (P.async_faces) {
+  if (PEF && P.async_faces) {
     depth = P.depth;
     const uint32_t n32 = (uint32_t)n;  // step indices stay below 2^31
     slot_n = (int)(n32 - fast_div(n32, P.depth_div) * (uint32_t)depth);
@@ -310,24 +348,42 @@ __device__ __forceinline__ void wave_tile(const DevProblem& P, const WorkItem wi
   }
 }
 
-template <int NP, int RK, int PHYS, int R, int K>
+// MODE: fused_mode of the range.  Under FUSED_SPLIT the range interleaves
+// window items (tile index -(g + 1) for window group g) with tile items in
+// order of position along the mesh, so that the workgroups of one XCD hold
+// the windows and the tiles of one stretch of elements (balanced work, and
+// the windows' reads meet the tiles' in that XCD's L2); a wave takes one of
+// the two paths as a whole, so the kernel's registers are those of the
+// larger path, not of both.
+template <int NP, int RK, int PHYS, int R, int K, int MODE>
 __global__ __launch_bounds__(kBlock) void k_fused_step(const DevProblem* __restrict__ probs,
                                                        const WorkItem* __restrict__ work,
                                                        const int64_t* __restrict__ ctr, double* __restrict__ ring,
                                                        double* __restrict__ atsum, RecWord* __restrict__ atk,
-                                                       int32_t w_begin, int32_t w_end, const double* __restrict__ uin,
-                                                       double* __restrict__ uout, double* __restrict__ umid,
-                                                       int32_t step_offset, int32_t single_prob) {
+                                                       int32_t w_begin, int32_t w_end,
+                                                       const double* __restrict__ uin, double* __restrict__ uout,
+                                                       double* __restrict__ umid, int32_t step_offset,
+                                                       int32_t single_prob) {
   __shared__ WaveSmemK<K, rk_stages(RK)> sm;
   const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
   const int lane = (int)(threadIdx.x % kWave);
   const int w = w_begin + xcd_block((int)blockIdx.x, (int)gridDim.x) * kWavesPerBlock + wv;
   if (w >= w_end) return;  // whole wave
   const int64_t n = ctr[0] + step_offset;
-  // a range holding one problem lists its tiles in order: no work-list load
-  const WorkItem wi = single_prob >= 0 ? WorkItem{single_prob, w - w_begin} : work[w];
   const FusedPtrs A{ring, atsum, atk};
-  wave_tile<NP, RK, PHYS, R, K>(probs[wi.prob], wi, A, n, uin, uout, umid, sm, wv, lane);
+  if constexpr (MODE == FUSED_SPLIT) {
+    const WorkItem wi = work[w];
+    if (wi.tile < 0)
+      wave_tile<NP, RK, PHYS, 1, K, TILE_WINDOW>(probs[wi.prob], WorkItem{wi.prob, -wi.tile - 1}, A, n, uin, uout,
+                                                 umid, sm, wv, lane);
+    else
+      wave_tile<NP, RK, PHYS, R, K, TILE_MAIN>(probs[wi.prob], wi, A, n, uin, uout, umid, sm, wv, lane);
+  } else {
+    // a range holding one problem lists its tiles in order: no work-list load
+    const WorkItem wi = single_prob >= 0 ? WorkItem{single_prob, w - w_begin} : work[w];
+    wave_tile<NP, RK, PHYS, R, K, MODE == FUSED_NOPE ? TILE_NOPE : TILE_FULL>(probs[wi.prob], wi, A, n, uin, uout,
+                                                                             umid, sm, wv, lane);
+  }
 }
 
 // Viscous Burgers in local DG form (Sec. 7): K in {1, 2} time steps per
@@ -538,15 +594,24 @@ static void fused_ldg_np(const StepArgs& a, const double* uin, double* uout, int
   }
 }
 
-template <int NP, int RK, int PHYS, int R>
-static void fused_go_r(const StepArgs& a, int gi, const double* uin, double* uout, int32_t off, hipStream_t st) {
+template <int NP, int RK, int PHYS, int R, int MODE>
+static void fused_go_m(const StepArgs& a, int gi, const double* uin, double* uout, int32_t off, hipStream_t st) {
   const dim3 g(a.grid[gi]), b(kBlock);
   if (a.steps == 2)
-    hipLaunchKernelGGL((k_fused_step<NP, RK, PHYS, R, 2>), g, b, 0, st, a.probs, a.work, a.ctr, a.ring, a.atsum, a.atk,
-                       a.group[gi], a.group[gi + 1], uin, uout, a.umid, off, a.single[gi]);
+    hipLaunchKernelGGL((k_fused_step<NP, RK, PHYS, R, 2, MODE>), g, b, 0, st, a.probs, a.work, a.ctr, a.ring, a.atsum,
+                       a.atk, a.group[gi], a.group[gi + 1], uin, uout, a.umid, off, a.single[gi]);
   else
-    hipLaunchKernelGGL((k_fused_step<NP, RK, PHYS, R, 1>), g, b, 0, st, a.probs, a.work, a.ctr, a.ring, a.atsum, a.atk,
-                       a.group[gi], a.group[gi + 1], uin, uout, nullptr, off, a.single[gi]);
+    hipLaunchKernelGGL((k_fused_step<NP, RK, PHYS, R, 1, MODE>), g, b, 0, st, a.probs, a.work, a.ctr, a.ring, a.atsum,
+                       a.atk, a.group[gi], a.group[gi + 1], uin, uout, nullptr, off, a.single[gi]);
+}
+
+template <int NP, int RK, int PHYS, int R>
+static void fused_go_r(const StepArgs& a, int gi, const double* uin, double* uout, int32_t off, hipStream_t st) {
+  switch (a.mode[gi]) {
+    case FUSED_NOPE: fused_go_m<NP, RK, PHYS, R, FUSED_NOPE>(a, gi, uin, uout, off, st); break;
+    case FUSED_SPLIT: fused_go_m<NP, RK, PHYS, R, FUSED_SPLIT>(a, gi, uin, uout, off, st); break;
+    default: fused_go_m<NP, RK, PHYS, R, FUSED_FULL>(a, gi, uin, uout, off, st); break;
+  }
 }
 
 template <int NP, int RK, int PHYS>

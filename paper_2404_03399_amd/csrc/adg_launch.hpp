@@ -21,6 +21,8 @@ struct StepArgs {
   double* qbuf;              // local DG: q = u_x of the current stage input (state layout)
   double* umid;              // fused kernel, two steps per launch: also write the state after
                              // the first step here (state layout), or null
+  int32_t mode[8];           // fused kernel: fused_mode of each range (FUSED_SPLIT ranges mark
+                             // their window items by tile index -(window group + 1))
 };
 
 // Work items of the fused kernel are sorted by descending np and, within a
@@ -39,6 +41,18 @@ constexpr int kWave = 64;
 constexpr int kWavesPerBlock = kBlock / kWave;
 __host__ __device__ constexpr int fused_halo(int rk, int R, int K) { return (K * rk_stages(rk) + R - 1) / R; }
 __host__ __device__ constexpr int fused_tile(int rk, int R, int K) { return R * (kWave - 2 * fused_halo(rk, R, K)); }
+
+// Fused kernel modes, per work range: FUSED_FULL handles PE faces in every
+// tile; FUSED_NOPE has every PE-face path compiled out (ranges without
+// asynchronous problems); FUSED_SPLIT (the PE-face split) runs two kinds of
+// wave in one launch: window waves (one element per lane, windows of
+// fused_window elements centred on PE faces, each owning the 2 K S elements
+// that the face's delayed flux reaches in K S stages, with every PE-face
+// path) and tile waves with the PE-face paths compiled out that store only
+// the elements outside those windows.
+enum fused_mode { FUSED_FULL = 0, FUSED_NOPE = 1, FUSED_SPLIT = 2 };
+__host__ __device__ constexpr int fused_window(int rk, int K) { return 4 * K * rk_stages(rk); }
+__host__ __device__ constexpr int fused_windows_per_wave(int rk, int K) { return kWave / fused_window(rk, K); }
 
 // Workgroups of the fused kernel for n_work items (kWavesPerBlock per group).
 inline int fused_grid(int n_work) { return n_work < 1 ? 1 : (n_work + kWavesPerBlock - 1) / kWavesPerBlock; }

@@ -328,3 +328,24 @@ def test_scratch_init_rejects_oversized_problems(L):
         adg.adg_init_scratch([p], adg.adg_options(), 0)
     assert ei.value.code == adg.ADG_E_WORKSPACE
     assert "static scratch" in str(ei.value)
+
+
+def test_option_flags_validated(L):
+    """adg_options.flags: the two PE-face split bits are accepted alone and
+    refused together; any other bit is refused; the split adds the window
+    work lists to the workspace."""
+    p = solver.to_problem(W.c2_advection_large("adg_at", n_elem=1 << 16))
+    base = adg.adg_workspace_size([p], adg.adg_options())
+    for f in (adg.ADG_OPT_PE_SPLIT_OFF, adg.ADG_OPT_PE_SPLIT_ON):
+        opt = adg.adg_options()
+        opt.flags = f
+        assert adg.adg_workspace_size([p], opt) > 0
+    off = adg.adg_options()
+    off.flags = adg.ADG_OPT_PE_SPLIT_OFF
+    assert adg.adg_workspace_size([p], off) < base  # PE size 256 splits by default
+    for f in (adg.ADG_OPT_PE_SPLIT_OFF | adg.ADG_OPT_PE_SPLIT_ON, 4, 1 << 31):
+        opt = adg.adg_options()
+        opt.flags = f
+        with pytest.raises(adg.AdgError) as ei:
+            adg.adg_workspace_size([p], opt)
+        assert ei.value.code == adg.ADG_E_INVALID
