@@ -41,7 +41,7 @@ def fused_flops_per_elem_step(np_: int) -> int:
     return 4 * (2 * np_ * np_ + np_ + 1) + 13 * np_
 
 
-FUSED_SOURCES = ("adg_fused.hip", "adg_device.hpp", "adg_common.hpp")
+FUSED_SOURCES = ("adg_fused.hip", "adg_device.hpp", "adg_common.hpp", "adg_launch.hpp")
 
 
 def kernel_source_hash() -> str:
@@ -428,14 +428,31 @@ def bench_ensemble(torch, W, Solver, n_steps: int, n_real: int, plain: bool):
             v = v + a * torch.sin(k * x + ph)
         s.view(ref, i).copy_(v)
     gstats = s.ensemble_stats(u, ref, group, max(group) + 1)
+    # the asynchrony term of each realization: its state against the
+    # synchronous run of its own mesh (both share the discretization error)
+    from paper_2404_03399_amd import experiments as X
+    twins = {}
+    ref_dg = s.empty_state()
+    for i, w in enumerate(ws):
+        key = (w.n_elem, w.degree, w.dt)
+        if key not in twins:
+            sd = Solver(X.synchronous_twin(w))
+            ud = sd.initial_state()
+            sd.run(ud, n_steps, graph=False)
+            twins[key] = sd.view(ud, 0).clone()
+            sd.close()
+        s.view(ref_dg, i).copy_(twins[key])
+    astats = s.ensemble_stats(u, ref_dg, group, max(group) + 1)
     out = {"workload": f"{len(set(group))} meshes x {n_real} realizations ({len(ws)} problems), "
                        f"{dofs} DOFs, {n_steps} RK4 steps, ADG-AT q=p+1",
            "lane_elems": R, "steps_per_launch": K,
            "batched_dof_stage_per_s": dofs * 4 * n_steps / t_batched, "batched_s": t_batched,
            "batched_rep_s": reps_batched, "roofline": roof,
            "per_mesh": [{"n_elem": ws[group.index(g)].n_elem, "degree": ws[group.index(g)].degree,
-                         "mean_err": st[0], "var_err": st[1], "mean_linf": st[2], "var_linf": st[3]}
-                        for g, st in enumerate(gstats)]}
+                         "mean_err": st[0], "var_err": st[1], "mean_linf": st[2], "var_linf": st[3],
+                         "async_mean": at[0], "async_var": at[1], "async_linf_mean": at[2],
+                         "async_linf_var": at[3]}
+                        for g, (st, at) in enumerate(zip(gstats, astats))]}
     if plain:
         # one context per problem, same problems and kernels, each at its own
         # tuned launch shape (context set-up, tuning and graph capture
