@@ -301,6 +301,8 @@ def bench_experiments():
     f9b = X.error_vs_pe("at4", n_elems=(64, 128, 256, 512))
     f10a = X.error_vs_delay("at2", n_elem=512, delay_counts=(1, 2, 3, 4, 5))
     f10b = X.error_vs_delay("at4", n_elem=128, delay_counts=(1, 2, 3, 4))
+    a9 = X.async_vs_pe("at4", n_elem=64, n_real=256)
+    a10 = X.async_vs_delay("at4", n_elem=128, delay_counts=(1, 2, 3, 4))
     caa = X.error_caa("at2")
     vb = X.viscous_burgers_convergence()
     bc = X.burgers_convergence()
@@ -313,6 +315,10 @@ def bench_experiments():
             "fig9_at4": {"order_in_n_elem": f9b["order_in_n_elem"], "order_dg": f9b["order_in_n_elem_dg"],
                          "inset_n_elem": f9b["inset"]["n_elem"], "inset_excess_over_dg": f9b["inset"]["excess_over_dg"]},
             "fig10_at2": slim(f10a), "fig10_at4": slim(f10b),
+            "fig9_at4_async_term": {k: a9[k] for k in ("n_elem", "n_real", "pe_counts", "async_mean", "async_std",
+                                                       "slope_vs_pe", "slope_se")},
+            "fig10_at4_async_term": {k: a10[k] for k in ("n_elem", "n_pe", "sigma", "n_real", "delay_counts",
+                                                         "async_mean", "delay_moment", "stable", "ratio_to_moment")},
             "caa_at2": {k: caa[k] for k in ("n_elems", "order_caa", "order_dg", "ratio_to_dg")},
             "fig11_viscous_burgers": {k: vb[k] for k in ("n_elems", "n_ref", "t_final", "dg", "adg_at",
                                                            "order_dg", "order_adg_at")},

@@ -127,7 +127,8 @@ typedef struct adg_options {
                                   straight into its slot, and the adjoint recomputes nothing) */
   int32_t kernel;              /* adg_kernel; AUTO -> FUSED */
   int32_t lane_elems;          /* fused kernel: consecutive elements per lane, 1, 2 or 4 (<= every
-                                  asynchronous problem's pe_size); 0 -> 1 */
+                                  asynchronous problem's pe_size); 0 -> 2, or 1 for viscous Burgers or
+                                  a PE size of 1 */
   uint32_t flags;              /* ADG_OPT_* bits, 0 = defaults */
   uint32_t fused_steps;        /* fused kernel: time steps per launch, 1 or 2 (halo of 2S elements per side,
                                   half the state traffic per step); 0 -> 2.  Every (lane_elems,

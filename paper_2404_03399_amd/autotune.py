@@ -1,5 +1,6 @@
 """Autotuner for the fused step kernel's launch shape: elements per lane
-(1, 2 or 4) and time steps per launch (1 or 2).
+(1, 2 or 4), time steps per launch (1 or 2) and, where the PE sizes allow
+it, the PE-face split on or off.
 
 The best pair depends on the problem set: register pressure grows with the
 elements per lane (fewer resident waves), larger tiles cut the halo
@@ -11,7 +12,7 @@ winner in a JSON file keyed by device, integrator, equation/flux, degrees
 and size.  Every pair gives bitwise the same states (the kernels use
 explicit FMAs with contraction off), so tuning never changes results.
 
-    R, K = autotune.tune(workloads)               # tuned (or cached) pair
+    R, K, split = autotune.tune(workloads)        # tuned (or cached) shape
     R = autotune.lane_elems(workloads)            # its elements per lane
     Solver(workloads, lane_elems="auto")           # same, through the solver
 """
@@ -21,7 +22,7 @@ import json
 import math
 import os
 import statistics
-from typing import List, Tuple
+from typing import List, Optional, Tuple
 
 CANDIDATES = (1, 2, 4)
 STEPS_PER_LAUNCH = (1, 2)
@@ -61,18 +62,38 @@ def admissible(workloads) -> List[int]:
     return [r for r in CANDIDATES if r <= pes]
 
 
-def configs(workloads) -> List[Tuple[int, int]]:
+def split_possible(workloads, k: int) -> bool:
+    """The PE-face split needs an asynchronous problem and, for every one, a
+    PE size holding a window of 4 k S elements (k steps per launch, S
+    stages)."""
+    from .adg import RK_STAGES
+    asyn = [w for w in workloads if w.scheme != "dg" and w.n_elem // w.pe_size > 1]
+    if not asyn or workloads[0].equation == "viscous_burgers":
+        return False
+    return min(w.pe_size for w in asyn) >= 4 * k * RK_STAGES[workloads[0].rk]
+
+
+def configs(workloads) -> List[Tuple[int, int, Optional[bool]]]:
+    """Candidate (R, K, split): split None where the PE-face split does not
+    apply (the library then has nothing to choose)."""
     if workloads[0].equation == "viscous_burgers":  # the local DG kernel: one element per lane
-        return [(1, k) for k in STEPS_PER_LAUNCH]
-    return [(r, k) for r in admissible(workloads) for k in STEPS_PER_LAUNCH]
+        return [(1, k, None) for k in STEPS_PER_LAUNCH]
+    out = []
+    for r in admissible(workloads):
+        for k in STEPS_PER_LAUNCH:
+            if split_possible(workloads, k):
+                out += [(r, k, False), (r, k, True)]
+            else:
+                out.append((r, k, None))
+    return out
 
 
 def tune(workloads, steps: int = 32, use_cache: bool = True, verbose: bool = False,
-         reps: int = 3) -> Tuple[int, int]:
-    """(elements per lane, steps per launch) with the shortest time per step:
-    for each pair the step graph is captured first (outside the timing), then
-    `reps` runs of `steps` graph-replayed steps are timed with HIP events and
-    the median is kept."""
+         reps: int = 3) -> Tuple[int, int, Optional[bool]]:
+    """(elements per lane, steps per launch, PE-face split) with the shortest
+    time per step: for each candidate the step graph is captured first
+    (outside the timing), then `reps` runs of `steps` graph-replayed steps are
+    timed with HIP events and the median is kept."""
     import torch
     from .solver import Solver
 
@@ -88,13 +109,17 @@ def tune(workloads, steps: int = 32, use_cache: bool = True, verbose: bool = Fal
             cache = json.load(open(path))
         except (OSError, ValueError):
             cache = {}
-        if key in cache and "fused_steps" in cache[key]:
-            return int(cache[key]["lane_elems"]), int(cache[key]["fused_steps"])
+        if key in cache and "pe_split" in cache[key]:
+            c = cache[key]
+            return int(c["lane_elems"]), int(c["fused_steps"]), c["pe_split"]
     steps = max(16, steps - steps % 16)  # whole graph replays only
     timings = {}
-    for r, k in configs(workloads):
-        s = Solver(workloads, lane_elems=r, fused_steps=k)
-        u = s.initial_state()
+    u_init = None  # the state layout does not depend on the launch shape
+    for r, k, split in configs(workloads):
+        s = Solver(workloads, lane_elems=r, fused_steps=k, pe_split=split)
+        if u_init is None:
+            u_init = s.initial_state()
+        u = u_init.clone()
         s.capture_graph(u)
         s.run(u, 16, graph=True)  # warm-up replay
         stream = s.stream if s.stream is not None else torch.cuda.current_stream()
@@ -108,15 +133,16 @@ def tune(workloads, steps: int = 32, use_cache: bool = True, verbose: bool = Fal
             ev1.record(stream)
             torch.cuda.synchronize()
             times.append(ev0.elapsed_time(ev1) / steps)
-        timings[(r, k)] = statistics.median(times)
+        timings[(r, k, split)] = statistics.median(times)
         s.close()
+        del u
     best = min(timings, key=timings.get)
     if verbose:
-        print(f"autotune {key}: " + ", ".join(f"R={r} K={k}: {t * 1e3:.2f} us" for (r, k), t in timings.items()),
-              flush=True)
+        print(f"autotune {key}: " + ", ".join(f"R={r} K={k} split={sp}: {t * 1e3:.2f} us"
+                                              for (r, k, sp), t in timings.items()), flush=True)
     if use_cache:
-        cache[key] = {"lane_elems": best[0], "fused_steps": best[1],
-                      "ms_per_step": {f"R={r},K={k}": t for (r, k), t in timings.items()}}
+        cache[key] = {"lane_elems": best[0], "fused_steps": best[1], "pe_split": best[2],
+                      "ms_per_step": {f"R={r},K={k},split={sp}": t for (r, k, sp), t in timings.items()}}
         os.makedirs(os.path.dirname(path), exist_ok=True)
         tmp = path + ".tmp"
         with open(tmp, "w") as fh:

@@ -259,7 +259,7 @@ int lane_elems_of(const adg_problem* probs, int32_t n, const adg_options* opt) {
   for (int32_t i = 0; i < n; ++i)
     if (async_of(probs[i])) min_pes = std::min(min_pes, probs[i].pe_size);
   const int req = opt ? opt->lane_elems : 0;
-  if (req == 0) return 1;
+  if (req == 0) return (probs[0].equation == ADG_EQ_VISCOUS_BURGERS || min_pes < 2) ? 1 : 2;
   if (req != 1 && req != 2 && req != 4) return 0;
   return req <= min_pes ? req : 0;
 }

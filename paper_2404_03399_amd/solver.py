@@ -82,8 +82,10 @@ class Solver:
             # elements per lane and (unless given) steps per launch, tuned together
             from . import autotune
             fused = kernel in ("fused", "auto")
-            lane_elems, k = autotune.tune(self.workloads) if fused else (0, 0)
+            lane_elems, k, split = autotune.tune(self.workloads) if fused else (0, 0, None)
             fused_steps = fused_steps or k
+            if pe_split is None:
+                pe_split = split
         self.opt.lane_elems = int(lane_elems)
         self.opt.fused_steps = int(fused_steps)
         if pe_split is not None:

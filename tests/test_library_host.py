@@ -349,3 +349,18 @@ def test_option_flags_validated(L):
         with pytest.raises(adg.AdgError) as ei:
             adg.adg_workspace_size([p], opt)
         assert ei.value.code == adg.ADG_E_INVALID
+
+
+def test_autotune_candidates_include_the_pe_split():
+    """The tuner tries the PE-face split on and off where every asynchronous
+    PE size holds a window of 4 K S elements, and leaves it to the library
+    elsewhere (no asynchronous face, or the local DG kernel)."""
+    from paper_2404_03399_amd import autotune
+    w = W.c2_advection_large("adg_at", n_elem=4096)          # RK4, PE size 256
+    c = autotune.configs([w])
+    assert {(r, k) for r, k, _ in c} == {(1, 1), (1, 2), (2, 1), (2, 2), (4, 1), (4, 2)}
+    assert all({(r, k, True), (r, k, False)} <= set(c) for r in (1, 2, 4) for k in (1, 2))
+    small = replace(w, pe_size=24)                           # holds a one-step window (16), not a two-step one (32)
+    c = autotune.configs([small])
+    assert (1, 1, True) in c and (1, 2, None) in c and (1, 2, True) not in c
+    assert all(sp is None for _, _, sp in autotune.configs([replace(w, scheme="dg")]))
