@@ -143,79 +143,106 @@ __global__ __launch_bounds__(kBlock) void k_adj_stage(const DevProblem* __restri
   }
 }
 
-// One reverse RK step of a lane's element in Butcher form: lamp = lambda^{m+1}
-// in, lu = lambda^m out, keep = the forward stage values (FWD).  On a lane
-// whose left face is a PE face, kd(s) and adjn(s) give the face's delay at
-// (m, s) and the adjoint already collected for its level-m raw flux, and
-// on_lf(s, lf) receives the face sensitivity to scatter.  Returns the lane's
-// dJ/da share (FWD, advection, owned lanes).  Explicit FMAs with contraction
-// off: every kernel that reverses a step does it with the same roundings.
-template <int NP, int RK, int PHYS, bool FWD, class KdF, class AdjF, class LfF>
-__device__ __forceinline__ double adj_reverse(const DevProblem& P, const double (&lamp)[NP], double (&lu)[NP],
-                                              const double (&keep)[rk_stages(RK)][NP], bool pe, bool owned,
-                                              KdF kd_of, AdjF adjn_of, LfF on_lf) {
+// One reverse RK step of a lane's R consecutive elements in Butcher form:
+// lamp = lambda^{m+1} in, lu = lambda^m out, keep = the forward stage values
+// (FWD, one element per lane).  pe[r]: the left face of element r is a PE
+// face (at most one r per lane); for it kd(s) and adjn(s) give the face's
+// delay at (m, s) and the adjoint already collected for its level-m raw flux,
+// and on_lf(s, lf) receives the face sensitivity to scatter.  Returns the
+// lane's dJ/da share (FWD, advection, owned lanes).  Each element takes the
+// same operations in the same order whatever R (a neighbour's face term comes
+// from the lane's own registers or by a lane shift), and explicit FMAs with
+// contraction off give every kernel that reverses a step the same roundings.
+template <int NP, int RK, int PHYS, bool FWD, int R, class KdF, class AdjF, class LfF>
+__device__ __forceinline__ double adj_reverse(const DevProblem& P, const double (&lamp)[R][NP], double (&lu)[R][NP],
+                                              const double (&keep)[rk_stages(RK)][NP], const bool (&pe)[R],
+                                              bool owned, KdF kd_of, AdjF adjn_of, LfF on_lf) {
 #pragma clang fp contract(off)
+  static_assert(R == 1 || (!FWD && PHYS != PHYS_BURGERS_LLF), "several elements per lane: constant Jacobian only");
   constexpr int S = rk_stages(RK);
   const double a = P.speed, dt = P.dt;
-  double Q[S][NP];
+  bool any_pe = false;
 #pragma unroll
-  for (int j = 0; j < NP; ++j) lu[j] = lamp[j];
+  for (int r = 0; r < R; ++r) any_pe = any_pe || pe[r];
+  double Q[R][S][NP];
 #pragma unroll
-  for (int s = 0; s < S; ++s)
+  for (int r = 0; r < R; ++r)
 #pragma unroll
-    for (int j = 0; j < NP; ++j) Q[s][j] = 0.0;
+    for (int j = 0; j < NP; ++j) lu[r][j] = lamp[r][j];
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int s = 0; s < S; ++s)
+#pragma unroll
+      for (int j = 0; j < NP; ++j) Q[r][s][j] = 0.0;
   double ca = 0.0;
 #pragma unroll
   for (int s = S - 1; s >= 0; --s) {
-    double lk[NP];
+    double lk[R][NP], cl[R], cr[R];
     const double bs = dt * bt_b<RK>(s);
 #pragma unroll
-    for (int i = 0; i < NP; ++i) lk[i] = s < S - 1 ? fma(bs, lamp[i], dt * Q[s][i]) : bs * lamp[i];
-    double cl = 0.0, cr = 0.0;
+    for (int r = 0; r < R; ++r) {
 #pragma unroll
-    for (int i = 0; i < NP; ++i) {
-      cl = fma(P.Kl[i], lk[i], cl);
-      cr = fma(P.Kr[i], lk[i], cr);
+      for (int i = 0; i < NP; ++i) lk[r][i] = s < S - 1 ? fma(bs, lamp[r][i], dt * Q[r][s][i]) : bs * lamp[r][i];
+      cl[r] = 0.0;
+      cr[r] = 0.0;
+#pragma unroll
+      for (int i = 0; i < NP; ++i) {
+        cl[r] = fma(P.Kl[i], lk[r][i], cl[r]);
+        cr[r] = fma(P.Kr[i], lk[r][i], cr[r]);
+      }
     }
-    // sensitivity of the flux applied at the left face (both neighbours' lifts)
-    const double lf = cl - lane_from_left(cr);
+    // sensitivity of the flux applied at each element's left face (both
+    // neighbours' lifts)
+    double raw[R];
+    raw[0] = cl[0] - lane_from_left(cr[R - 1]);
+#pragma unroll
+    for (int r = 1; r < R; ++r) raw[r] = cl[r] - cr[r - 1];
     double dm, dp;
     if constexpr (PHYS == PHYS_BURGERS_LLF)
       flux_partials<PHYS>(lane_from_left(keep[s][NP - 1]), keep[s][0], a, dm, dp);
     else
       flux_partials<PHYS>(0.0, 0.0, a, dm, dp);
-    double raw = lf;
-    if (pe) {
+    if (any_pe) {
+      double lf = raw[0];
+#pragma unroll
+      for (int r = 1; r < R; ++r) lf = pe[r] ? raw[r] : lf;
       const int kk = kd_of(s);
-      raw = (kk == 0 ? lf : 0.0) + adjn_of(s);
+      const double rp = (kk == 0 ? lf : 0.0) + adjn_of(s);
       on_lf(s, lf);
+#pragma unroll
+      for (int r = 0; r < R; ++r) raw[r] = pe[r] ? rp : raw[r];
     }
-    double mu[NP];
+    const double rdm = lane_from_right(raw[0] * dm);  // the right face of element R-1 is the next lane's first
 #pragma unroll
-    for (int j = 0; j < NP; ++j) {
-      double v = 0.0;
+    for (int r = 0; r < R; ++r) {
+      double mu[NP];
 #pragma unroll
-      for (int i = 0; i < NP; ++i) v = fma(P.Kd[i * kMaxNp + j], lk[i], v);
-      if constexpr (PHYS == PHYS_BURGERS_LLF)
-        mu[j] = (2.0 * keep[s][j]) * v;
-      else
-        mu[j] = v;
-    }
-    mu[0] = fma(raw, dp, mu[0]);
-    mu[NP - 1] += lane_from_right(raw * dm);  // the right face is the next lane's left face
+      for (int j = 0; j < NP; ++j) {
+        double v = 0.0;
 #pragma unroll
-    for (int j = 0; j < NP; ++j) lu[j] += mu[j];
+        for (int i = 0; i < NP; ++i) v = fma(P.Kd[i * kMaxNp + j], lk[r][i], v);
+        if constexpr (PHYS == PHYS_BURGERS_LLF)
+          mu[j] = (2.0 * keep[s][j]) * v;
+        else
+          mu[j] = v;
+      }
+      mu[0] = fma(raw[r], dp, mu[0]);
+      mu[NP - 1] += r + 1 < R ? raw[r + 1] * dm : rdm;
 #pragma unroll
-    for (int i = 0; i < s; ++i) {
-      const double c = bt_a<RK>(s, i);
-      if (c != 0.0)
+      for (int j = 0; j < NP; ++j) lu[r][j] += mu[j];
 #pragma unroll
-        for (int j = 0; j < NP; ++j) Q[i][j] = fma(c, mu[j], Q[i][j]);
-    }
-    if constexpr (FWD && PHYS != PHYS_BURGERS_LLF) {
-      if (owned)
+      for (int i = 0; i < s; ++i) {
+        const double c = bt_a<RK>(s, i);
+        if (c != 0.0)
 #pragma unroll
-        for (int i = 0; i < NP; ++i) ca = fma(lk[i], keep[s][i], ca);
+          for (int j = 0; j < NP; ++j) Q[r][i][j] = fma(c, mu[j], Q[r][i][j]);
+      }
+      if constexpr (FWD && PHYS != PHYS_BURGERS_LLF) {
+        if (owned)
+#pragma unroll
+          for (int i = 0; i < NP; ++i) ca = fma(lk[r][i], keep[s][i], ca);
+      }
     }
   }
   return ca;
@@ -266,11 +293,11 @@ __device__ __forceinline__ void adj_tile(const DevProblem& P, const WorkItem wi,
   const bool owned = lane >= HL && lane < kWave - HL && (x - e0) < teff;
   const int64_t ld = P.ld;
   const double* __restrict__ lp = lam + P.u_off;
-  double u0[NP], lamp[NP];
+  double u0[NP], lamp[1][NP];
 #pragma unroll
   for (int j = 0; j < NP; ++j) {
     if constexpr (FWD) u0[j] = uin[P.u_off + j * ld + e];
-    lamp[j] = lp[j * ld + e];
+    lamp[0][j] = lp[j * ld + e];
   }
 
   // PE face on this lane's left face.  Its delays of step n, the applied AT
@@ -327,15 +354,16 @@ __device__ __forceinline__ void adj_tile(const DevProblem& P, const WorkItem wi,
   }
 
   // reverse stages
-  double lu[NP];
-  const double ca = adj_reverse<NP, RK, PHYS, FWD>(
-      P, lamp, lu, keep, pe, owned, [&](int s) { return (int)sm.kd[wv][s][lane]; },
+  double lu[1][NP];
+  const bool pe1[1] = {pe};
+  const double ca = adj_reverse<NP, RK, PHYS, FWD, 1>(
+      P, lamp, lu, keep, pe1, owned, [&](int s) { return (int)sm.kd[wv][s][lane]; },
       [&](int s) { return sm.adjn[wv][s][lane]; }, [&](int s, double lf) { sm.adjn[wv][s][lane] = lf; });
 
   double* __restrict__ lo = lamo + P.u_off;
   if (owned)
 #pragma unroll
-    for (int j = 0; j < NP; ++j) lo[j * ld + e] = lu[j];
+    for (int j = 0; j < NP; ++j) lo[j * ld + e] = lu[0][j];
 
   // the delayed levels' share of the AT sensitivities into the adjoint ring
   // (levels below n, which nothing in this launch reads), one job lane per
@@ -368,51 +396,88 @@ __device__ __forceinline__ void adj_tile(const DevProblem& P, const WorkItem wi,
 }
 
 // Two reverse steps per launch without the forward stages (linear
-// advection, dJ/du0 only): lambda^n from lambda^{n+2}, halo 2S lanes.  Step
-// n+1 is reversed first.  Its PE-face sensitivity with delay 1 lands at level
-// n, which step n reads in the same launch: every lane holding that face adds
-// it to its own copy of step n's collected adjoint (the same FMA the adjoint
+// advection, dJ/du0 only): lambda^n from lambda^{n+2}, a halo of 2S elements
+// per side, R consecutive elements per lane as in the fused step.  Step n+1
+// is reversed first.  Its PE-face sensitivity with delay 1 lands at level n,
+// which step n reads in the same launch: every lane holding that face adds it
+// to its own copy of step n's collected adjoint (the same FMA the adjoint
 // ring would take) instead of waiting for the ring.  At the end one job lane
-// per (owned PE lane, stage, level below n) adds both steps' shares to the
+// per (owned PE element, stage, level below n) adds both steps' shares to the
 // adjoint ring, step n+1's first, so each entry is touched once per launch
-// and sums in the order of one step per launch.
+// and sums in the order of one step per launch.  A PE size of at least R puts
+// at most one PE face on a lane.
 template <int S>
 struct AdjSmem2 {
   uint8_t kd[2][kWavesPerBlock][S][kWave];
   double adjn[2][kWavesPerBlock][S][kWave];  // collected adjoint, then (once read) the sensitivity lf
 };
 
-template <int NP, int RK, int PHYS>
+template <int NP, int RK, int PHYS, int R>
 __device__ __forceinline__ void adj_tile2(const DevProblem& P, const WorkItem wi, int lane, int32_t n,
                                           const double* __restrict__ lam, double* __restrict__ lamo,
                                           double* __restrict__ adjring, AdjSmem2<rk_stages(RK)>& sm, int wv) {
   constexpr int S = rk_stages(RK);
-  constexpr int HL = 2 * adj_halo(RK, false);
-  constexpr int T = kWave - 2 * HL;
+  constexpr int HL = adj_halo2(RK, R);
+  constexpr int T = adj_tile_elems2(RK, R);
   const int N = (int)P.n_elem;
   const int e0 = wi.tile * T;
   const int teff = (N - e0) < T ? (N - e0) : T;
-  const int x = e0 - HL + lane;
-  const int e = N < kWave ? wrap_elem(x, N) : wrap_once(x, N);
-  const bool owned = lane >= HL && lane < kWave - HL && (x - e0) < teff;
+  const int xb = e0 - R * HL;  // element position of lane 0, element 0
+  const bool lane_owned = lane >= HL && lane < kWave - HL;
+  const bool tiny = N < kWave * R;  // the wave's extent may wrap more than once
+  int e[R];
+  bool owned[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int x = xb + R * lane + r;
+    e[r] = tiny ? wrap_elem(x, N) : wrap_once(x, N);
+    owned[r] = lane_owned && (x - e0) < teff;
+  }
+  // with N a multiple of R a lane's elements never straddle the periodic wrap
+  const bool grouped = R > 1 && (N % R) == 0;
   const int64_t ld = P.ld;
   const double* __restrict__ lp = lam + P.u_off;
-  double lamp[NP];
+  double lamp[R][NP];
+  if (grouped) {
+    const double2* __restrict__ l2 = reinterpret_cast<const double2*>(__builtin_assume_aligned(lp, 16));
 #pragma unroll
-  for (int j = 0; j < NP; ++j) lamp[j] = lp[j * ld + e];
+    for (int j = 0; j < NP; ++j)
+#pragma unroll
+      for (int r = 0; r < R; r += 2) {
+        const double2 v = l2[(j * ld + e[0] + r) >> 1];
+        lamp[r][j] = v.x;
+        lamp[r + 1 < R ? r + 1 : r][j] = R > 1 ? v.y : v.x;
+      }
+  } else {
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int j = 0; j < NP; ++j) lamp[r][j] = lp[j * ld + e[r]];
+  }
 
-  bool pe = false;
+  bool pe[R];
+  bool own_pe = false;  // the lane owns the element right of its PE face
   uint32_t b = 0;
   int depth = 1, slot_n = 0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) pe[r] = false;
   if (P.async_faces) {
     depth = P.depth;
     slot_n = (int)((uint32_t)n - fast_div((uint32_t)n, P.depth_div) * (uint32_t)depth);
-    b = fast_div((uint32_t)e, P.pe_div);
-    pe = (uint32_t)e == b * P.pe_div.d;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const uint32_t br = fast_div((uint32_t)e[r], P.pe_div);
+      pe[r] = (uint32_t)e[r] == br * P.pe_div.d;
+      if (pe[r]) b = br;
+      own_pe = own_pe || (pe[r] && owned[r]);
+    }
   }
+  bool any_pe = false;
+#pragma unroll
+  for (int r = 0; r < R; ++r) any_pe = any_pe || pe[r];
   // delays and collected adjoint of levels n+1 (t = 0) and n (t = 1), one job
   // lane per (PE lane, step, stage)
-  const uint64_t m_pe = __ballot(pe);
+  const uint64_t m_pe = __ballot(any_pe);
   const int n_jobs = 2 * S * __builtin_popcountll(m_pe);
   for (int g0 = 0; g0 < n_jobs; g0 += kWave) {  // uniform
     const int g = g0 + lane;
@@ -429,28 +494,46 @@ __device__ __forceinline__ void adj_tile2(const DevProblem& P, const WorkItem wi
   }
 
   const double keep[S][NP] = {};  // no forward stages: the Jacobian is constant
-  double l1[NP], l0[NP];
+  double l1[R][NP], l0[R][NP];
   // step n + 1: a delay of 1 deposits c_0(1) lf at level n, which step n reads
-  adj_reverse<NP, RK, PHYS, false>(
-      P, lamp, l1, keep, pe, owned, [&](int s) { return (int)sm.kd[0][wv][s][lane]; },
+  adj_reverse<NP, RK, PHYS, false, R>(
+      P, lamp, l1, keep, pe, false, [&](int s) { return (int)sm.kd[0][wv][s][lane]; },
       [&](int s) { return sm.adjn[0][wv][s][lane]; },
       [&](int s, double lf) {
         sm.adjn[0][wv][s][lane] = lf;
         if (sm.kd[0][wv][s][lane] == 1) sm.adjn[1][wv][s][lane] = fma(P.atc[1][0], lf, sm.adjn[1][wv][s][lane]);
       });
-  adj_reverse<NP, RK, PHYS, false>(
-      P, l1, l0, keep, pe, owned, [&](int s) { return (int)sm.kd[1][wv][s][lane]; },
+  adj_reverse<NP, RK, PHYS, false, R>(
+      P, l1, l0, keep, pe, false, [&](int s) { return (int)sm.kd[1][wv][s][lane]; },
       [&](int s) { return sm.adjn[1][wv][s][lane]; }, [&](int s, double lf) { sm.adjn[1][wv][s][lane] = lf; });
 
   double* __restrict__ lo = lamo + P.u_off;
-  if (owned)
+  bool all_owned = true;
 #pragma unroll
-    for (int j = 0; j < NP; ++j) lo[j * ld + e] = l0[j];
+  for (int r = 0; r < R; ++r) all_owned = all_owned && owned[r];
+  if (grouped && all_owned) {
+    double2* __restrict__ lo2 = reinterpret_cast<double2*>(__builtin_assume_aligned(lo, 16));
+#pragma unroll
+    for (int j = 0; j < NP; ++j)
+#pragma unroll
+      for (int r = 0; r < R; r += 2) {
+        double2 v;
+        v.x = l0[r][j];
+        v.y = l0[r + 1 < R ? r + 1 : r][j];
+        lo2[(j * ld + e[0] + r) >> 1] = v;
+      }
+  } else {
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (owned[r])
+#pragma unroll
+        for (int j = 0; j < NP; ++j) lo[j * ld + e[r]] = l0[r][j];
+  }
 
   // levels n - d of each owned PE face and stage that either step reaches:
   // d >= 1 up to (L - 1) + (q - 1), taken at the largest L and q
   constexpr int W = (kMaxL - 1) + (kMaxQ - 1);
-  const uint64_t m_own = __ballot(pe && owned);
+  const uint64_t m_own = __ballot(own_pe);
   const int n_sc = S * W * __builtin_popcountll(m_own);
   for (int g0 = 0; g0 < n_sc; g0 += kWave) {  // uniform
     const int g = g0 + lane;
@@ -472,7 +555,7 @@ __device__ __forceinline__ void adj_tile2(const DevProblem& P, const WorkItem wi
   }
 }
 
-template <int NP, int RK, int PHYS>
+template <int NP, int RK, int PHYS, int R>
 __global__ __launch_bounds__(kBlock) void k_adj_fused2(const DevProblem* __restrict__ probs,
                                                        const WorkItem* __restrict__ work, int32_t w_begin,
                                                        int32_t w_end, const double* __restrict__ lam,
@@ -484,7 +567,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_fused2(const DevProblem* __restr
   if (w >= w_end) return;  // whole wave
   __shared__ AdjSmem2<rk_stages(RK)> sm;
   const WorkItem wi = work[w];
-  adj_tile2<NP, RK, PHYS>(probs[wi.prob], wi, lane, n, lam, lamo, adjring, sm, wv);
+  adj_tile2<NP, RK, PHYS, R>(probs[wi.prob], wi, lane, n, lam, lamo, adjring, sm, wv);
 }
 
 template <int NP, int RK, int PHYS, bool FWD>
@@ -582,7 +665,7 @@ static void adj_fused_rk(int phys, const AdjArgs& a, const double* u, const doub
   }
 }
 
-template <int RK, int PHYS>
+template <int RK, int PHYS, int R>
 static void adj_fused2_go(const AdjArgs& a, const double* lam, double* lamo, double* adjring, int32_t n,
                           hipStream_t st) {
   for (int gi = 0; gi < 4; ++gi) {
@@ -590,28 +673,36 @@ static void adj_fused2_go(const AdjArgs& a, const double* lam, double* lamo, dou
     if (we <= wb) continue;
     const dim3 grid(a.grid[gi]), block(kBlock);
     switch (gi) {
-      case 0: hipLaunchKernelGGL((k_adj_fused2<5, RK, PHYS>), grid, block, 0, st, a.probs, a.work, wb, we, lam, lamo,
-                                 adjring, n); break;
-      case 1: hipLaunchKernelGGL((k_adj_fused2<4, RK, PHYS>), grid, block, 0, st, a.probs, a.work, wb, we, lam, lamo,
-                                 adjring, n); break;
-      case 2: hipLaunchKernelGGL((k_adj_fused2<3, RK, PHYS>), grid, block, 0, st, a.probs, a.work, wb, we, lam, lamo,
-                                 adjring, n); break;
-      default: hipLaunchKernelGGL((k_adj_fused2<2, RK, PHYS>), grid, block, 0, st, a.probs, a.work, wb, we, lam, lamo,
-                                  adjring, n); break;
+      case 0: hipLaunchKernelGGL((k_adj_fused2<5, RK, PHYS, R>), grid, block, 0, st, a.probs, a.work, wb, we, lam,
+                                 lamo, adjring, n); break;
+      case 1: hipLaunchKernelGGL((k_adj_fused2<4, RK, PHYS, R>), grid, block, 0, st, a.probs, a.work, wb, we, lam,
+                                 lamo, adjring, n); break;
+      case 2: hipLaunchKernelGGL((k_adj_fused2<3, RK, PHYS, R>), grid, block, 0, st, a.probs, a.work, wb, we, lam,
+                                 lamo, adjring, n); break;
+      default: hipLaunchKernelGGL((k_adj_fused2<2, RK, PHYS, R>), grid, block, 0, st, a.probs, a.work, wb, we, lam,
+                                  lamo, adjring, n); break;
     }
   }
+}
+
+template <int RK, int PHYS>
+static void adj_fused2_r(const AdjArgs& a, const double* lam, double* lamo, double* adjring, int32_t n,
+                         hipStream_t st) {
+  if (a.lane_elems == 2) adj_fused2_go<RK, PHYS, 2>(a, lam, lamo, adjring, n, st);
+  else adj_fused2_go<RK, PHYS, 1>(a, lam, lamo, adjring, n, st);
 }
 
 template <int RK>
 static void adj_fused2_rk(int phys, const AdjArgs& a, const double* lam, double* lamo, double* adjring, int32_t n,
                           hipStream_t st) {
-  if (phys == PHYS_ADV_CENTRAL) adj_fused2_go<RK, PHYS_ADV_CENTRAL>(a, lam, lamo, adjring, n, st);
-  else adj_fused2_go<RK, PHYS_ADV_UPWIND>(a, lam, lamo, adjring, n, st);
+  if (phys == PHYS_ADV_CENTRAL) adj_fused2_r<RK, PHYS_ADV_CENTRAL>(a, lam, lamo, adjring, n, st);
+  else adj_fused2_r<RK, PHYS_ADV_UPWIND>(a, lam, lamo, adjring, n, st);
 }
 
 hipError_t launch_adj_fused2(int rk, int phys, const AdjArgs& a, const double* lam, double* lamo, double* adjring,
                              int32_t n, hipStream_t stream) {
   if (phys == PHYS_BURGERS_LLF) return hipErrorInvalidValue;  // the Burgers Jacobian needs the forward stages
+  if (a.lane_elems != 1 && a.lane_elems != 2) return hipErrorInvalidValue;
   switch (rk) {
     case RK_HEUN: adj_fused2_rk<RK_HEUN>(phys, a, lam, lamo, adjring, n, stream); break;
     case RK_SSP3: adj_fused2_rk<RK_SSP3>(phys, a, lam, lamo, adjring, n, stream); break;

@@ -305,6 +305,9 @@ bool pe_split_of(const adg_problem* probs, int32_t n, const adg_options* opt) {
 }
 // linear advection can reverse two steps per launch (no forward stages needed)
 bool adj_two_steps(const adg_problem* probs) { return probs[0].equation == ADG_EQ_ADVECTION; }
+// elements per lane of the two-step reverse: the forward's, at most 2 (its
+// reverse stages keep R sets of Butcher accumulators in registers)
+int adj_lane_elems(int lane_elems) { return lane_elems >= 2 ? 2 : 1; }
 
 Layout make_layout(const adg_problem* probs, int32_t n, const adg_options* opt, int64_t n_rec) {
   Layout L{};
@@ -313,7 +316,7 @@ Layout make_layout(const adg_problem* probs, int32_t n, const adg_options* opt, 
   const int T = fused_tile((int)probs[0].rk, R, 1);
   const int T2 = fused_tile((int)probs[0].rk, R, 2);
   const int T1 = adj_tile_elems((int)probs[0].rk, probs[0].equation == ADG_EQ_BURGERS);
-  const int TA2 = adj_tile_elems2((int)probs[0].rk);
+  const int TA2 = adj_tile_elems2((int)probs[0].rk, adj_lane_elems(R));
   int64_t nwf = 0, nwf2 = 0, nws = 0, nwa = 0, nwa2 = 0, tot = 0, ring = 0, at = 0, nww[2] = {0, 0};
   const bool split = pe_split_of(probs, n, opt);
   for (int32_t i = 0; i < n; ++i) {
@@ -460,6 +463,7 @@ struct adg_ctx {
     a.work = (const WorkItem*)(ws + (K == 2 ? L.work_a2 : L.work_a));
     for (int i = 0; i < 5; ++i) a.group[i] = K == 2 ? group_a2[i] : group_a[i];
     for (int i = 0; i < 4; ++i) a.grid[i] = K == 2 ? grid_a2[i] : grid_a[i];
+    a.lane_elems = K == 2 ? adj_lane_elems(lane_elems) : 1;
     return a;
   }
   // copy the fused kernel's PE-face records to / from checkpoint slot k
@@ -858,7 +862,8 @@ int adg_init(adg_ctx** out, const adg_problem* probs, int32_t n_probs, const adg
   };
   if (c->L.work_a >= 0)
     adj_list(adj_tile_elems(c->rk, probs[0].equation == ADG_EQ_BURGERS), c->work_a, c->group_a, c->grid_a);
-  if (c->L.work_a2 >= 0) adj_list(adj_tile_elems2(c->rk), c->work_a2, c->group_a2, c->grid_a2);
+  if (c->L.work_a2 >= 0)
+    adj_list(adj_tile_elems2(c->rk, adj_lane_elems(c->lane_elems)), c->work_a2, c->group_a2, c->grid_a2);
 
   auto up = [&](int64_t off, const void* src, int64_t bytes) -> int {
     ADG_HIP(hipMemcpyAsync(c->ws + off, src, bytes, hipMemcpyHostToDevice, c->stream));

@@ -97,6 +97,7 @@ struct AdjArgs {
   const WorkItem* work;
   int32_t group[5];
   int32_t grid[4];
+  int32_t lane_elems;  // two-step reverse: elements per lane (1 or 2)
 };
 
 // Reverse of the whole RK step n (absolute index) for all problems in one
@@ -108,10 +109,12 @@ hipError_t launch_adj_fused(int rk, int phys, const AdjArgs& a, const double* u,
 
 // Reverse of steps n + 1 and n (absolute indices) for linear advection without
 // the forward states (dJ/du0 only): lamo = lambda^n from lam = lambda^{n+2},
-// halo 2S lanes (work list of adj_tile_elems2 elements per item).
+// R = a.lane_elems consecutive elements per lane, halo of 2S elements per
+// side (work list of adj_tile_elems2(rk, R) elements per item).
 hipError_t launch_adj_fused2(int rk, int phys, const AdjArgs& a, const double* lam, double* lamo, double* adjring,
                              int32_t n, hipStream_t stream);
-__host__ __device__ constexpr int adj_tile_elems2(int rk) { return kWave - 4 * adj_halo(rk, false); }
+__host__ __device__ constexpr int adj_halo2(int rk, int R) { return (2 * adj_halo(rk, false) + R - 1) / R; }
+__host__ __device__ constexpr int adj_tile_elems2(int rk, int R) { return R * (kWave - 2 * adj_halo2(rk, R)); }
 
 // Zero fill of `bytes` bytes at p (8-byte aligned, a multiple of 8).
 hipError_t launch_zero(void* p, int64_t bytes, hipStream_t stream);

@@ -143,8 +143,9 @@ def test_checkpoint_interval_does_not_change_gradient(torch_cuda, kernel):
 def test_fused_adjoint_lane_elems_and_batch(torch_cuda, lane_elems):
     """A batched recording (degrees 1..4, different speeds, meshes and PE
     sizes, forward with R elements per lane) against the oracle problem by
-    problem; the adjoint always runs one element per lane.  dJ/du0 without
-    dJ/da (two reverse steps per launch) is bitwise the same."""
+    problem; the reverse step with dJ/da runs one element per lane.  dJ/du0
+    without dJ/da (two reverse steps per launch, min(R, 2) elements per lane)
+    is bitwise the same."""
     from paper_2404_03399_amd.solver import Solver
     specs = [(1, 90, 15, 1.3, "ssprk3"), (2, 128, 16, 0.7, "ssprk3"), (3, 75, 5, -1.1, "ssprk3"),
              (4, 64, 8, 2.0, "ssprk3")]
@@ -176,6 +177,38 @@ def test_fused_adjoint_lane_elems_and_batch(torch_cuda, lane_elems):
         assert stats.rel_l2(uts[i], ut_o) <= 1e-12
         assert stats.rel_l2(gl[i], g_o) <= 1e-12, (i, stats.rel_l2(gl[i], g_o))
         assert abs(gs[i] - ga_o) <= 1e-12 * max(1.0, abs(ga_o)), (i, gs[i], ga_o)
+
+
+@pytest.mark.parametrize("rk,p,flux,ne,pe", [("rk4", 3, "upwind", 1000, 40), ("lsrk4", 2, "central", 1030, 10),
+                                             ("ssprk3", 4, "upwind", 777, 7), ("heun", 1, "upwind", 2048, 2),
+                                             ("lsrk3", 2, "upwind", 130, 13)])
+def test_two_step_reverse_lane_elems(torch_cuda, rk, p, flux, ne, pe):
+    """The two-step reverse with two elements per lane (tiles of R (64 - 2H)
+    elements, halo H = 2S / R lanes) is bitwise the one-element reverse, over
+    several tiles with a ragged last one, an odd mesh (a lane's two elements
+    straddle the periodic wrap), a PE face every other element, and a mesh
+    shorter than one wave's extent; both match the oracle."""
+    from paper_2404_03399_amd.solver import Solver
+    dt = {1: 0.05, 2: 0.02, 3: 0.005, 4: 0.002}[p] * W.TWO_PI / ne
+    w = W.Workload(name="adj2r", scheme="adg_at", rk=rk, degree=p, n_elem=ne, pe_size=pe, flux=flux,
+                   probs=W.DELAYS_C2, seed=21, dt=dt, speed=0.9, ic=W.PAPER_MULTISINE)
+    u0 = stepper.initial_state(w)
+    ref = np.random.default_rng(5).standard_normal(u0.shape)
+    n = 22
+    _say(f"two-step reverse R=1 vs 2: {rk} p={p} {flux} N={ne} pe={pe} steps={n}")
+    out = {}
+    for R in (1, 2):
+        s = Solver(w, kernel="fused", n_steps_record=n, ckpt_every=5, fused_steps=2, lane_elems=R)
+        u = s.pack(u0)
+        s.run(u, n, graph=True, record=True)
+        cot = s.pack(s.unpack(u)[0] - ref)
+        g, _ = s.adjoint(cot, want_speed=False)
+        torch_cuda.cuda.synchronize()
+        out[R] = s.unpack(g)[0]
+        s.close()
+    assert np.array_equal(out[1], out[2])
+    _, g_o, _ = oadj.gradient(w, u0, n, oadj.misfit_cotangent(ref))
+    assert stats.rel_l2(out[2], g_o) <= 1e-12, stats.rel_l2(out[2], g_o)
 
 
 @pytest.mark.parametrize("kernel", ["fused", "stage"])
