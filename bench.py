@@ -459,6 +459,21 @@ def bench_ensemble(torch, W, Solver, n_steps: int, n_real: int, plain: bool):
                          "async_mean": at[0], "async_var": at[1], "async_linf_mean": at[2],
                          "async_linf_var": at[3]}
                         for g, (st, at) in enumerate(zip(gstats, astats))]}
+    # launch structure: one fused launch per degree range (the library's
+    # default) against one launch over every range (ADG_OPT_ONE_LAUNCH), both
+    # at two elements per lane, two steps per launch and no PE-face split (the
+    # shape the one-launch kernel supports)
+    launches = {}
+    for one in (False, True):
+        so = Solver(ws, lane_elems=2, fused_steps=2, pe_split=False, one_launch=one)
+        uo = u_init.clone()
+        t1, reps1 = timed(so, uo, u_init, 3)
+        launches["one_launch" if one else "per_range"] = {
+            "batched_s": t1, "rep_s": reps1, "advance_us": t1 * 2 / n_steps * 1e6,
+            "launches_per_advance": 1 if one else len({(w.degree, w.flux == "upwind" and w.speed > 0) for w in ws}),
+            "bitwise_equal_to_tuned": bool(torch.equal(uo, u))}
+        so.close()
+    out["launch_structure"] = launches
     if plain:
         # one context per problem, same problems and kernels, each at its own
         # tuned launch shape (context set-up, tuning and graph capture
@@ -478,6 +493,8 @@ def bench_ensemble(torch, W, Solver, n_steps: int, n_real: int, plain: bool):
         out["plain_s"] = total
         out["batched_over_plain"] = total / t_batched
         out["max_abs_diff_batched_vs_plain"] = max_diff
+        for v in launches.values():
+            v["batched_over_plain"] = total / v["batched_s"]
     s.close()
     return out
 

@@ -144,10 +144,19 @@ typedef struct adg_options {
  * used when a wave holds at least two windows of the longest launch and
  * every asynchronous problem's PE size holds four (RK4 with two steps per
  * launch: PE size >= 128); ADG_OPT_PE_SPLIT_OFF never splits,
- * ADG_OPT_PE_SPLIT_ON splits whenever the PE sizes hold one window.  Other
- * bits: ADG_E_INVALID. */
+ * ADG_OPT_PE_SPLIT_ON splits whenever the PE sizes hold one window.  Bits
+ * other than those defined here: ADG_E_INVALID. */
 #define ADG_OPT_PE_SPLIT_OFF 1u
 #define ADG_OPT_PE_SPLIT_ON 2u
+/* ADG_OPT_ONE_LAUNCH: the fused kernel advances every problem of a batch in
+ * one launch per step batch instead of one launch per degree range (Sec. 4.3
+ * ensembles mix degrees): each wave takes its range's tile with the PE-face
+ * paths compiled in, so every range runs at the register footprint of the
+ * degree-4 tile; the results are bitwise those of the per-range launches.
+ * Needs the fused kernel with lane_elems 0 or 2 and no PE-face split
+ * (together with ADG_OPT_PE_SPLIT_ON: ADG_E_INVALID); viscous Burgers:
+ * ADG_E_UNSUPPORTED. */
+#define ADG_OPT_ONE_LAUNCH 4u
 
 typedef struct adg_ctx adg_ctx;  /* opaque, host side, library owned */
 

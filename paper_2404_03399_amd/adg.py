@@ -33,6 +33,7 @@ ADG_SCRATCH_BYTES = 64 << 20
 
 ADG_OPT_PE_SPLIT_OFF = 1
 ADG_OPT_PE_SPLIT_ON = 2
+ADG_OPT_ONE_LAUNCH = 4
 
 ADG_RUN_GRAPH = 1
 ADG_RUN_RECORD = 2

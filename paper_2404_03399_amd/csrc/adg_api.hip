@@ -290,7 +290,8 @@ bool is_ldg(const adg_problem* probs) { return probs[0].equation == ADG_EQ_VISCO
 // slower for the five-stage scheme, whose 40-element window fills a wave).
 bool pe_split_of(const adg_problem* probs, int32_t n, const adg_options* opt) {
   const uint32_t f = opt ? opt->flags : 0u;
-  if ((f & ADG_OPT_PE_SPLIT_OFF) || kernel_of(probs, opt) != ADG_KERNEL_FUSED || is_ldg(probs)) return false;
+  if ((f & (ADG_OPT_PE_SPLIT_OFF | ADG_OPT_ONE_LAUNCH)) || kernel_of(probs, opt) != ADG_KERNEL_FUSED || is_ldg(probs))
+    return false;
   const int K = fused_steps_of(opt) == 1 ? 1 : 2;
   const bool force = (f & ADG_OPT_PE_SPLIT_ON) != 0;
   if (!force && fused_windows_per_wave((int)probs[0].rk, K) < 2) return false;
@@ -425,6 +426,7 @@ struct adg_ctx {
   int32_t group[2][kFusedRanges + 1] = {};  // fused work lists, 1 and 2 steps per launch
   int32_t grid[2][kFusedRanges] = {};
   int32_t single[2][kFusedRanges] = {};
+  int32_t one_launch = 0;  // ADG_OPT_ONE_LAUNCH
   int32_t mode[2][kFusedRanges] = {};       // fused_mode of each range of those lists
   bool split = false;                       // PE-face split in use
   int32_t lane_elems = 2;
@@ -448,6 +450,7 @@ struct adg_ctx {
     for (int i = 0; i < kFusedRanges; ++i) a.single[i] = single[K - 1][i];
     for (int i = 0; i < kFusedRanges; ++i) a.mode[i] = mode[K - 1][i];
     a.lane_elems = lane_elems;
+    a.one_launch = one_launch;
     a.steps = K;
     a.qbuf = L.qbuf >= 0 ? (double*)(ws + L.qbuf) : nullptr;
     return a;
@@ -672,10 +675,15 @@ int adg_workspace_size(const adg_problem* probs, int32_t n_probs, const adg_opti
   if (lane_elems_of(probs, n_probs, opt) == 0)
     return fail(ADG_E_INVALID, "lane_elems must be 1, 2 or 4 and not exceed the PE size");
   if (fused_steps_of(opt) == 0) return fail(ADG_E_INVALID, "fused_steps must be 0, 1 or 2");
-  if (opt && (opt->flags & ~(ADG_OPT_PE_SPLIT_OFF | ADG_OPT_PE_SPLIT_ON)))
+  if (opt && (opt->flags & ~(ADG_OPT_PE_SPLIT_OFF | ADG_OPT_PE_SPLIT_ON | ADG_OPT_ONE_LAUNCH)))
     return fail(ADG_E_INVALID, "unknown adg_options.flags bits");
   if (opt && (opt->flags & ADG_OPT_PE_SPLIT_OFF) && (opt->flags & ADG_OPT_PE_SPLIT_ON))
     return fail(ADG_E_INVALID, "ADG_OPT_PE_SPLIT_OFF and ADG_OPT_PE_SPLIT_ON together");
+  if (opt && (opt->flags & ADG_OPT_ONE_LAUNCH)) {
+    if ((opt->flags & ADG_OPT_PE_SPLIT_ON) || k != ADG_KERNEL_FUSED || lane_elems_of(probs, n_probs, opt) != 2)
+      return fail(ADG_E_INVALID, "ADG_OPT_ONE_LAUNCH needs the fused kernel, two elements per lane and no PE-face split");
+    if (is_ldg(probs)) return fail(ADG_E_UNSUPPORTED, "ADG_OPT_ONE_LAUNCH: the local DG kernel launches per range");
+  }
   if (is_ldg(probs) && k == ADG_KERNEL_FUSED && opt && opt->lane_elems > 1)
     return fail(ADG_E_UNSUPPORTED, "the fused local DG kernel runs one element per lane");
   if (is_ldg(probs) && n_steps_record > 0)
@@ -789,6 +797,7 @@ int adg_init(adg_ctx** out, const adg_problem* probs, int32_t n_probs, const adg
   // element; ranges without asynchronous problems take the kernel with the
   // PE-face paths compiled out
   c->split = pe_split_of(probs, n_probs, opt);
+  c->one_launch = (opt && (opt->flags & ADG_OPT_ONE_LAUNCH)) ? 1 : 0;
   for (int K = 1; K <= 2; ++K) {
     const int T = fused_tile(c->rk, c->lane_elems, K);
     const int fw = fused_windows_per_wave(c->rk, K);

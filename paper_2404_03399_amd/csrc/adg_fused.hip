@@ -386,6 +386,58 @@ __global__ __launch_bounds__(kBlock) void k_fused_step(const DevProblem* __restr
   }
 }
 
+// One launch over every degree range (ADG_OPT_ONE_LAUNCH): wave w finds its
+// range from the range table (ranges are contiguous in the work list, in the
+// order of the per-range launches) and runs that range's tile with every
+// PE-face path compiled in, as a FUSED_FULL range does.  A kernel's registers
+// are those of its largest body, so every range runs at the occupancy of the
+// degree-4 tile; one launch per range (the default) lets each degree keep its
+// own.  The per-element arithmetic is that of the per-range kernels: the
+// results are bitwise the same.
+struct FusedRangeTable {
+  int32_t group[kFusedRanges + 1];
+};
+
+template <int RK, int PHYS, int R, int K>
+__global__ __launch_bounds__(kBlock) void k_fused_all(const DevProblem* __restrict__ probs,
+                                                      const WorkItem* __restrict__ work,
+                                                      const int64_t* __restrict__ ctr, double* __restrict__ ring,
+                                                      double* __restrict__ atsum, RecWord* __restrict__ atk,
+                                                      const FusedRangeTable rt, const double* __restrict__ uin,
+                                                      double* __restrict__ uout, double* __restrict__ umid,
+                                                      int32_t step_offset) {
+  __shared__ WaveSmemK<K, rk_stages(RK)> sm;
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+  const int lane = (int)(threadIdx.x % kWave);
+  const int w = xcd_block((int)blockIdx.x, (int)gridDim.x) * kWavesPerBlock + wv;
+  if (w >= rt.group[kFusedRanges]) return;  // whole wave
+  const int64_t n = ctr[0] + step_offset;
+  const FusedPtrs A{ring, atsum, atk};
+  const WorkItem wi = work[w];
+  const DevProblem& P = probs[wi.prob];
+  int gi = 0;  // uniform
+#pragma unroll
+  for (int g = 1; g < kFusedRanges; ++g) gi += w >= rt.group[g] ? 1 : 0;
+  // even ranges hold the a > 0 upwind form, which exists for upwind advection only
+  constexpr bool kPos = PHYS == PHYS_ADV_UPWIND;
+  constexpr int PH0 = kPos ? PHYS_ADV_UPWIND_POS : PHYS;
+  if (kPos && (gi & 1) == 0) {
+    switch (gi) {
+      case 0: wave_tile<5, RK, PH0, R, K, TILE_FULL>(P, wi, A, n, uin, uout, umid, sm, wv, lane); break;
+      case 2: wave_tile<4, RK, PH0, R, K, TILE_FULL>(P, wi, A, n, uin, uout, umid, sm, wv, lane); break;
+      case 4: wave_tile<3, RK, PH0, R, K, TILE_FULL>(P, wi, A, n, uin, uout, umid, sm, wv, lane); break;
+      default: wave_tile<2, RK, PH0, R, K, TILE_FULL>(P, wi, A, n, uin, uout, umid, sm, wv, lane); break;
+    }
+  } else {
+    switch (gi / 2) {
+      case 0: wave_tile<5, RK, PHYS, R, K, TILE_FULL>(P, wi, A, n, uin, uout, umid, sm, wv, lane); break;
+      case 1: wave_tile<4, RK, PHYS, R, K, TILE_FULL>(P, wi, A, n, uin, uout, umid, sm, wv, lane); break;
+      case 2: wave_tile<3, RK, PHYS, R, K, TILE_FULL>(P, wi, A, n, uin, uout, umid, sm, wv, lane); break;
+      default: wave_tile<2, RK, PHYS, R, K, TILE_FULL>(P, wi, A, n, uin, uout, umid, sm, wv, lane); break;
+    }
+  }
+}
+
 // Viscous Burgers in local DG form (Sec. 7): K in {1, 2} time steps per
 // launch, one element per lane, halo K S lanes per side.  Per stage: u-hat at
 // a face is the trace of the element on its left (alternating flux); q = Kr
@@ -657,9 +709,32 @@ static void fused_phys(int phys, const StepArgs& a, const double* uin, double* u
   }
 }
 
+// ADG_OPT_ONE_LAUNCH: one launch over every range (two elements per lane).
+template <int RK, int PHYS>
+static void fused_all_go(const StepArgs& a, const double* uin, double* uout, int32_t off, hipStream_t st) {
+  FusedRangeTable rt;
+  for (int i = 0; i <= kFusedRanges; ++i) rt.group[i] = a.group[i];
+  const dim3 g(fused_grid(a.group[kFusedRanges])), b(kBlock);
+  if (a.steps == 2)
+    hipLaunchKernelGGL((k_fused_all<RK, PHYS, 2, 2>), g, b, 0, st, a.probs, a.work, a.ctr, a.ring, a.atsum, a.atk, rt,
+                       uin, uout, a.umid, off);
+  else
+    hipLaunchKernelGGL((k_fused_all<RK, PHYS, 2, 1>), g, b, 0, st, a.probs, a.work, a.ctr, a.ring, a.atsum, a.atk, rt,
+                       uin, uout, nullptr, off);
+}
+
 template <int RK>
 hipError_t launch_fused_rk(int phys, const StepArgs& a, const double* uin, double* uout, int32_t step_offset,
                            hipStream_t stream) {
+  if (a.one_launch) {
+    if (a.lane_elems != 2 || phys == PHYS_BURGERS_LDG) return hipErrorInvalidValue;
+    switch (phys) {
+      case PHYS_ADV_UPWIND: fused_all_go<RK, PHYS_ADV_UPWIND>(a, uin, uout, step_offset, stream); break;
+      case PHYS_ADV_CENTRAL: fused_all_go<RK, PHYS_ADV_CENTRAL>(a, uin, uout, step_offset, stream); break;
+      default: fused_all_go<RK, PHYS_BURGERS_LLF>(a, uin, uout, step_offset, stream); break;
+    }
+    return hipGetLastError();
+  }
   fused_phys<RK>(phys, a, uin, uout, step_offset, stream);
   return hipGetLastError();
 }

@@ -23,6 +23,8 @@ struct StepArgs {
                              // the first step here (state layout), or null
   int32_t mode[8];           // fused kernel: fused_mode of each range (FUSED_SPLIT ranges mark
                              // their window items by tile index -(window group + 1))
+  int32_t one_launch;        // fused kernel: one launch over every range (two elements per lane,
+                             // every range FUSED_FULL), else one launch per range
 };
 
 // Work items of the fused kernel are sorted by descending np and, within a

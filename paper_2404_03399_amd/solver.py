@@ -65,11 +65,12 @@ class Solver:
 
     def __init__(self, workloads, kernel: str = "auto", n_steps_record: int = 0, ckpt_every: int = 0,
                  device: str = "cuda", stream=None, lane_elems=0, fused_steps: int = 0, scratch: bool = False,
-                 pe_split=None):
+                 pe_split=None, one_launch: bool = False):
         """scratch: take the library's static device workspace (adg_init_scratch)
         instead of allocating one; no recording horizon.  pe_split: None for
         the library's choice, True / False to force the fused kernel's
-        PE-face split on (where the PE sizes allow it) or off."""
+        PE-face split on (where the PE sizes allow it) or off.  one_launch:
+        one fused launch over every degree range (ADG_OPT_ONE_LAUNCH)."""
         if not isinstance(workloads, (list, tuple)):
             workloads = [workloads]
         self.workloads = list(workloads)
@@ -90,6 +91,8 @@ class Solver:
         self.opt.fused_steps = int(fused_steps)
         if pe_split is not None:
             self.opt.flags = adg.ADG_OPT_PE_SPLIT_ON if pe_split else adg.ADG_OPT_PE_SPLIT_OFF
+        if one_launch:
+            self.opt.flags |= adg.ADG_OPT_ONE_LAUNCH
         self.ws_bytes = adg.adg_workspace_size(self.probs, self.opt, n_steps_record)
         self.stream = stream
         if scratch:

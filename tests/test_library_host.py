@@ -332,8 +332,10 @@ def test_scratch_init_rejects_oversized_problems(L):
 
 def test_option_flags_validated(L):
     """adg_options.flags: the two PE-face split bits are accepted alone and
-    refused together; any other bit is refused; the split adds the window
-    work lists to the workspace."""
+    refused together; the one-launch bit needs the fused kernel, two elements
+    per lane and no forced split, and is refused for the local DG kernel; any
+    other bit is refused; the split adds the window work lists to the
+    workspace."""
     p = solver.to_problem(W.c2_advection_large("adg_at", n_elem=1 << 16))
     base = adg.adg_workspace_size([p], adg.adg_options())
     for f in (adg.ADG_OPT_PE_SPLIT_OFF, adg.ADG_OPT_PE_SPLIT_ON):
@@ -343,12 +345,28 @@ def test_option_flags_validated(L):
     off = adg.adg_options()
     off.flags = adg.ADG_OPT_PE_SPLIT_OFF
     assert adg.adg_workspace_size([p], off) < base  # PE size 256 splits by default
-    for f in (adg.ADG_OPT_PE_SPLIT_OFF | adg.ADG_OPT_PE_SPLIT_ON, 4, 1 << 31):
+    for f in (adg.ADG_OPT_PE_SPLIT_OFF | adg.ADG_OPT_PE_SPLIT_ON, 8, 1 << 31,
+              adg.ADG_OPT_ONE_LAUNCH | adg.ADG_OPT_PE_SPLIT_ON):
         opt = adg.adg_options()
         opt.flags = f
         with pytest.raises(adg.AdgError) as ei:
             adg.adg_workspace_size([p], opt)
         assert ei.value.code == adg.ADG_E_INVALID
+    one = adg.adg_options()
+    for f in (adg.ADG_OPT_ONE_LAUNCH, adg.ADG_OPT_ONE_LAUNCH | adg.ADG_OPT_PE_SPLIT_OFF):
+        one.flags = f
+        for lane_elems in (0, 2):
+            one.lane_elems = lane_elems
+            assert adg.adg_workspace_size([p], one) == adg.adg_workspace_size([p], off)  # never split
+    for lane_elems, kernel in ((1, 0), (4, 0), (2, adg.KERNEL["stage"])):
+        one.lane_elems, one.kernel = lane_elems, kernel
+        with pytest.raises(adg.AdgError) as ei:
+            adg.adg_workspace_size([p], one)
+        assert ei.value.code == adg.ADG_E_INVALID
+    one.lane_elems, one.kernel = 0, 0
+    with pytest.raises(adg.AdgError) as ei:  # the local DG kernel runs one element per lane
+        adg.adg_workspace_size([solver.to_problem(W.viscous_burgers_workload(1024))], one)
+    assert ei.value.code in (adg.ADG_E_INVALID, adg.ADG_E_UNSUPPORTED)
 
 
 def test_autotune_candidates_include_the_pe_split():
