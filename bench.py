@@ -65,8 +65,8 @@ def ring_bytes_per_step(w) -> float:
 def read_traffic(lane_elems: int, steps_per_launch: int, n_elem: int = 1 << 20, profile: str = ""):
     """HBM bytes per launch (or per advance of an ensemble) from a committed
     rocprofv3 PMC summary (by default the one of the single-problem mesh
-    size), if it was taken on the current kernel source and the same launch
-    shape."""
+    size), if it was taken on the current kernel source and holds a line for
+    this launch shape."""
     tag = {1 << 20: "2p20", 1 << 24: "2p24"}.get(n_elem)
     name = profile or (f"pmc_fused_step_advection_{tag}.md" if tag else "")
     path = os.path.join(ROOT, "profiles", name)
@@ -74,13 +74,13 @@ def read_traffic(lane_elems: int, steps_per_launch: int, n_elem: int = 1 << 20, 
         return None
     text = open(path).read()
     m = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", text)
-    t = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
-    shape = re.search(r"launch_shape:\s*R=(\d+)\s+K=(\d+)", text)
-    if not m or not t or not shape or m.group(1) != kernel_source_hash():
+    if not m or m.group(1) != kernel_source_hash():
         return None
-    if (int(shape.group(1)), int(shape.group(2))) != (lane_elems, steps_per_launch):
-        return None
-    return float(t.group(1))
+    # one line per measured launch shape
+    for t in re.finditer(r"traffic_bytes_per_launch R=(\d+) K=(\d+):\s*([0-9.eE+]+)", text):
+        if (int(t.group(1)), int(t.group(2))) == (lane_elems, steps_per_launch):
+            return float(t.group(3))
+    return None
 
 
 def time_solver(torch, solver, u, steps, warmup, graph=True, reps=5):
@@ -200,7 +200,7 @@ def _timed_adjoint(torch, s, n_steps, cot_of):
     return g, ga[0], t_fwd, time.perf_counter() - t0
 
 
-def bench_adjoint(torch, W, Solver, n_steps: int, n_elem: int, stage: bool):
+def bench_adjoint(torch, W, Solver, n_steps: int, n_elem: int, stage: bool, large: bool = True):
     """Recorded forward + discrete adjoint of the misfit J = 1/2 ||u(T) - u_ref||^2
     against the exact solution for a speed 1% larger, u_ref = u0(x - 1.01 a T)
     (linear advection, ADG-AT, p=3, RK4, checkpoint every 64 steps): fused
@@ -256,6 +256,55 @@ def bench_adjoint(torch, W, Solver, n_steps: int, n_elem: int, stage: bool):
                                 "dJ_da": ga2}
         s.close()
     out["burgers"] = bench_adjoint_burgers(torch, W, Solver, stage)
+    out["roofline"] = adjoint_roofline(torch, W, Solver, n_elem)
+    if large:
+        out["roofline_large"] = adjoint_roofline(torch, W, Solver, 1 << 24)
+    return out
+
+
+def adjoint_roofline(torch, W, Solver, n_elem: int, n1: int = 64, n2: int = 128):
+    """HBM fractions of the two reverse kernels on the headline problem at
+    n_elem elements (linear advection ADG-AT, p = 3, RK4).  Two recordings of
+    n1 and n2 steps; each adjoint call is timed with HIP events on the
+    solver's stream (median of three), and the difference of the two calls
+    per reverse launch drops the per-call copies and fills.  dJ/du0 only:
+    k_adj_fused2, two reverse steps per launch, reads lambda^{n+2} and writes
+    lambda^n (16 B per DOF); with dJ/da: k_adj_fused with the forward stages
+    recomputed in registers, every state kept (checkpoint interval 1, so no
+    segment is recomputed), reads u^n and lambda^{n+1} and writes lambda^n
+    (24 B per DOF)."""
+    dofs = n_elem * 4
+    out = {"n_elem": n_elem}
+    for key, want, ckpt, per, bytes_dof, kern in (
+            ("two_step_reverse", False, 64, 2, 16, "k_adj_fused2<p=3, rk4, upwind, two steps, R=2>"),
+            ("one_step_reverse_with_speed", True, 1, 1, 24, "k_adj_fused<p=3, rk4, upwind, forward stages kept>")):
+        ts = {}
+        for n in (n1, n2):
+            w = W.c5_adjoint_advection(n_elem=n_elem, n_steps=n)
+            s = Solver(w, n_steps_record=n, ckpt_every=ckpt)
+            u = s.initial_state()
+            s.run(u, n, graph=True, record=True)
+            stream = s.stream if s.stream is not None else torch.cuda.current_stream()
+            reps = []
+            for _ in range(3):
+                torch.cuda.synchronize()
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                g, _ = s.adjoint(u, want_speed=want)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                reps.append(e0.elapsed_time(e1) / 1e3)
+            ts[n] = statistics.median(reps)
+            s.close()
+            del u, g
+            torch.cuda.empty_cache()
+        launch = (ts[n2] - ts[n1]) / ((n2 - n1) / per)
+        alg = bytes_dof * dofs
+        ach = alg / launch / 1e9
+        out[key] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                    "kernel": kern, "launch_us": launch * 1e6, "alg_bytes_per_launch": alg,
+                    "adjoint_call_s": {str(n1): ts[n1], str(n2): ts[n2]}}
     return out
 
 
@@ -382,14 +431,14 @@ def bench_viscous_burgers(torch, W, Solver, n_elem: int = 1 << 20, steps: int = 
     return out
 
 
-def bench_ensemble(torch, W, Solver, n_steps: int, n_real: int, plain: bool):
+def bench_ensemble(torch, W, Solver, n_steps: int, n_real: int, plain: bool, lane_elems: int = -1):
     """Batched ensemble (12 meshes x n_real delay realizations, one context,
     one launch per degree per step) against one context per problem."""
     ws = W.c4_ensemble(n_real=n_real, n_steps=n_steps)
     group = [int(w.name.split("_")[1][1:]) for w in ws]
     dofs = sum(w.n_elem * (w.degree + 1) for w in ws)
-    s = Solver(ws, lane_elems="auto")
-    R, K = s.opt.lane_elems or 1, s.opt.fused_steps or 2
+    s = Solver(ws, lane_elems="auto") if lane_elems < 0 else Solver(ws, lane_elems=lane_elems, fused_steps=2)
+    R, K = s.opt.lane_elems or 2, s.opt.fused_steps or 2
 
     def timed(sv, uu, init, reps):
         # the step graph is captured on this buffer first; every rep restarts
@@ -558,6 +607,8 @@ def main():
     ap.add_argument("--large-steps", type=int, default=64)
     ap.add_argument("--adjoint-steps", type=int, default=2000)
     ap.add_argument("--ensemble-real", type=int, default=256)
+    ap.add_argument("--ensemble-lane-elems", type=int, default=-1,
+                    help="ensemble: elements per lane with two steps per launch (default: autotuned)")
     ap.add_argument("--ensemble-steps", type=int, default=500)
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true")
@@ -663,10 +714,10 @@ def main():
         out["calib_copy_bytes_each_way"] = n * 8
     if not args.no_adjoint:
         out["adjoint"] = bench_adjoint(torch, W, Solver, args.adjoint_steps, args.n_elem,
-                                       not args.no_adjoint_stage)
+                                       not args.no_adjoint_stage, not args.no_large)
     if not args.no_ensemble:
         out["ensemble"] = bench_ensemble(torch, W, Solver, args.ensemble_steps, args.ensemble_real,
-                                         not args.no_plain)
+                                         not args.no_plain, args.ensemble_lane_elems)
     if not args.no_experiments:
         if not args.no_scaling:
             out["experiments"] = bench_experiments()
