@@ -151,9 +151,9 @@ def draw_batch(case: int):
     return ws, n, R, K, graph
 
 
-def _run(torch, w, u0, n, R, K, graph, kernel="fused"):
+def _run(torch, w, u0, n, R, K, graph, kernel="fused", one_launch=False):
     from paper_2404_03399_amd.solver import Solver
-    s = Solver(w, kernel=kernel, lane_elems=R, fused_steps=K)
+    s = Solver(w, kernel=kernel, lane_elems=R, fused_steps=K, one_launch=one_launch)
     u = s.pack(u0)
     s.run(u, n, graph=graph)
     torch.cuda.synchronize()
@@ -286,7 +286,8 @@ N_BATCH = 80
 @pytest.mark.parametrize("case", range(N_BATCH))
 def test_random_batch_matches_single_runs(torch_cuda, case):
     """A context over several different problems advances each exactly as a
-    context of its own would (bitwise), at any launch shape."""
+    context of its own would (bitwise), at any launch shape; with two
+    elements per lane also in one launch over every degree range."""
     ws, n, R, K, graph = draw_batch(case)
     _say(f"random batch {case}: {len(ws)} x {ws[0].equation} {ws[0].flux} {ws[0].scheme} {ws[0].rk}, "
          f"p={[w.degree for w in ws]} N={[w.n_elem for w in ws]} pe={[w.pe_size for w in ws]} "
@@ -295,6 +296,10 @@ def test_random_batch_matches_single_runs(torch_cuda, case):
     outs = _run(torch_cuda, ws, u0s, n, R, K, graph)
     for w, u0, got in zip(ws, u0s, outs):
         assert same(got, _run(torch_cuda, w, u0, n, 1, 1, False)), w.name
+    if R == 2 and ws[0].equation != "viscous_burgers":
+        one = _run(torch_cuda, ws, u0s, n, 2, K, not graph, one_launch=True)
+        for w, a, b in zip(ws, outs, one):
+            assert same(a, b), w.name
 
 
 N_ADJ = 100
