@@ -195,6 +195,14 @@ __device__ __forceinline__ void rk_update(int s, double dt, const double (&u0)[N
   }
 }
 
+// Raw buffer resource over the planes of one problem (gfx9 descriptor: base
+// address, no stride, byte range 2^31 - 1, dword 3 = 0x00020000 for untyped
+// loads and stores); accesses pass the lane's byte offset and the plane's.
+typedef unsigned int BufWord4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const double* p) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(p), 0, 0x7fffffff, 0x00020000);
+}
+
 // Element index of virtual position x on the periodic mesh of N elements.
 __device__ __forceinline__ int wrap_elem(int x, int N) {
   while (x < 0) x += N;

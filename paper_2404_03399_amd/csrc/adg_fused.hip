@@ -102,15 +102,22 @@ __device__ __forceinline__ void wave_tile(const DevProblem& P, const WorkItem wi
     }
   }
   double u0[R][NP];
-  if (grouped) {
-    const double2* __restrict__ u2 = reinterpret_cast<const double2*>(__builtin_assume_aligned(u, 16));
+  // A grouped lane reads and writes its R elements of every plane as 16-byte
+  // pieces through a buffer resource: the lane's byte offset sits in one
+  // VGPR and each plane's offset in an SGPR, so no 64-bit address is formed
+  // per plane (the problem's planes must span less than 2 GiB).
+  const bool buffered = R > 1 && grouped && (int64_t)P.np * ld < (int64_t)1 << 28;
+  const int voff = e[0] * 8;
+  if (buffered) {
+    const __amdgpu_buffer_rsrc_t rs = plane_rsrc(u);
 #pragma unroll
     for (int j = 0; j < NP; ++j)
 #pragma unroll
       for (int r = 0; r < R; r += 2) {
-        const double2 v = u2[(j * ld + e[0] + r) >> 1];
+        const double2 v = __builtin_bit_cast(double2,
+                                             __builtin_amdgcn_raw_buffer_load_b128(rs, voff + 8 * r, (int)(8 * j * ld), 0));
         u0[r][j] = v.x;
-        u0[r + 1 < R ? r + 1 : r][j] = R > 1 ? v.y : v.x;
+        u0[r + 1 < R ? r + 1 : r][j] = v.y;  // R >= 2 here
       }
   } else {
 #pragma unroll
@@ -210,8 +217,8 @@ __device__ __forceinline__ void wave_tile(const DevProblem& P, const WorkItem wi
   double y[R][NP], ks[R][NP], k[NP];
   auto store = [&](double* __restrict__ dst) {
     double* __restrict__ uo = dst + P.u_off;
-    if (grouped && all_owned) {
-      double2* __restrict__ uo2 = reinterpret_cast<double2*>(__builtin_assume_aligned(uo, 16));
+    if (buffered && all_owned) {
+      const __amdgpu_buffer_rsrc_t rs = plane_rsrc(uo);
 #pragma unroll
       for (int j = 0; j < NP; ++j)
 #pragma unroll
@@ -219,7 +226,7 @@ __device__ __forceinline__ void wave_tile(const DevProblem& P, const WorkItem wi
           double2 v;
           v.x = y[r][j];
           v.y = y[r + 1 < R ? r + 1 : r][j];
-          uo2[(j * ld + e[0] + r) >> 1] = v;
+          __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(BufWord4, v), rs, voff + 8 * r, (int)(8 * j * ld), 0);
         }
     } else {
 #pragma unroll
