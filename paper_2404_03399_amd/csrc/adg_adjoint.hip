@@ -294,10 +294,25 @@ __device__ __forceinline__ void adj_tile(const DevProblem& P, const WorkItem wi,
   const int64_t ld = P.ld;
   const double* __restrict__ lp = lam + P.u_off;
   double u0[NP], lamp[1][NP];
+  // plane accesses through buffer resources (lane byte offset in a VGPR, the
+  // plane's in an SGPR) where the problem's planes span less than 2 GiB
+  const bool buffered = (int64_t)P.np * ld < (int64_t)1 << 28;
+  const int voff = e * 8;
+  if (buffered) {
+    const __amdgpu_buffer_rsrc_t rl = plane_rsrc(lp);
 #pragma unroll
-  for (int j = 0; j < NP; ++j) {
-    if constexpr (FWD) u0[j] = uin[P.u_off + j * ld + e];
-    lamp[0][j] = lp[j * ld + e];
+    for (int j = 0; j < NP; ++j) {
+      if constexpr (FWD)
+        u0[j] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(plane_rsrc(uin + P.u_off), voff,
+                                                                                (int)(8 * j * ld), 0));
+      lamp[0][j] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rl, voff, (int)(8 * j * ld), 0));
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+      if constexpr (FWD) u0[j] = uin[P.u_off + j * ld + e];
+      lamp[0][j] = lp[j * ld + e];
+    }
   }
 
   // PE face on this lane's left face.  Its delays of step n, the applied AT
@@ -361,9 +376,17 @@ __device__ __forceinline__ void adj_tile(const DevProblem& P, const WorkItem wi,
       [&](int s) { return sm.adjn[wv][s][lane]; }, [&](int s, double lf) { sm.adjn[wv][s][lane] = lf; });
 
   double* __restrict__ lo = lamo + P.u_off;
-  if (owned)
+  if (owned) {
+    if (buffered) {
+      const __amdgpu_buffer_rsrc_t ro = plane_rsrc(lo);
 #pragma unroll
-    for (int j = 0; j < NP; ++j) lo[j * ld + e] = lu[0][j];
+      for (int j = 0; j < NP; ++j)
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(BufWord2, lu[0][j]), ro, voff, (int)(8 * j * ld), 0);
+    } else {
+#pragma unroll
+      for (int j = 0; j < NP; ++j) lo[j * ld + e] = lu[0][j];
+    }
+  }
 
   // the delayed levels' share of the AT sensitivities into the adjoint ring
   // (levels below n, which nothing in this launch reads), one job lane per
@@ -438,15 +461,20 @@ __device__ __forceinline__ void adj_tile2(const DevProblem& P, const WorkItem wi
   const int64_t ld = P.ld;
   const double* __restrict__ lp = lam + P.u_off;
   double lamp[R][NP];
-  if (grouped) {
-    const double2* __restrict__ l2 = reinterpret_cast<const double2*>(__builtin_assume_aligned(lp, 16));
+  // a grouped lane's planes as 16-byte pieces through a buffer resource (the
+  // problem's planes must span less than 2 GiB)
+  const bool buffered = grouped && (int64_t)P.np * ld < (int64_t)1 << 28;
+  const int voff = e[0] * 8;
+  if (buffered) {
+    const __amdgpu_buffer_rsrc_t rl = plane_rsrc(lp);
 #pragma unroll
     for (int j = 0; j < NP; ++j)
 #pragma unroll
       for (int r = 0; r < R; r += 2) {
-        const double2 v = l2[(j * ld + e[0] + r) >> 1];
+        const double2 v = __builtin_bit_cast(double2,
+                                             __builtin_amdgcn_raw_buffer_load_b128(rl, voff + 8 * r, (int)(8 * j * ld), 0));
         lamp[r][j] = v.x;
-        lamp[r + 1 < R ? r + 1 : r][j] = R > 1 ? v.y : v.x;
+        lamp[r + 1 < R ? r + 1 : r][j] = v.y;  // R >= 2 here
       }
   } else {
 #pragma unroll
@@ -511,8 +539,8 @@ __device__ __forceinline__ void adj_tile2(const DevProblem& P, const WorkItem wi
   bool all_owned = true;
 #pragma unroll
   for (int r = 0; r < R; ++r) all_owned = all_owned && owned[r];
-  if (grouped && all_owned) {
-    double2* __restrict__ lo2 = reinterpret_cast<double2*>(__builtin_assume_aligned(lo, 16));
+  if (buffered && all_owned) {
+    const __amdgpu_buffer_rsrc_t ro = plane_rsrc(lo);
 #pragma unroll
     for (int j = 0; j < NP; ++j)
 #pragma unroll
@@ -520,7 +548,7 @@ __device__ __forceinline__ void adj_tile2(const DevProblem& P, const WorkItem wi
         double2 v;
         v.x = l0[r][j];
         v.y = l0[r + 1 < R ? r + 1 : r][j];
-        lo2[(j * ld + e[0] + r) >> 1] = v;
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(BufWord4, v), ro, voff + 8 * r, (int)(8 * j * ld), 0);
       }
   } else {
 #pragma unroll

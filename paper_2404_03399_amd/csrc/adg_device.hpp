@@ -199,6 +199,7 @@ __device__ __forceinline__ void rk_update(int s, double dt, const double (&u0)[N
 // address, no stride, byte range 2^31 - 1, dword 3 = 0x00020000 for untyped
 // loads and stores); accesses pass the lane's byte offset and the plane's.
 typedef unsigned int BufWord4 __attribute__((ext_vector_type(4)));
+typedef unsigned int BufWord2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const double* p) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(p), 0, 0x7fffffff, 0x00020000);
 }
