@@ -332,6 +332,36 @@ def test_full_size_dot_product_and_speed_fd(torch_cuda):
     s.close()
 
 
+def test_adjoint_past_2gib_planes(torch_cuda):
+    """2^26 elements, p=3 (planes of one state span 2 GiB, so every kernel
+    takes its 64-bit-address path instead of the buffer resources): the
+    dot-product identity <G v, c> = <v, G^T c> for the one-step and the
+    two-step reverse, and both give bitwise the same dJ/du0."""
+    torch = torch_cuda
+    from paper_2404_03399_amd.solver import Solver
+    w = W.c5_adjoint_advection(n_elem=1 << 26, n_steps=6)
+    n = 6
+    assert (w.degree + 1) * w.n_elem * 8 >= 1 << 31
+    _say("adjoint past 2 GiB planes, N=2^26, 6 steps, one- and two-step reverse")
+    out = {}
+    for K in (1, 2):
+        s = Solver(w, n_steps_record=n, ckpt_every=3, fused_steps=K)
+        v = s.initial_state()
+        c = torch.sin(3.0 * v) + 0.25
+        u = v.clone()
+        s.run(u, n, graph=False, record=True)
+        gtc, _ = s.adjoint(c, want_speed=False)
+        torch.cuda.synchronize()
+        lhs = float((u * c).sum())
+        rhs = float((v * gtc).sum())
+        assert abs(lhs - rhs) <= 1e-11 * max(1.0, abs(lhs)), (K, lhs, rhs)
+        out[K] = gtc.clone()
+        s.close()
+        del v, c, u, gtc
+        torch.cuda.empty_cache()
+    assert torch.equal(out[1], out[2])
+
+
 def test_burgers_gradient_against_central_difference(torch_cuda):
     """Burgers (p=2, LLF, ADG-AT q=3, SSP-RK3) on 2^10 elements over 100
     steps, checkpoint every 16: <dJ/du0, v> against a central difference of
