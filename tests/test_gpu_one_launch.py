@@ -87,3 +87,29 @@ def test_one_launch_single_step_launches(torch_cuda):
     per = _run(torch_cuda, ws, u0s, n, False, True, K=2)
     for w, a, b in zip(ws, one, per):
         assert np.array_equal(a, b), w.name
+
+
+def test_one_launch_adjoint_bitwise(torch_cuda):
+    """The adjoint's checkpoint segments are recomputed by the fused step:
+    with one launch over every range the recorded states, and so dJ/du0 and
+    dJ/da, are bitwise those of the per-range launches."""
+    from paper_2404_03399_amd.solver import Solver
+    ws = _batch(*BATCHES["upwind_both_forms"])
+    u0s = [stepper.initial_state(w) for w in ws]
+    n = 13
+    _say(f"one launch, recorded run and adjoint, {len(ws)} problems, steps={n}")
+    res = {}
+    for one in (True, False):
+        s = Solver(ws, kernel="fused", lane_elems=2, fused_steps=2, n_steps_record=n, ckpt_every=4,
+                   one_launch=one, pe_split=False if one else None)
+        u = s.pack(u0s)
+        s.run(u, n, graph=True, record=True)
+        cot = s.pack([np.cos(x) for x in s.unpack(u)])
+        g, ga = s.adjoint(cot)
+        torch_cuda.cuda.synchronize()
+        res[one] = (s.unpack(u), s.unpack(g), list(ga))
+        s.close()
+    for i, w in enumerate(ws):
+        assert np.array_equal(res[True][0][i], res[False][0][i]), w.name
+        assert np.array_equal(res[True][1][i], res[False][1][i]), w.name
+    assert res[True][2] == res[False][2]
