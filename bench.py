@@ -9,8 +9,8 @@ time step of the whole hot path (all four stages, interior and PE faces,
 delay draws, ring traffic); the fused step kernel is replayed from a
 hipGraph.  Metric: DOF-stage updates per second (N_E (p+1) S steps / s).
 
-Prints ONE JSON line.  --gpus above 1 is rejected: this build runs on a
-single GPU.
+Prints ONE JSON line.  --gpus above 1 is rejected: the benchmark runs on
+a single GPU.
 """
 from __future__ import annotations
 
@@ -622,7 +622,7 @@ def main():
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
 
     import torch

@@ -64,7 +64,7 @@ enum adg_status {
   ADG_E_HIP = -4,          /* a HIP runtime call failed                         */
   ADG_E_STATE = -5,        /* call sequence invalid (e.g. adjoint w/o record)   */
   ADG_E_NONFINITE = -6,    /* ADG_RUN_CHECK_FINITE found a NaN/Inf              */
-  ADG_E_UNSUPPORTED = -7   /* valid request not implemented by this build       */
+  ADG_E_UNSUPPORTED = -7   /* valid request the library does not implement     */
 };
 
 /* VISCOUS_BURGERS: the fused kernel runs one element per lane (lane_elems
@@ -166,7 +166,7 @@ int adg_abi_version(void);
 /* Thread-local description of the last failure in this thread ("" if none). */
 const char* adg_last_error(void);
 
-/* Identity of this build: a hash of the library's source files (kernels,
+/* Identity of the library binary: a hash of its source files (kernels,
  * host code and this header), fixed when the library is compiled, so that a
  * caller can refuse a library built from other sources.  Static string. */
 const char* adg_build_id(void);

@@ -10,7 +10,7 @@ Test infrastructure only (see oracle/__init__.py).
   Omega = i ln(lambda) / (sigma (N_p + 1)).
 * Asynchronous ADG(1)-RK2 with one-level delay: the block-companion matrix
   built from the coefficient matrices of Sec. 4.2.2, transcribed as printed
-  (parity unpinned beyond the qualitative verdict at sigma = 0.333).
+  (parity unpinned beyond the paper's qualitative statement at sigma = 0.333).
 """
 from __future__ import annotations
 

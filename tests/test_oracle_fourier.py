@@ -55,7 +55,7 @@ def test_stepper_matrix_spectrum_equals_symbol(p, rk, flux):
     assert d.max() < 1e-10
 
 
-def test_paper_async_companion_verdict():
+def test_paper_async_companion_statement():
     # Sec. 4.2.2: ADG(1)-RK2-L2 is unstable at sigma = 0.333; decreasing sigma
     # decreases the growth (the paper calls 0.1 and 0.05 stable; the printed
     # matrices give growth below 1.5e-4 there).
