@@ -873,6 +873,11 @@ int adg_init(adg_ctx** out, const adg_problem* probs, int32_t n_probs, const adg
     adj_list(adj_tile_elems(c->rk, probs[0].equation == ADG_EQ_BURGERS), c->work_a, c->group_a, c->grid_a);
   if (c->L.work_a2 >= 0)
     adj_list(adj_tile_elems2(c->rk, adj_lane_elems(c->lane_elems)), c->work_a2, c->group_a2, c->grid_a2);
+  if ((c->L.work_a >= 0 && (int64_t)c->work_a.size() != c->L.n_work_a) ||
+      (c->L.work_a2 >= 0 && (int64_t)c->work_a2.size() != c->L.n_work_a2)) {
+    delete c;
+    return fail(ADG_E_INVALID, "internal: adjoint work list does not match the workspace layout");
+  }
 
   auto up = [&](int64_t off, const void* src, int64_t bytes) -> int {
     ADG_HIP(hipMemcpyAsync(c->ws + off, src, bytes, hipMemcpyHostToDevice, c->stream));
