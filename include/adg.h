@@ -67,9 +67,9 @@ enum adg_status {
   ADG_E_UNSUPPORTED = -7   /* valid request the library does not implement     */
 };
 
-/* VISCOUS_BURGERS: the fused kernel runs one element per lane (lane_elems
- * above 1 returns ADG_E_UNSUPPORTED) and one or two steps per launch; the
- * per-stage kernels run it too; adjoint recording returns ADG_E_UNSUPPORTED. */
+/* VISCOUS_BURGERS: the fused kernel (local DG form, Sec. 7) runs one, two or
+ * four elements per lane and one or two steps per launch; the per-stage
+ * kernels run it too; adjoint recording returns ADG_E_UNSUPPORTED. */
 enum adg_equation { ADG_EQ_ADVECTION = 0, ADG_EQ_BURGERS = 1, ADG_EQ_VISCOUS_BURGERS = 2 };
 enum adg_scheme { ADG_SCHEME_DG = 0, ADG_SCHEME_ADG = 1, ADG_SCHEME_ADG_AT = 2 };
 /* upwind / central: f^ = a (B+ u- + B- u+) (Sec. 2);  llf: local Lax-Friedrichs
@@ -127,8 +127,7 @@ typedef struct adg_options {
                                   straight into its slot, and the adjoint recomputes nothing) */
   int32_t kernel;              /* adg_kernel; AUTO -> FUSED */
   int32_t lane_elems;          /* fused kernel: consecutive elements per lane, 1, 2 or 4 (<= every
-                                  asynchronous problem's pe_size); 0 -> 2, or 1 for viscous Burgers or
-                                  a PE size of 1 */
+                                  asynchronous problem's pe_size); 0 -> 2, or 1 for a PE size of 1 */
   uint32_t flags;              /* ADG_OPT_* bits, 0 = defaults */
   uint32_t fused_steps;        /* fused kernel: time steps per launch, 1 or 2 (halo of 2S elements per side,
                                   half the state traffic per step); 0 -> 2.  Every (lane_elems,

@@ -76,8 +76,6 @@ def split_possible(workloads, k: int) -> bool:
 def configs(workloads) -> List[Tuple[int, int, Optional[bool]]]:
     """Candidate (R, K, split): split None where the PE-face split does not
     apply (the library then has nothing to choose)."""
-    if workloads[0].equation == "viscous_burgers":  # the local DG kernel: one element per lane
-        return [(1, k, None) for k in STEPS_PER_LAUNCH]
     out = []
     for r in admissible(workloads):
         for k in STEPS_PER_LAUNCH:

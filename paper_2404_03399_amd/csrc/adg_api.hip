@@ -259,7 +259,7 @@ int lane_elems_of(const adg_problem* probs, int32_t n, const adg_options* opt) {
   for (int32_t i = 0; i < n; ++i)
     if (async_of(probs[i])) min_pes = std::min(min_pes, probs[i].pe_size);
   const int req = opt ? opt->lane_elems : 0;
-  if (req == 0) return (probs[0].equation == ADG_EQ_VISCOUS_BURGERS || min_pes < 2) ? 1 : 2;
+  if (req == 0) return min_pes < 2 ? 1 : 2;
   if (req != 1 && req != 2 && req != 4) return 0;
   return req <= min_pes ? req : 0;
 }
@@ -684,8 +684,6 @@ int adg_workspace_size(const adg_problem* probs, int32_t n_probs, const adg_opti
       return fail(ADG_E_INVALID, "ADG_OPT_ONE_LAUNCH needs the fused kernel, two elements per lane and no PE-face split");
     if (is_ldg(probs)) return fail(ADG_E_UNSUPPORTED, "ADG_OPT_ONE_LAUNCH: the local DG kernel launches per range");
   }
-  if (is_ldg(probs) && k == ADG_KERNEL_FUSED && opt && opt->lane_elems > 1)
-    return fail(ADG_E_UNSUPPORTED, "the fused local DG kernel runs one element per lane");
   if (is_ldg(probs) && n_steps_record > 0)
     return fail(ADG_E_UNSUPPORTED, "no adjoint for viscous Burgers (local DG)");
   *bytes_out = make_layout(probs, n_probs, opt, n_steps_record).total;

@@ -446,22 +446,27 @@ __global__ __launch_bounds__(kBlock) void k_fused_all(const DevProblem* __restri
 }
 
 // Viscous Burgers in local DG form (Sec. 7): K in {1, 2} time steps per
-// launch, one element per lane, halo K S lanes per side.  Per stage: u-hat at
-// a face is the trace of the element on its left (alternating flux); q = Kr
-// u-hat_right - Kl u-hat_left - Kd u; the total flux at a face is G =
-// LLF(u-, u+) - nu q+ with q+ from the element on its right; the element
-// update is Kl G_left - Kr G_right + Kd (u^2/2 - nu q).  u-hat_left comes from
-// the left lane by a lane shift and u-hat_right is the lane's own trace, so q
-// needs no data from the right; G_right comes from the right lane.  Each
-// stage then depends on one lane to either side, as the inviscid update does.
-// At a PE face the element right of it writes the raw level-m u-hat and G to
-// their rings; every lane holding the face as its left face takes the AT
-// combinations of past levels of both, and every lane holding it as its right
-// face the u-hat combination.  The levels before n were written by earlier
-// launches, so these sums are formed at the start of the launch; for the
-// second step a delay of 1 also needs level n, which each lane adds from its
-// own raw values (the left-face u-hat and G it computes, and for the right
-// face its own trace, which is that face's u-hat).
+// launch, R in {1, 2, 4} consecutive elements per lane, halo of K S elements
+// per side.  Per stage: u-hat at a face is the trace of the element on its
+// left (alternating flux); q = Kr u-hat_right - Kl u-hat_left - Kd u; the
+// total flux at a face is G = LLF(u-, u+) - nu q+ with q+ from the element on
+// its right; the element update is Kl G_left - Kr G_right + Kd (u^2/2 - nu q).
+// u-hat_left comes from the element on the left (the left lane's last element
+// by a lane shift) and u-hat_right is the element's own trace, so q needs no
+// data from the right; G_right comes from the element on the right.  Each
+// stage then depends on one element to either side, as the inviscid update
+// does, and every element takes the same operations whatever R.  At a PE
+// face the element right of it writes the raw level-m u-hat and G to their
+// rings; the element holding the face as its left face takes the AT
+// combinations of past levels of both, and the element holding it as its
+// right face the u-hat combination.  The levels before n were written by
+// earlier launches, so these sums are formed at the start of the launch; for
+// the second step a delay of 1 also needs level n, which each lane adds from
+// its own raw values (the left-face u-hat and G it computes, and for the
+// right face its own trace, which is that face's u-hat).  A PE size of at
+// least R gives a lane at most one PE face as some element's left face and
+// at most one as some element's right face, so the per-lane LDS slots below
+// hold each kind once.
 template <int S, int K>
 struct LdgSmem {
   double atu[K][kWavesPerBlock][S][kWave];   // left face: u-hat
@@ -471,40 +476,77 @@ struct LdgSmem {
   uint8_t kr[K][kWavesPerBlock][S][kWave];   // delays of the right face
 };
 
-template <int NP, int RK, int K>
+template <int NP, int RK, int K, int R>
 __device__ __forceinline__ void wave_tile_ldg(const DevProblem& P, const WorkItem wi, double* __restrict__ ring,
                                               int64_t n, const double* __restrict__ uin, double* __restrict__ uout,
                                               LdgSmem<rk_stages(RK), K>& sm, int wv, int lane) {
 #pragma clang fp contract(off)  // explicit FMAs only
   constexpr int S = rk_stages(RK);
-  constexpr int HL = fused_halo(RK, 1, K);
-  constexpr int T = fused_tile(RK, 1, K);
+  constexpr int HL = fused_halo(RK, R, K);
+  constexpr int T = fused_tile(RK, R, K);
   const int N = (int)P.n_elem;
   const int e0 = wi.tile * T;
   const int teff = (N - e0) < T ? (N - e0) : T;
-  const int x = e0 - HL + lane;
-  const int e = N < kWave ? wrap_elem(x, N) : wrap_once(x, N);
-  const bool owned = lane >= HL && lane < kWave - HL && (x - e0) < teff;
+  const int xb = e0 - R * HL;  // element position of lane 0, element 0 (a multiple of R)
+  const bool lane_owned = lane >= HL && lane < kWave - HL;
+  const bool tiny = N < kWave * R;  // the wave's extent may wrap more than once
+  int e[R];
+  bool owned[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int x = xb + R * lane + r;
+    e[r] = tiny ? wrap_elem(x, N) : wrap_once(x, N);
+    owned[r] = lane_owned && (x - e0) < teff;
+  }
+  // with N a multiple of R a lane's elements never straddle the periodic
+  // wrap: its planes move as 16-byte pieces through a buffer resource
+  const bool buffered = R > 1 && (N % R) == 0 && (int64_t)P.np * P.ld < (int64_t)1 << 28;
+  const int voff = e[0] * 8;
   const int64_t ld = P.ld;
   const double* __restrict__ u = uin + P.u_off;
-  double u0[NP];
+  double u0[R][NP];
+  if (buffered) {
+    const __amdgpu_buffer_rsrc_t rs = plane_rsrc(u);
 #pragma unroll
-  for (int j = 0; j < NP; ++j) u0[j] = u[j * ld + e];
+    for (int j = 0; j < NP; ++j)
+#pragma unroll
+      for (int r = 0; r < R; r += 2) {
+        const double2 v = __builtin_bit_cast(double2,
+                                             __builtin_amdgcn_raw_buffer_load_b128(rs, voff + 8 * r, (int)(8 * j * ld), 0));
+        u0[r][j] = v.x;
+        u0[r + 1 < R ? r + 1 : r][j] = v.y;  // R >= 2 here
+      }
+  } else {
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int j = 0; j < NP; ++j) u0[r][j] = u[j * ld + e[r]];
+  }
 
-  bool pe = false;    // the left face of this lane's element is a PE face
-  bool pe_r = false;  // the right face is a PE face
-  uint32_t b = 0, br = 0;
+  bool pe[R];    // the left face of element r is a PE face
+  bool per[R];   // the right face of element r is a PE face
+  bool pe_any = false, per_any = false;
+  uint32_t b = 0, br = 0;  // the lane's PE face of each kind
   int depth = 1, slot_n = 0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) pe[r] = per[r] = false;
   if (P.async_faces) {
     depth = P.depth;
     const uint32_t n32 = (uint32_t)n;  // step indices stay below 2^31
     slot_n = (int)(n32 - fast_div(n32, P.depth_div) * (uint32_t)depth);
     const uint32_t pes = P.pe_div.d;
-    b = fast_div((uint32_t)e, P.pe_div);
-    pe = (uint32_t)e == b * pes;
-    const uint32_t e1 = (e + 1 == N) ? 0u : (uint32_t)(e + 1);
-    br = fast_div(e1, P.pe_div);
-    pe_r = e1 == br * pes;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const uint32_t bl = fast_div((uint32_t)e[r], P.pe_div);
+      pe[r] = (uint32_t)e[r] == bl * pes;
+      if (pe[r]) b = bl;
+      const uint32_t e1 = (e[r] + 1 == N) ? 0u : (uint32_t)(e[r] + 1);
+      const uint32_t b1 = fast_div(e1, P.pe_div);
+      per[r] = e1 == b1 * pes;
+      if (per[r]) br = b1;
+      pe_any = pe_any || pe[r];
+      per_any = per_any || per[r];
+    }
   }
   // The delays and the AT sums over the levels before n, one job lane per
   // (PE lane, step, stage, value): the left-face u-hat and G of each lane with
@@ -512,15 +554,15 @@ __device__ __forceinline__ void wave_tile_ldg(const DevProblem& P, const WorkIte
   // Each job draws its delay and sums its past levels; the target lane reads
   // both from LDS.
   constexpr int KS = K * S;
-  const uint64_t m_l = __ballot(pe), m_r = __ballot(pe_r);
+  const uint64_t m_l = __ballot(pe_any), m_r = __ballot(per_any);
   const int n_l = 2 * KS * __builtin_popcountll(m_l);
   const int n_jobs = n_l + KS * __builtin_popcountll(m_r);
   for (int g0 = 0; g0 < n_jobs; g0 += kWave) {  // uniform
     const int g = g0 + lane;
     const bool left = g < n_l;
     const int h = left ? g : g - n_l;
-    const int per = left ? 2 * KS : KS;
-    const int i = h / per, r = h - i * per;
+    const int per_face = left ? 2 * KS : KS;
+    const int i = h / per_face, r = h - i * per_face;
     const int v = left ? r / KS : 2;  // 0: u-hat, 1: G (left face); 2: u-hat (right face)
     const int rr = r - (left ? v * KS : 0);
     const int kk = rr / S, s = rr - kk * S;
@@ -544,9 +586,11 @@ __device__ __forceinline__ void wave_tile_ldg(const DevProblem& P, const WorkIte
     }
   }
 
-  double y[NP], ks[NP], k[NP], q[NP];
+  double y[R][NP], ks[R][NP], k[NP], q[R][NP];
 #pragma unroll
-  for (int j = 0; j < NP; ++j) y[j] = u0[j];
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int j = 0; j < NP; ++j) y[r][j] = u0[r][j];
   const double nu = P.nu;
   const double dt = P.dt;
   int slot_m = slot_n;
@@ -555,65 +599,98 @@ __device__ __forceinline__ void wave_tile_ldg(const DevProblem& P, const WorkIte
     if (kk > 0) {
       slot_m = slot_m + 1 == depth ? 0 : slot_m + 1;
 #pragma unroll
-      for (int j = 0; j < NP; ++j) u0[j] = y[j];
+      for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int j = 0; j < NP; ++j) u0[r][j] = y[r][j];
     }
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       const int64_t rs = ((int64_t)b * S + s) * depth + slot_m;
-      const double um = lane_from_left(y[NP - 1]);  // u- at the left face, and its u-hat
-      double hl = um;
-      if (pe) {
-        if (owned) ring[P.ring2_off + rs] = um;
-        if constexpr (K == 2) {  // level n completes step n+1's u-hat sum when its delay is 1
-          if (kk == 0 && sm.kl[1][wv][s][lane] == 1) sm.atu[1][wv][s][lane] = fma(P.atc[1][0], um, sm.atu[1][wv][s][lane]);
+      double um[R], G[R];
+      const double um0 = lane_from_left(y[R - 1][NP - 1]);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        um[r] = r == 0 ? um0 : y[r - 1][NP - 1];  // u- at the left face, and its u-hat
+        double hl = um[r];
+        if (pe[r]) {
+          if (owned[r]) ring[P.ring2_off + rs] = um[r];
+          if constexpr (K == 2) {  // level n completes step n+1's u-hat sum when its delay is 1
+            if (kk == 0 && sm.kl[1][wv][s][lane] == 1)
+              sm.atu[1][wv][s][lane] = fma(P.atc[1][0], um[r], sm.atu[1][wv][s][lane]);
+          }
+          if (sm.kl[kk][wv][s][lane] != 0) hl = sm.atu[kk][wv][s][lane];
         }
-        if (sm.kl[kk][wv][s][lane] != 0) hl = sm.atu[kk][wv][s][lane];
-      }
-      double hr = y[NP - 1];  // u-hat at the right face: this element's own trace
-      if (pe_r) {
-        if constexpr (K == 2) {
-          if (kk == 0 && sm.kr[1][wv][s][lane] == 1)
-            sm.atur[1][wv][s][lane] = fma(P.atc[1][0], hr, sm.atur[1][wv][s][lane]);
+        double hr = y[r][NP - 1];  // u-hat at the right face: this element's own trace
+        if (per[r]) {
+          if constexpr (K == 2) {
+            if (kk == 0 && sm.kr[1][wv][s][lane] == 1)
+              sm.atur[1][wv][s][lane] = fma(P.atc[1][0], hr, sm.atur[1][wv][s][lane]);
+          }
+          if (sm.kr[kk][wv][s][lane] != 0) hr = sm.atur[kk][wv][s][lane];
         }
-        if (sm.kr[kk][wv][s][lane] != 0) hr = sm.atur[kk][wv][s][lane];
-      }
 #pragma unroll
-      for (int i = 0; i < NP; ++i) {
-        double v = fma(-P.Kl[i], hl, P.Kr[i] * hr);
+        for (int i = 0; i < NP; ++i) {
+          double v = fma(-P.Kl[i], hl, P.Kr[i] * hr);
 #pragma unroll
-        for (int j = 0; j < NP; ++j) v = fma(-P.Kd[i * kMaxNp + j], y[j], v);
-        q[i] = v;
-      }
-      double G = fma(-nu, q[0], Physics<PHYS_BURGERS_LLF>::fhat(um, y[0], 1.0));
-      if (pe) {
-        if (owned) ring[P.ring_off + rs] = G;
-        if constexpr (K == 2) {
-          if (kk == 0 && sm.kl[1][wv][s][lane] == 1) sm.atg[1][wv][s][lane] = fma(P.atc[1][0], G, sm.atg[1][wv][s][lane]);
+          for (int j = 0; j < NP; ++j) v = fma(-P.Kd[i * kMaxNp + j], y[r][j], v);
+          q[r][i] = v;
         }
-        if (sm.kl[kk][wv][s][lane] != 0) G = sm.atg[kk][wv][s][lane];
       }
-      const double Gr = lane_from_right(G);
-      double g[NP];
 #pragma unroll
-      for (int j = 0; j < NP; ++j) g[j] = fma(0.5 * y[j], y[j], -nu * q[j]);
-#pragma unroll
-      for (int i = 0; i < NP; ++i) {
-        double v = fma(-P.Kr[i], Gr, P.Kl[i] * G);
-#pragma unroll
-        for (int j = 0; j < NP; ++j) v = fma(P.Kd[i * kMaxNp + j], g[j], v);
-        k[i] = v;
+      for (int r = 0; r < R; ++r) {
+        G[r] = fma(-nu, q[r][0], Physics<PHYS_BURGERS_LLF>::fhat(um[r], y[r][0], 1.0));
+        if (pe[r]) {
+          if (owned[r]) ring[P.ring_off + rs] = G[r];
+          if constexpr (K == 2) {
+            if (kk == 0 && sm.kl[1][wv][s][lane] == 1)
+              sm.atg[1][wv][s][lane] = fma(P.atc[1][0], G[r], sm.atg[1][wv][s][lane]);
+          }
+          if (sm.kl[kk][wv][s][lane] != 0) G[r] = sm.atg[kk][wv][s][lane];
+        }
       }
-      rk_update<NP, RK>(s, dt, u0, y, ks, k);
+      const double Gr_last = lane_from_right(G[0]);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const double Gr = r + 1 < R ? G[r + 1] : Gr_last;
+        double g[NP];
+#pragma unroll
+        for (int j = 0; j < NP; ++j) g[j] = fma(0.5 * y[r][j], y[r][j], -nu * q[r][j]);
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+          double v = fma(-P.Kr[i], Gr, P.Kl[i] * G[r]);
+#pragma unroll
+          for (int j = 0; j < NP; ++j) v = fma(P.Kd[i * kMaxNp + j], g[j], v);
+          k[i] = v;
+        }
+        rk_update<NP, RK>(s, dt, u0[r], y[r], ks[r], k);
+      }
     }
   }
-  if (owned) {
-    double* __restrict__ uo = uout + P.u_off;
+  bool all_owned = true;
 #pragma unroll
-    for (int j = 0; j < NP; ++j) uo[j * ld + e] = y[j];
+  for (int r = 0; r < R; ++r) all_owned = all_owned && owned[r];
+  double* __restrict__ uo = uout + P.u_off;
+  if (buffered && all_owned) {
+    const __amdgpu_buffer_rsrc_t rs = plane_rsrc(uo);
+#pragma unroll
+    for (int j = 0; j < NP; ++j)
+#pragma unroll
+      for (int r = 0; r < R; r += 2) {
+        double2 v;
+        v.x = y[r][j];
+        v.y = y[r + 1 < R ? r + 1 : r][j];
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(BufWord4, v), rs, voff + 8 * r, (int)(8 * j * ld), 0);
+      }
+  } else {
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (owned[r])
+#pragma unroll
+        for (int j = 0; j < NP; ++j) uo[j * ld + e[r]] = y[r][j];
   }
 }
 
-template <int NP, int RK, int K>
+template <int NP, int RK, int K, int R>
 __global__ __launch_bounds__(kBlock) void k_fused_ldg(const DevProblem* __restrict__ probs,
                                                       const WorkItem* __restrict__ work,
                                                       const int64_t* __restrict__ ctr, double* __restrict__ ring,
@@ -627,17 +704,26 @@ __global__ __launch_bounds__(kBlock) void k_fused_ldg(const DevProblem* __restri
   if (w >= w_end) return;  // whole wave
   const int64_t n = ctr[0] + step_offset;
   const WorkItem wi = single_prob >= 0 ? WorkItem{single_prob, w - w_begin} : work[w];
-  wave_tile_ldg<NP, RK, K>(probs[wi.prob], wi, ring, n, uin, uout, sm, wv, lane);
+  wave_tile_ldg<NP, RK, K, R>(probs[wi.prob], wi, ring, n, uin, uout, sm, wv, lane);
+}
+
+template <int NP, int RK, int R>
+static void fused_ldg_go_r(const StepArgs& a, int gi, const double* uin, double* uout, int32_t off, hipStream_t st) {
+  if (a.steps == 2)
+    hipLaunchKernelGGL((k_fused_ldg<NP, RK, 2, R>), dim3(a.grid[gi]), dim3(kBlock), 0, st, a.probs, a.work, a.ctr,
+                       a.ring, a.group[gi], a.group[gi + 1], uin, uout, off, a.single[gi]);
+  else
+    hipLaunchKernelGGL((k_fused_ldg<NP, RK, 1, R>), dim3(a.grid[gi]), dim3(kBlock), 0, st, a.probs, a.work, a.ctr,
+                       a.ring, a.group[gi], a.group[gi + 1], uin, uout, off, a.single[gi]);
 }
 
 template <int NP, int RK>
 static void fused_ldg_go(const StepArgs& a, int gi, const double* uin, double* uout, int32_t off, hipStream_t st) {
-  if (a.steps == 2)
-    hipLaunchKernelGGL((k_fused_ldg<NP, RK, 2>), dim3(a.grid[gi]), dim3(kBlock), 0, st, a.probs, a.work, a.ctr,
-                       a.ring, a.group[gi], a.group[gi + 1], uin, uout, off, a.single[gi]);
-  else
-    hipLaunchKernelGGL((k_fused_ldg<NP, RK, 1>), dim3(a.grid[gi]), dim3(kBlock), 0, st, a.probs, a.work, a.ctr,
-                       a.ring, a.group[gi], a.group[gi + 1], uin, uout, off, a.single[gi]);
+  switch (a.lane_elems) {
+    case 2: fused_ldg_go_r<NP, RK, 2>(a, gi, uin, uout, off, st); break;
+    case 4: fused_ldg_go_r<NP, RK, 4>(a, gi, uin, uout, off, st); break;
+    default: fused_ldg_go_r<NP, RK, 1>(a, gi, uin, uout, off, st); break;
+  }
 }
 
 template <int RK>

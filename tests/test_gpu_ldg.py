@@ -147,6 +147,38 @@ def test_ldg_two_steps_per_launch_bitwise(torch_cuda, p, rk, scheme, q, per_stag
     assert stats.rel_l2(out[2, 19], stepper.Stepper(w).run(u0, 19)) <= 1e-12
 
 
+@pytest.mark.parametrize("p,rk,scheme,q,per_stage,ne,pe", [
+    (2, "heun", "adg_at", 2, False, 600, 20), (1, "rk4", "adg_at", 0, True, 130, 13),
+    (3, "ssprk3", "adg", 0, True, 200, 2), (2, "lsrk3", "adg_at", 3, False, 800, 8),
+    (4, "heun", "dg", 0, False, 64, 16), (2, "lsrk4", "adg_at", 2, True, 150, 15),
+    (3, "heun", "adg_at", 3, False, 36, 4)])
+def test_ldg_lane_elems_bitwise(torch_cuda, p, rk, scheme, q, per_stage, ne, pe):
+    """Two and four elements per lane (tiles of R (64 - 2H) elements, halo
+    H = K S / R lanes; a PE face every other element; odd meshes whose lanes
+    straddle the periodic wrap; a mesh shorter than one wave's extent) give
+    bitwise the one-element results at one and two steps per launch, and
+    match the oracle."""
+    from paper_2404_03399_amd.solver import Solver
+    w = _w(p, rk, scheme, q, per_stage, ne=ne, pe=pe, seed=ne + 7 * p)
+    u0 = stepper.initial_state(w)
+    n = 21
+    _say(f"viscous Burgers LDG lane counts p={p} {rk} {scheme} q={q} N={ne} pe={pe} steps={n}")
+    out = {}
+    for R in (1, 2, 4):
+        if scheme != "dg" and R > pe:
+            continue
+        for K in (1, 2):
+            s = Solver(w, kernel="fused", lane_elems=R, fused_steps=K)
+            u = s.pack(u0)
+            s.run(u, n, graph=(R + K) % 2 == 0)
+            torch_cuda.cuda.synchronize()
+            out[R, K] = s.unpack(u)[0]
+            s.close()
+    for key, v in out.items():
+        assert np.array_equal(v, out[1, 1]), key
+    assert stats.rel_l2(out[1, 1], stepper.Stepper(w).run(u0, n)) <= 1e-12
+
+
 @pytest.mark.parametrize("scheme,q,probs", [("adg", 0, ("0", "0", "1")), ("adg_at", 1, ("0", "0", "0", "1")),
                                             ("adg_at", 2, ("0", "0", "1")), ("adg_at", 3, ("0", "1"))])
 def test_two_step_launch_reads_no_level_written_in_it(torch_cuda, scheme, q, probs):

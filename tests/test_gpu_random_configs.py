@@ -87,7 +87,7 @@ def draw(case: int, large: bool = False):
         dt = min(0.002 * dx * dx / nu, 0.01 * dx / 6.0)
         ic = W.PAPER_MULTISINE
     async_faces = scheme != "dg" and ne // pe > 1
-    lanes = [1] if eq == "viscous_burgers" else [r for r in (1, 2, 4) if not async_faces or r <= pe]
+    lanes = [r for r in (1, 2, 4) if not async_faces or r <= pe]
     R = int(rng.choice(lanes))
     K = int(rng.choice([1, 2]))
     w = W.Workload(name=f"rand{case}", equation=eq, scheme=scheme, flux=flux, rk=rk, degree=p, n_elem=ne,
@@ -146,7 +146,7 @@ def draw_batch(case: int):
                              speed=w.speed if first.equation == "advection" else 1.0,
                              viscosity=first.viscosity, dt=dt, ic=first.ic))
     async_pes = [w.pe_size for w in ws if w.scheme != "dg" and w.n_elem // w.pe_size > 1]
-    lanes = [1] if first.equation == "viscous_burgers" else [r for r in (1, 2, 4) if r <= min(async_pes or [4])]
+    lanes = [r for r in (1, 2, 4) if r <= min(async_pes or [4])]
     R = int(rng.choice(lanes))
     return ws, n, R, K, graph
 

@@ -111,10 +111,13 @@ def test_viscous_burgers_options(L):
     opt.kernel = adg.KERNEL["fused"]
     opt.fused_steps = 1
     assert adg.adg_workspace_size([p], opt) > 0                         # one or two steps per launch
-    opt.lane_elems = 2                                                  # one element per lane only
+    for r in (2, 4):                                                    # several elements per lane
+        opt.lane_elems = r
+        assert adg.adg_workspace_size([p], opt) > 0
+    opt.lane_elems = 32                                                 # more than the PE size
     with pytest.raises(adg.AdgError) as ei:
         adg.adg_workspace_size([p], opt)
-    assert ei.value.code == adg.ADG_E_UNSUPPORTED
+    assert ei.value.code == adg.ADG_E_INVALID
     with pytest.raises(adg.AdgError) as ei:
         adg.adg_workspace_size([p], adg.adg_options(), 10)             # no adjoint for local DG
     assert ei.value.code == adg.ADG_E_UNSUPPORTED
@@ -238,7 +241,7 @@ def test_random_descriptors_are_validated(L):
         p = solver.to_problem(w)
         opt = adg.adg_options()
         opt.kernel = int(rng.choice([0, 1, 2]))
-        opt.lane_elems = int(rng.choice([0, 1, 2, 4])) if w.equation != "viscous_burgers" else 0
+        opt.lane_elems = int(rng.choice([0, 1, 2, 4]))
         if w.scheme != "dg" and w.n_elem // w.pe_size > 1:
             opt.lane_elems = min(opt.lane_elems, 1 if w.pe_size < 2 else (2 if w.pe_size < 4 else opt.lane_elems))
         opt.fused_steps = int(rng.choice([0, 1, 2]))
