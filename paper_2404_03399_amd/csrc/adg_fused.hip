@@ -60,7 +60,7 @@ __device__ __forceinline__ void wave_tile(const DevProblem& P, const WorkItem wi
   constexpr int T = fused_tile(RK, R, K);
   const int N = (int)P.n_elem;
   // With N a multiple of R a lane's R elements never straddle the periodic
-  // wrap, so one R*8-byte access per plane serves them all.
+  // wrap, so its planes can move as 16-byte pieces.
   const bool grouped = R > 1 && (N % R) == 0;
   const int64_t ld = P.ld;
   const double* __restrict__ u = uin + P.u_off;
@@ -106,7 +106,7 @@ __device__ __forceinline__ void wave_tile(const DevProblem& P, const WorkItem wi
   // pieces through a buffer resource: the lane's byte offset sits in one
   // VGPR and each plane's offset in an SGPR, so no 64-bit address is formed
   // per plane (the problem's planes must span less than 2 GiB).
-  const bool buffered = R > 1 && grouped && (int64_t)P.np * ld < (int64_t)1 << 28;
+  const bool buffered = grouped && (int64_t)P.np * ld < (int64_t)1 << 28;
   const int voff = e[0] * 8;
   if (buffered) {
     const __amdgpu_buffer_rsrc_t rs = plane_rsrc(u);
