@@ -153,6 +153,12 @@ __global__ __launch_bounds__(kBlock) void k_adj_stage(const DevProblem* __restri
 // same operations in the same order whatever R (a neighbour's face term comes
 // from the lane's own registers or by a lane shift), and explicit FMAs with
 // contraction off give every kernel that reverses a step the same roundings.
+//
+// PHYS_ADV_UPWIND_POS (upwind, a > 0) transposes the folded forward operator:
+// the interior flux a u_p of an element's right face sits in Kdu, so an
+// element's sensitivity is Kdu^T lambda_K plus a (l_l . lambda_K of the right
+// neighbour) at its last node, and the right lift (l_r . lambda_K) is formed
+// only in waves that hold a PE face, where the applied flux replaces a u_p.
 template <int NP, int RK, int PHYS, bool FWD, int R, class KdF, class AdjF, class LfF>
 __device__ __forceinline__ double adj_reverse(const DevProblem& P, const double (&lamp)[R][NP], double (&lu)[R][NP],
                                               const double (&keep)[rk_stages(RK)][NP], const bool (&pe)[R],
@@ -160,10 +166,14 @@ __device__ __forceinline__ double adj_reverse(const DevProblem& P, const double 
 #pragma clang fp contract(off)
   static_assert(R == 1 || (!FWD && PHYS != PHYS_BURGERS_LLF), "several elements per lane: constant Jacobian only");
   constexpr int S = rk_stages(RK);
+  constexpr bool POS = PHYS == PHYS_ADV_UPWIND_POS;
   const double a = P.speed, dt = P.dt;
   bool any_pe = false;
 #pragma unroll
   for (int r = 0; r < R; ++r) any_pe = any_pe || pe[r];
+  // POS: the right lifts are needed only where some lane holds a PE face
+  const bool with_cr = !POS || __ballot(any_pe) != 0;  // uniform
+  // Q[r][i] = dt sum_{j>i} a_ji mu_j (dt folded into the stage weights)
   double Q[R][S][NP];
 #pragma unroll
   for (int r = 0; r < R; ++r)
@@ -183,37 +193,56 @@ __device__ __forceinline__ double adj_reverse(const DevProblem& P, const double 
 #pragma unroll
     for (int r = 0; r < R; ++r) {
 #pragma unroll
-      for (int i = 0; i < NP; ++i) lk[r][i] = s < S - 1 ? fma(bs, lamp[r][i], dt * Q[r][s][i]) : bs * lamp[r][i];
+      for (int i = 0; i < NP; ++i) lk[r][i] = s < S - 1 ? fma(bs, lamp[r][i], Q[r][s][i]) : bs * lamp[r][i];
       cl[r] = 0.0;
       cr[r] = 0.0;
 #pragma unroll
-      for (int i = 0; i < NP; ++i) {
-        cl[r] = fma(P.Kl[i], lk[r][i], cl[r]);
-        cr[r] = fma(P.Kr[i], lk[r][i], cr[r]);
-      }
-    }
-    // sensitivity of the flux applied at each element's left face (both
-    // neighbours' lifts)
-    double raw[R];
-    raw[0] = cl[0] - lane_from_left(cr[R - 1]);
+      for (int i = 0; i < NP; ++i) cl[r] = fma(P.Kl[i], lk[r][i], cl[r]);
+      if (with_cr)
 #pragma unroll
-    for (int r = 1; r < R; ++r) raw[r] = cl[r] - cr[r - 1];
-    double dm, dp;
+        for (int i = 0; i < NP; ++i) cr[r] = fma(P.Kr[i], lk[r][i], cr[r]);
+    }
+    // raw[r]: sensitivity of the flux applied at element r's left face (both
+    // neighbours' lifts); POS: g[r], what that face gives its left element's
+    // last node, over a
+    double crl[R], raw[R], g[R];  // crl[r]: the right lift of element r's left neighbour
+    if (with_cr) {
+      crl[0] = lane_from_left(cr[R - 1]);
+#pragma unroll
+      for (int r = 1; r < R; ++r) crl[r] = cr[r - 1];
+#pragma unroll
+      for (int r = 0; r < R; ++r) raw[r] = cl[r] - crl[r];
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) g[r] = cl[r];
+    double dm = 0.0, dp = 0.0;
     if constexpr (PHYS == PHYS_BURGERS_LLF)
       flux_partials<PHYS>(lane_from_left(keep[s][NP - 1]), keep[s][0], a, dm, dp);
-    else
+    else if constexpr (!POS)
       flux_partials<PHYS>(0.0, 0.0, a, dm, dp);
-    if (any_pe) {
+    if (any_pe) {  // with_cr holds here
       double lf = raw[0];
 #pragma unroll
       for (int r = 1; r < R; ++r) lf = pe[r] ? raw[r] : lf;
       const int kk = kd_of(s);
       const double rp = (kk == 0 ? lf : 0.0) + adjn_of(s);
       on_lf(s, lf);
+      if constexpr (POS) {
+        // the left element's right lift, which Kdu^T took off, comes back
+        // with the raw flux's sensitivity
 #pragma unroll
-      for (int r = 0; r < R; ++r) raw[r] = pe[r] ? rp : raw[r];
+        for (int r = 0; r < R; ++r) g[r] = pe[r] ? crl[r] + rp : g[r];
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) raw[r] = pe[r] ? rp : raw[r];
+      }
     }
-    const double rdm = lane_from_right(raw[0] * dm);  // the right face of element R-1 is the next lane's first
+    // the right face of element R-1 is the next lane's first
+    double rdm;
+    if constexpr (POS)
+      rdm = lane_from_right(g[0]);
+    else
+      rdm = lane_from_right(raw[0] * dm);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       double mu[NP];
@@ -221,22 +250,28 @@ __device__ __forceinline__ double adj_reverse(const DevProblem& P, const double 
       for (int j = 0; j < NP; ++j) {
         double v = 0.0;
 #pragma unroll
-        for (int i = 0; i < NP; ++i) v = fma(P.Kd[i * kMaxNp + j], lk[r][i], v);
+        for (int i = 0; i < NP; ++i) v = fma((POS ? P.Kdu : P.Kd)[i * kMaxNp + j], lk[r][i], v);
         if constexpr (PHYS == PHYS_BURGERS_LLF)
           mu[j] = (2.0 * keep[s][j]) * v;
         else
           mu[j] = v;
       }
-      mu[0] = fma(raw[r], dp, mu[0]);
-      mu[NP - 1] += r + 1 < R ? raw[r + 1] * dm : rdm;
+      if constexpr (POS) {
+        mu[NP - 1] = fma(a, r + 1 < R ? g[r + 1] : rdm, mu[NP - 1]);
+      } else {
+        mu[0] = fma(raw[r], dp, mu[0]);
+        mu[NP - 1] += r + 1 < R ? raw[r + 1] * dm : rdm;
+      }
 #pragma unroll
       for (int j = 0; j < NP; ++j) lu[r][j] += mu[j];
 #pragma unroll
       for (int i = 0; i < s; ++i) {
         const double c = bt_a<RK>(s, i);
-        if (c != 0.0)
+        if (c != 0.0) {
+          const double dc = dt * c;
 #pragma unroll
-          for (int j = 0; j < NP; ++j) Q[r][i][j] = fma(c, mu[j], Q[r][i][j]);
+          for (int j = 0; j < NP; ++j) Q[r][i][j] = fma(dc, mu[j], Q[r][i][j]);
+        }
       }
       if constexpr (FWD && PHYS != PHYS_BURGERS_LLF) {
         if (owned)
@@ -246,6 +281,20 @@ __device__ __forceinline__ double adj_reverse(const DevProblem& P, const double 
     }
   }
   return ca;
+}
+
+// adj_reverse in the a > 0 upwind form where the problem has one (a
+// wave-uniform choice), else in the general form of PHYS
+template <int NP, int RK, int PHYS, bool FWD, int R, class KdF, class AdjF, class LfF>
+__device__ __forceinline__ double adj_reverse_form(const DevProblem& P, const double (&lamp)[R][NP],
+                                                   double (&lu)[R][NP], const double (&keep)[rk_stages(RK)][NP],
+                                                   const bool (&pe)[R], bool owned, KdF kd_of, AdjF adjn_of,
+                                                   LfF on_lf) {
+  if constexpr (PHYS == PHYS_ADV_UPWIND) {
+    if (P.speed > 0.0)
+      return adj_reverse<NP, RK, PHYS_ADV_UPWIND_POS, FWD, R>(P, lamp, lu, keep, pe, owned, kd_of, adjn_of, on_lf);
+  }
+  return adj_reverse<NP, RK, PHYS, FWD, R>(P, lamp, lu, keep, pe, owned, kd_of, adjn_of, on_lf);
 }
 
 // Per-lane PE-face values of a reverse step (lane = the PE lane they belong
@@ -371,7 +420,7 @@ __device__ __forceinline__ void adj_tile(const DevProblem& P, const WorkItem wi,
   // reverse stages
   double lu[1][NP];
   const bool pe1[1] = {pe};
-  const double ca = adj_reverse<NP, RK, PHYS, FWD, 1>(
+  const double ca = adj_reverse_form<NP, RK, PHYS, FWD, 1>(
       P, lamp, lu, keep, pe1, owned, [&](int s) { return (int)sm.kd[wv][s][lane]; },
       [&](int s) { return sm.adjn[wv][s][lane]; }, [&](int s, double lf) { sm.adjn[wv][s][lane] = lf; });
 
@@ -524,14 +573,14 @@ __device__ __forceinline__ void adj_tile2(const DevProblem& P, const WorkItem wi
   const double keep[S][NP] = {};  // no forward stages: the Jacobian is constant
   double l1[R][NP], l0[R][NP];
   // step n + 1: a delay of 1 deposits c_0(1) lf at level n, which step n reads
-  adj_reverse<NP, RK, PHYS, false, R>(
+  adj_reverse_form<NP, RK, PHYS, false, R>(
       P, lamp, l1, keep, pe, false, [&](int s) { return (int)sm.kd[0][wv][s][lane]; },
       [&](int s) { return sm.adjn[0][wv][s][lane]; },
       [&](int s, double lf) {
         sm.adjn[0][wv][s][lane] = lf;
         if (sm.kd[0][wv][s][lane] == 1) sm.adjn[1][wv][s][lane] = fma(P.atc[1][0], lf, sm.adjn[1][wv][s][lane]);
       });
-  adj_reverse<NP, RK, PHYS, false, R>(
+  adj_reverse_form<NP, RK, PHYS, false, R>(
       P, l1, l0, keep, pe, false, [&](int s) { return (int)sm.kd[1][wv][s][lane]; },
       [&](int s) { return sm.adjn[1][wv][s][lane]; }, [&](int s, double lf) { sm.adjn[1][wv][s][lane] = lf; });
 
